@@ -1,0 +1,197 @@
+/*
+ * xy_levy.h -- C ABI of the MI355X (gfx950) library for equilibrium Monte
+ * Carlo of O(2)/XY spins on dilute Levy graphs.
+ *
+ * Paper: M. Ibanez Berganza and L. Leuzzi, "Critical behavior of the XY model
+ * in complex topologies", arXiv:1211.3991.
+ *
+ * The library covers the data-parallel hot path of the paper's method:
+ *   graph build (Sec. 2, Eq. Levyi) -> smallest-last colouring (App. B,
+ *   "Graph coloring") -> colour-sorted CSR -> sweeps of Metropolis plus
+ *   over-relaxation with parallel tempering (App. B, "Improved equilibrium
+ *   dynamics") -> measurement of E, |m|^2, |m|^4 and chi(k_min) (Sec. 3).
+ *
+ * Conventions for every entry point:
+ *   - Return value: XY_OK (0) or a negative xy_status.  On error the call has
+ *     no effect on device memory unless stated, and xy_last_error() returns a
+ *     message (thread-local, valid until the next call on the same thread).
+ *   - Device memory is CALLER-OWNED: the caller allocates the buffers whose
+ *     sizes xy_batch_sizes() reports and passes raw device pointers; the
+ *     library never allocates, frees or keeps device memory beyond a batch.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is enqueued asynchronously on it; a HIP launch error is
+ *     reported as XY_EHIP by the call that observes it.
+ *   - Host objects (xy_graph, xy_batch) are library-owned and freed with the
+ *     matching *_free call.  Calls on one handle are not thread-safe; calls on
+ *     different handles are.
+ *   - Site numbering: "lattice index" i = y*L + x of the L x L torus; the
+ *     device works in "colour-major index" (sites sorted by (colour, lattice
+ *     index)).  Host-visible state is always in lattice order.
+ */
+#ifndef XY_LEVY_H
+#define XY_LEVY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int xy_status;
+#define XY_OK         0
+#define XY_EINVAL    -1   /* bad argument */
+#define XY_ENOMEM    -2   /* host allocation failed */
+#define XY_EHIP      -3   /* HIP runtime error */
+#define XY_ESTATE    -4   /* call not valid in the handle's current state */
+#define XY_EUNSUP    -5   /* valid request this build does not support */
+#define XY_ECONVERGE -6   /* graph sampler hit its attempt cap */
+
+/* Spin representation. */
+#define XY_FP64  0   /* unit vector (x, y) in FP64; decisions bit-identical to the oracle */
+#define XY_FIX16 1   /* angle k * 2pi/65536 as uint16, FP32 local fields, FP64 accumulators */
+
+#define XY_NOBS 8    /* per (sample, temperature) record: E, |m|^2, |m|^4, F_x, F_y, m_x, m_y, 0 */
+
+typedef struct xy_graph xy_graph;
+typedef struct xy_batch xy_batch;
+
+/* ----------------------------------------------------------------------- */
+/* Graphs (host)                                                           */
+/* ----------------------------------------------------------------------- */
+
+/* Dilute Levy graph on the periodic L x L lattice (Sec. 2, Eq. Levyi):
+ * N = L*L sites and exactly N*z/2 links.  Each raw draw t (t = 0, 1, ...)
+ * takes Philox4x32-10 of counter (t lo, t hi, 0, 1<<24) under key `seed`:
+ * site i = floor(w0 * N / 2^32); a displacement d = (dx, dy) with
+ * dx, dy in {-L/2+1..L/2}, d != 0, listed dy-outer/dx-inner, drawn with
+ * weight (dx^2+dy^2)^(-rho/2) by inverting the sequential prefix sums with the
+ * 53-bit uniform ((w1 << 21) | (w2 >> 11)) * 2^-53; j = i + d on the torus.
+ * A draw that repeats an existing link is rejected.  Then the graph is
+ * coloured by smallest-last ordering (App. B; ties to the smallest lattice
+ * index, greedy smallest colour in reverse removal order) and laid out as a
+ * colour-sorted CSR.
+ *   L    : even, >= 2.         z : >= 1, N*z even, z < N-1.     rho : >= 0.
+ *   out  : receives a new graph (free with xy_graph_free).
+ * Errors: XY_EINVAL for bad arguments, XY_ECONVERGE if 1000*M + 10^6 draws do
+ * not give M links, XY_ENOMEM. */
+xy_status xy_graph_levy(int L, int z, double rho, uint64_t seed, xy_graph **out);
+
+/* Graph from an explicit edge list (tiny exact-physics graphs, tests).
+ *   edges  : int32[2*m], pairs (i, j), 0 <= i, j < n, no self or repeated links.
+ *   coords : int32[2*n] lattice coordinates (x, y) of each site, 0 <= x, y < L,
+ *            or NULL for (i % L, i / L).  L (1..65535) is the period used by
+ *            the Fourier observables.
+ * Errors: XY_EINVAL (bad index, self or duplicate link), XY_ENOMEM. */
+xy_status xy_graph_from_edges(int n, int m, const int32_t *edges, const int32_t *coords,
+                              int L, xy_graph **out);
+
+/* Sizes: any pointer may be NULL.  attempts = raw draws used (0 for edge lists). */
+xy_status xy_graph_info(const xy_graph *g, int *n, int *m, int *n_colours, int *max_degree,
+                        int64_t *attempts);
+
+/* Copies out the graph (each pointer may be NULL; host buffers, caller-owned):
+ *   edges      int32[2m]   links in acceptance order, as drawn (i, j)
+ *   colour     int32[n]    colour of each lattice site
+ *   perm       int32[n]    lattice index of each colour-major index
+ *   colour_off int32[Q+1]  first colour-major index of each colour
+ *   row_ptr    int32[n+1]  CSR over colour-major indices
+ *   col        int32[2m]   neighbours (colour-major indices), ascending per row */
+xy_status xy_graph_export(const xy_graph *g, int32_t *edges, int32_t *colour, int32_t *perm,
+                          int32_t *colour_off, int32_t *row_ptr, int32_t *col);
+
+void xy_graph_free(xy_graph *g);
+
+/* ----------------------------------------------------------------------- */
+/* Batches (device): n_graphs samples x n_T temperatures, one replica slot  */
+/* per temperature.                                                         */
+/* ----------------------------------------------------------------------- */
+
+typedef struct {
+    size_t state_bytes;   /* spins */
+    size_t graph_bytes;   /* CSR, coordinates, tables (read-only after init) */
+    size_t work_bytes;    /* temperatures, permutations, energies, counters */
+    size_t obs_bytes;     /* measurement records [max_records][n_graphs][n_T][XY_NOBS] double */
+} xy_sizes;
+
+/* Device bytes needed for a batch.  n_T in [1, 256]; precision XY_FP64 or
+ * XY_FIX16 (fix16 needs L to divide 65536); max_records >= 0. */
+xy_status xy_batch_sizes(const xy_graph *const *g, int n_graphs, int n_T, int precision,
+                         int max_records, xy_sizes *out);
+
+/* Creates a batch on caller-owned device buffers (sizes from xy_batch_sizes,
+ * 256-byte aligned) and enqueues the upload of the graphs and the random
+ * initial state (an independent uniform direction per (sample, slot, site),
+ * Philox purpose 2) on `stream`.
+ *   T     : double[n_graphs * n_T] temperature ladders (T > 0), slot k starts at T[k]
+ *   seeds : uint64[n_graphs] Philox keys of the samples' dynamics
+ * The graphs may be freed after this call returns. */
+xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int n_graphs, int n_T,
+                        const double *T, int precision, const uint64_t *seeds, int max_records,
+                        void *d_state, void *d_graph, void *d_work, void *d_obs, void *stream);
+
+/* Runs n_sweeps sweeps (App. B).  A sweep is one Metropolis sub-sweep
+ * (uniform proposal) and n_or over-relaxation sub-sweeps; each sub-sweep
+ * visits the colours in increasing order.  After the sweep, when
+ * pt_every > 0 and (sweep+1) % pt_every == 0, parallel-tempering swaps of the
+ * temperature labels are attempted between T_k and T_{k+1} for k = sweep mod
+ * 2, sweep mod 2 + 2, ...; then, when meas_every > 0 and
+ * (sweep+1) % meas_every == 0, a record [n_graphs][n_T][XY_NOBS] is appended
+ * to the observation buffer (ignored once max_records are stored).
+ * n_sweeps >= 0, 0 <= n_or <= 255. */
+xy_status xy_sweep(xy_batch *b, int n_sweeps, int n_or, int pt_every, int meas_every, void *stream);
+
+/* Observables of the current state, by temperature, into caller-owned device
+ * memory d_out: double[n_graphs][n_T][XY_NOBS] (E, |m|^2, |m|^4, F_x, F_y,
+ * m_x, m_y, 0), with m = (1/N) sum_j S_j and
+ * F_a = |sum_j S_j exp(2 pi i a_j / L)|^2 / N (Sec. 3). */
+xy_status xy_measure(xy_batch *b, double *d_out, void *stream);
+
+/* Enqueues one parallel-tempering step now (energies recomputed from the
+ * current state, pair parity from the sweep counter). */
+xy_status xy_pt_swap(xy_batch *b, void *stream);
+
+/* Synchronous copies of the state (checkpoint, tests).  Host layout:
+ *   fp64 : double[n_graphs][n_T slots][n_i][2], lattice order
+ *   fix16: uint16[n_graphs][n_T slots][n_i], lattice order
+ * plus int32 slot_of_T[n_graphs][n_T] and the sweep counter.  Either array
+ * pointer may be NULL.  set_state does not touch records or PT counters. */
+xy_status xy_get_state(xy_batch *b, void *h_state, int32_t *h_slot_of_T, uint32_t *sweep,
+                       void *stream);
+xy_status xy_set_state(xy_batch *b, const void *h_state, const int32_t *h_slot_of_T,
+                       uint32_t sweep, void *stream);
+
+/* Synchronous read of counters: records stored so far; PT accepted/attempted
+ * per (sample, k) as uint64[n_graphs][n_T] (k = lower temperature of the
+ * pair); either pointer may be NULL. */
+xy_status xy_get_counters(xy_batch *b, int *n_records, uint64_t *pt_accepted,
+                          uint64_t *pt_attempted, void *stream);
+
+/* Parity harness (FP64 batches): while enabled, each Metropolis decision of
+ * sweep w < max_sweeps is written as one byte (1 accepted, 0 rejected) to
+ * d_log[w][sample][slot][lattice site] (caller-owned device memory of
+ * max_sweeps * n_graphs * n_T * max_n bytes, max_n = largest graph).
+ * Sweeps are counted from the enabling call.  d_log = NULL disables. */
+xy_status xy_decision_log(xy_batch *b, uint8_t *d_log, int max_sweeps);
+
+/* Captures `chunk` sweeps of the given shape into a HIP graph that later
+ * xy_sweep calls replay (chunk = 0 turns it off).  chunk must be a multiple of
+ * meas_every and of 2 (PT parity) when those are used. */
+xy_status xy_batch_use_graph(xy_batch *b, int chunk);
+
+/* Kernel timing for roofline reports: while enabled, every xy_sweep records a
+ * HIP event pair on its stream around the dominant kernel of each sweep (the
+ * fix16 sweep kernel, or the colour-phase kernels of an FP64 sweep); HIP graph
+ * replay is bypassed meanwhile.  xy_kernel_time synchronises the stream of the
+ * last sweep, returns the summed elapsed milliseconds and the number of timed
+ * sweeps since timing was enabled, and keeps timing on. */
+xy_status xy_kernel_timing(xy_batch *b, int enable);
+xy_status xy_kernel_time(xy_batch *b, double *ms_total, int *n_timed);
+
+const char *xy_last_error(void);
+void xy_batch_free(xy_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XY_LEVY_H */

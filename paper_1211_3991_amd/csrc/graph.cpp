@@ -1,0 +1,267 @@
+// Host side of the graph path: Levy graph sampling (Sec. 2, Eq. Levyi),
+// smallest-last-ordering colouring (App. B, "Graph coloring") and the
+// colour-sorted CSR that the device kernels stream.  Runs once per sample
+// before the dynamics, as in the paper.
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <set>
+#include <unordered_set>
+#include <utility>
+
+#include "xy_internal.hpp"
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+namespace xy {
+
+xy_status set_error(xy_status code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+// Colouring and CSR.  Smallest-last ordering: repeatedly remove a site of
+// minimum remaining degree (ties: smallest lattice index); colour sites in
+// reverse removal order with the smallest colour unused by their already
+// coloured neighbours.  Sites are then renumbered colour-major (by colour,
+// then lattice index) so that each colour class is one contiguous range and
+// every neighbour list, sorted by colour-major index, lists lower colours
+// first.
+xy_status finish_graph(xy_graph &g)
+{
+    const int n = g.n, m = g.m;
+    std::vector<int32_t> deg(n, 0), start(n + 1, 0), adj(2 * (size_t)m);
+    for (int e = 0; e < m; ++e) { deg[g.edges[2 * e]]++; deg[g.edges[2 * e + 1]]++; }
+    for (int v = 0; v < n; ++v) start[v + 1] = start[v] + deg[v];
+    {
+        std::vector<int32_t> pos(start.begin(), start.end() - 1);
+        for (int e = 0; e < m; ++e) {
+            const int a = g.edges[2 * e], b = g.edges[2 * e + 1];
+            adj[pos[a]++] = b;
+            adj[pos[b]++] = a;
+        }
+    }
+    g.max_deg = n ? *std::max_element(deg.begin(), deg.end()) : 0;
+
+    // removal order: an ordered set of (remaining degree, site)
+    std::vector<int32_t> order;
+    order.reserve(n);
+    {
+        std::vector<int32_t> rem(deg);
+        std::vector<char> gone(n, 0);
+        std::set<std::pair<int32_t, int32_t>> pool;
+        for (int v = 0; v < n; ++v) pool.emplace(rem[v], v);
+        while (!pool.empty()) {
+            const int v = pool.begin()->second;
+            pool.erase(pool.begin());
+            gone[v] = 1;
+            order.push_back(v);
+            for (int a = start[v]; a < start[v + 1]; ++a) {
+                const int w = adj[a];
+                if (gone[w]) continue;
+                pool.erase({rem[w], w});
+                rem[w]--;
+                pool.emplace(rem[w], w);
+            }
+        }
+    }
+    g.colour.assign(n, -1);
+    int Q = 0;
+    {
+        std::vector<int32_t> seen(g.max_deg + 2, -1);
+        for (int idx = n - 1; idx >= 0; --idx) {
+            const int v = order[idx];
+            for (int a = start[v]; a < start[v + 1]; ++a) {
+                const int c = g.colour[adj[a]];
+                if (c >= 0) seen[c] = v;
+            }
+            int c = 0;
+            while (seen[c] == v) ++c;
+            g.colour[v] = c;
+            Q = std::max(Q, c + 1);
+        }
+    }
+    if (n == 0) Q = 0;
+    if (Q > kMaxColours)
+        return set_error(XY_EUNSUP, "graph needs more than 31 colours");
+    g.Q = Q;
+
+    // colour-major renumbering (counting sort, stable in lattice index)
+    g.colour_off.assign(Q + 1, 0);
+    for (int v = 0; v < n; ++v) g.colour_off[g.colour[v] + 1]++;
+    for (int c = 0; c < Q; ++c) g.colour_off[c + 1] += g.colour_off[c];
+    g.perm.assign(n, 0);
+    g.inv.assign(n, 0);
+    {
+        std::vector<int32_t> next(g.colour_off.begin(), g.colour_off.end() - 1);
+        for (int v = 0; v < n; ++v) {
+            const int k = next[g.colour[v]]++;
+            g.perm[k] = v;
+            g.inv[v] = k;
+        }
+    }
+    g.row_ptr.assign(n + 1, 0);
+    g.col.assign(2 * (size_t)m, 0);
+    for (int k = 0; k < n; ++k) g.row_ptr[k + 1] = g.row_ptr[k] + deg[g.perm[k]];
+    for (int k = 0; k < n; ++k) {
+        const int v = g.perm[k];
+        int32_t *row = g.col.data() + g.row_ptr[k];
+        for (int a = start[v]; a < start[v + 1]; ++a) *row++ = g.inv[adj[a]];
+        std::sort(g.col.data() + g.row_ptr[k], g.col.data() + g.row_ptr[k + 1]);
+    }
+    return XY_OK;
+}
+
+}  // namespace xy
+
+using namespace xy;
+
+extern "C" const char *xy_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" xy_status xy_graph_levy(int L, int z, double rho, uint64_t seed, xy_graph **out)
+{
+    if (!out) return set_error(XY_EINVAL, "xy_graph_levy: out is NULL");
+    *out = nullptr;
+    if (L < 2 || (L & 1)) return set_error(XY_EINVAL, "xy_graph_levy: L must be even and >= 2");
+    if (L > 46340) return set_error(XY_EINVAL, "xy_graph_levy: L too large");
+    if (!(rho >= 0.0) || !std::isfinite(rho)) return set_error(XY_EINVAL, "xy_graph_levy: rho must be finite and >= 0");
+    const int64_t N = (int64_t)L * L;
+    if (z < 1 || (N * z) % 2 != 0 || z >= N - 1)
+        return set_error(XY_EINVAL, "xy_graph_levy: need z >= 1, N*z even and z < N-1");
+    const int64_t M = N * z / 2;
+    if (M > (int64_t)1 << 30) return set_error(XY_EINVAL, "xy_graph_levy: too many links");
+
+    xy_graph *g = new (std::nothrow) xy_graph;
+    if (!g) return set_error(XY_ENOMEM, "xy_graph_levy: out of memory");
+    try {
+        g->n = (int)N; g->m = (int)M; g->L = L;
+        // displacement weights w(d) = (dx^2 + dy^2)^(-rho/2), prefix sums in
+        // raster order (dy outer, dx inner), added one at a time
+        const int K = (int)(N - 1);
+        std::vector<int32_t> dxs(K), dys(K);
+        std::vector<double> prefix(K);
+        {
+            double run = 0.0;
+            int k = 0;
+            for (int dy = -L / 2 + 1; dy <= L / 2; ++dy)
+                for (int dx = -L / 2 + 1; dx <= L / 2; ++dx) {
+                    if (dx == 0 && dy == 0) continue;
+                    const double r2 = (double)(dx * dx + dy * dy);
+                    run = run + std::pow(r2, -0.5 * rho);
+                    dxs[k] = dx; dys[k] = dy; prefix[k] = run;
+                    ++k;
+                }
+        }
+        const double total = prefix[K - 1];
+        std::unordered_set<uint64_t> linked;
+        linked.reserve((size_t)(2 * M));
+        g->edges.reserve(2 * (size_t)M);
+        const int64_t cap = 1000 * M + 1000000;
+        int64_t t = 0, have = 0;
+        const uint32_t s0 = (uint32_t)seed, s1 = (uint32_t)(seed >> 32);
+        while (have < M) {
+            if (t >= cap) {
+                delete g;
+                return set_error(XY_ECONVERGE, "xy_graph_levy: attempt cap reached before N*z/2 links");
+            }
+            const U4 w = philox4x32_10({(uint32_t)t, (uint32_t)(t >> 32), 0u, tag(kGraph)}, s0, s1);
+            ++t;
+            const int32_t i = (int32_t)(((uint64_t)w.x * (uint64_t)N) >> 32);
+            const double target = unit53(w.y, w.z) * total;
+            int k = (int)(std::upper_bound(prefix.begin(), prefix.end(), target) - prefix.begin());
+            if (k == K) k = K - 1;
+            const int xi = i % L, yi = i / L;
+            const int xj = ((xi + dxs[k]) % L + L) % L, yj = ((yi + dys[k]) % L + L) % L;
+            const int32_t j = yj * L + xj;
+            const uint64_t key = (uint64_t)std::min(i, j) * (uint64_t)N + (uint64_t)std::max(i, j);
+            if (!linked.insert(key).second) continue;
+            g->edges.push_back(i);
+            g->edges.push_back(j);
+            ++have;
+        }
+        g->attempts = t;
+        g->cx.resize(N); g->cy.resize(N);
+        for (int v = 0; v < N; ++v) { g->cx[v] = v % L; g->cy[v] = v / L; }
+        const xy_status st = finish_graph(*g);
+        if (st != XY_OK) { delete g; return st; }
+    } catch (const std::bad_alloc &) {
+        delete g;
+        return set_error(XY_ENOMEM, "xy_graph_levy: out of memory");
+    }
+    *out = g;
+    return XY_OK;
+}
+
+extern "C" xy_status xy_graph_from_edges(int n, int m, const int32_t *edges, const int32_t *coords,
+                                         int L, xy_graph **out)
+{
+    if (!out) return set_error(XY_EINVAL, "xy_graph_from_edges: out is NULL");
+    *out = nullptr;
+    if (n < 1 || m < 0 || (m > 0 && !edges) || L < 1 || L > 65535)
+        return set_error(XY_EINVAL, "xy_graph_from_edges: need n >= 1, m >= 0, edges, 1 <= L < 65536");
+    xy_graph *g = new (std::nothrow) xy_graph;
+    if (!g) return set_error(XY_ENOMEM, "xy_graph_from_edges: out of memory");
+    try {
+        g->n = n; g->m = m; g->L = L;
+        std::unordered_set<uint64_t> seen;
+        for (int e = 0; e < m; ++e) {
+            const int a = edges[2 * e], b = edges[2 * e + 1];
+            if (a < 0 || b < 0 || a >= n || b >= n || a == b) {
+                delete g;
+                return set_error(XY_EINVAL, "xy_graph_from_edges: index out of range or self link");
+            }
+            const uint64_t key = (uint64_t)std::min(a, b) * (uint64_t)n + (uint64_t)std::max(a, b);
+            if (!seen.insert(key).second) {
+                delete g;
+                return set_error(XY_EINVAL, "xy_graph_from_edges: repeated link");
+            }
+        }
+        g->edges.assign(edges, edges + 2 * (size_t)m);
+        g->cx.resize(n); g->cy.resize(n);
+        for (int v = 0; v < n; ++v) {
+            g->cx[v] = coords ? coords[2 * v] : v % L;
+            g->cy[v] = coords ? coords[2 * v + 1] : v / L;
+            if (g->cx[v] < 0 || g->cy[v] < 0 || g->cx[v] >= L || g->cy[v] >= L) {
+                delete g;
+                return set_error(XY_EINVAL, "xy_graph_from_edges: coordinates must be in [0, L)");
+            }
+        }
+        const xy_status st = finish_graph(*g);
+        if (st != XY_OK) { delete g; return st; }
+    } catch (const std::bad_alloc &) {
+        delete g;
+        return set_error(XY_ENOMEM, "xy_graph_from_edges: out of memory");
+    }
+    *out = g;
+    return XY_OK;
+}
+
+extern "C" xy_status xy_graph_info(const xy_graph *g, int *n, int *m, int *n_colours, int *max_degree,
+                                   int64_t *attempts)
+{
+    if (!g) return set_error(XY_EINVAL, "xy_graph_info: graph is NULL");
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    if (n_colours) *n_colours = g->Q;
+    if (max_degree) *max_degree = g->max_deg;
+    if (attempts) *attempts = g->attempts;
+    return XY_OK;
+}
+
+extern "C" xy_status xy_graph_export(const xy_graph *g, int32_t *edges, int32_t *colour, int32_t *perm,
+                                     int32_t *colour_off, int32_t *row_ptr, int32_t *col)
+{
+    if (!g) return set_error(XY_EINVAL, "xy_graph_export: graph is NULL");
+    if (edges) std::copy(g->edges.begin(), g->edges.end(), edges);
+    if (colour) std::copy(g->colour.begin(), g->colour.end(), colour);
+    if (perm) std::copy(g->perm.begin(), g->perm.end(), perm);
+    if (colour_off) std::copy(g->colour_off.begin(), g->colour_off.end(), colour_off);
+    if (row_ptr) std::copy(g->row_ptr.begin(), g->row_ptr.end(), row_ptr);
+    if (col) std::copy(g->col.begin(), g->col.end(), col);
+    return XY_OK;
+}
+
+extern "C" void xy_graph_free(xy_graph *g) { delete g; }

@@ -1,0 +1,45 @@
+// Kernel argument blocks and host-side launchers (one TU per precision).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "xy_internal.hpp"
+
+namespace xy {
+
+// Everything a kernel needs to find a sample's data on the device.
+struct DevBatch {
+    const SampleDesc *desc;   // [G]
+    const int32_t *i32;       // row_ptr / col / perm pool
+    const uint32_t *u32;      // packed coordinates pool
+    const double2 *f64;       // (cos, sin)(2 pi x / L) pool
+    const float2 *tab32;      // [512]: (cos, sin)(2 pi * 256a / 2^16) then (cos, sin)(2 pi * b / 2^16)
+    const double2 *tab64;     // [512]: same angles in FP64
+    void *state;              // fp64: double2 [site][slot]; fix16: uint16 [slot][site_pad]
+    Ctl *ctl;
+    const double *beta;       // [G][R] by temperature index
+    int32_t *slot_of_T;       // [G][R]
+    int32_t *T_of_slot;       // [G][R]
+    double *E_slot;           // [G][R]
+    double *obs_slot;         // [G][R][XY_NOBS]
+    unsigned long long *pt_acc, *pt_try;  // [G][R]
+    double *records;          // [max_records][G][R][XY_NOBS]
+    int G, R, max_records, max_n;
+    uint8_t *log;             // Metropolis decision log (fp64) or NULL
+    int log_sweeps;
+};
+
+// FP64 path (kernels_fp64.hip, built with -ffp-contract=off).
+hipError_t launch_fp64_init(const DevBatch &b, int max_n, hipStream_t s);
+hipError_t launch_fp64_phase(const DevBatch &b, int colour, int met, int max_class, hipStream_t s);
+hipError_t launch_fp64_observe(const DevBatch &b, int full, double *out_by_T, hipStream_t s);
+hipError_t launch_end_sweep(const DevBatch &b, int do_pt, int do_record, int advance, hipStream_t s);
+
+// fix16 path (kernels_fix16.hip).
+hipError_t launch_fix16_init(const DevBatch &b, int max_n, hipStream_t s);
+hipError_t launch_fix16_sweep(const DevBatch &b, const Item *items, int n_items, bool lds,
+                              int n_or, int measure, size_t lds_bytes, hipStream_t s);
+hipError_t launch_fix16_observe(const DevBatch &b, double *out_by_T, hipStream_t s);
+size_t fix16_lds_bytes(int n_pad, int L);
+
+}  // namespace xy

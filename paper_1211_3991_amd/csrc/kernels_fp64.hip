@@ -1,0 +1,249 @@
+// FP64 plain path: spins are FP64 unit vectors, one thread per (site, slot)
+// of one colour class, one launch per colour phase (App. B: sites of one
+// colour are updated synchronously, colours one after another).  Built with
+// -ffp-contract=off: every state operation is a correctly rounded + - * / or
+// sqrt evaluated in the order written, so the trajectory is bit-identical to
+// a sequential FP64 evaluation of the same sweep.
+//
+// Also holds the end-of-sweep kernel (parallel tempering, records, sweep
+// counter) that both precisions share.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace xy {
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ U4 draw(const SampleDesc &d, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3)
+{
+    return philox4x32_10({c0, c1, c2, c3}, d.seed_lo, d.seed_hi);
+}
+
+// Uniform direction on the circle: points of the square [-1,1)^2 drawn until
+// one falls in the unit disk (0 < r^2 <= 1), then normalised.  Only correctly
+// rounded operations touch the result.
+__device__ __forceinline__ double2 uniform_direction(const SampleDesc &d, uint32_t site, uint32_t sweep,
+                                                     uint32_t slot, Purpose p)
+{
+    for (uint32_t attempt = 0; attempt < 64; ++attempt) {
+        const U4 w = draw(d, site, sweep, slot, tag(p, 0, attempt));
+        const double x = 2.0 * unit53(w.x, w.y) - 1.0;
+        const double y = 2.0 * unit53(w.z, w.w) - 1.0;
+        const double r2 = x * x + y * y;
+        if (r2 > 1.0 || r2 == 0.0) continue;
+        const double r = sqrt(r2);
+        return make_double2(x / r, y / r);
+    }
+    return make_double2(1.0, 0.0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fp64_init(DevBatch b)
+{
+    const SampleDesc d = b.desc[blockIdx.y];
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int site = (int)(t / b.R), slot = (int)(t % b.R);
+    if (site >= d.n) return;
+    double2 *S = static_cast<double2 *>(b.state) + d.state;
+    const uint32_t lattice = (uint32_t)b.i32[d.perm + site];
+    S[(int64_t)site * b.R + slot] = uniform_direction(d, lattice, 0u, (uint32_t)slot, kInit);
+}
+
+// One colour phase of one sub-sweep.  Thread t of sample blockIdx.y handles
+// site colour_off[c] + t / R in slot t % R; neighbouring threads read
+// neighbouring slots of the same site, so every gather is a contiguous run of
+// R * 16 bytes.
+__global__ __launch_bounds__(kBlock) void k_fp64_phase(DevBatch b, int colour, int met)
+{
+    const int s = blockIdx.y;
+    const SampleDesc &d = b.desc[s];
+    if (colour >= d.Q) return;
+    const int c0 = d.colour_off[colour], c1 = d.colour_off[colour + 1];
+    const int R = b.R;
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int site = c0 + (int)(t / R), slot = (int)(t % R);
+    if (site >= c1) return;
+
+    double2 *S = static_cast<double2 *>(b.state) + d.state;
+    const int32_t *row = b.i32 + d.row_ptr;
+    const int32_t *col = b.i32 + d.col;
+    double hx = 0.0, hy = 0.0;
+    for (int a = row[site]; a < row[site + 1]; ++a) {
+        const double2 v = S[(int64_t)col[a] * R + slot];
+        hx = hx + v.x;
+        hy = hy + v.y;
+    }
+    const int64_t me = (int64_t)site * R + slot;
+    const double2 cur = S[me];
+    if (met) {
+        const uint32_t sweep = b.ctl->sweep;
+        const uint32_t lattice = (uint32_t)b.i32[d.perm + site];
+        const double beta = b.beta[s * R + b.T_of_slot[s * R + slot]];
+        const double2 nw = uniform_direction(d, lattice, sweep, (uint32_t)slot, kMet);
+        const double e_old = hx * cur.x + hy * cur.y;
+        const double e_new = hx * nw.x + hy * nw.y;
+        const double dE = e_old - e_new;                 // H = -h.S
+        const U4 w = draw(d, lattice, sweep, (uint32_t)slot, tag(kMetAcc));
+        const bool accept = dE <= 0.0 || unit53(w.x, w.y) < exp(-(beta * dE));
+        if (accept) S[me] = nw;
+        if (b.log) {
+            const uint32_t rel = sweep - b.ctl->log_base;
+            if (rel < (uint32_t)b.log_sweeps)
+                b.log[(((int64_t)rel * b.G + s) * R + slot) * b.max_n + lattice] = accept ? 1 : 0;
+        }
+    } else {
+        // over-relaxation: reflection of S about h (h = 0: unchanged)
+        const double hh = hx * hx + hy * hy;
+        if (hh != 0.0) {
+            const double a = (hx * cur.x + hy * cur.y) / hh;
+            const double two_a = 2.0 * a;
+            S[me] = make_double2(two_a * hx - cur.x, two_a * hy - cur.y);
+        }
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *scratch)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+        for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_down(v[q], off, 64);
+    if (lane == 0)
+        for (int q = 0; q < NV; ++q) scratch[wave * NV + q] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+            for (int q = 0; q < NV; ++q) v[q] += scratch[w * NV + q];
+}
+
+// Energy (and, when full, the observables) of one (sample, slot).
+// E = -sum over links S_i.S_j, each link counted once at its higher
+// colour-major endpoint; m and the Fourier sums of Sec. 3.
+__global__ __launch_bounds__(kBlock) void k_fp64_observe(DevBatch b, int full, double *out_by_T)
+{
+    __shared__ double scratch[(kBlock / 64) * 11];
+    const int slot = blockIdx.x, s = blockIdx.y, R = b.R;
+    const SampleDesc &d = b.desc[s];
+    const double2 *S = static_cast<const double2 *>(b.state) + d.state;
+    const int32_t *row = b.i32 + d.row_ptr;
+    const int32_t *col = b.i32 + d.col;
+    const uint32_t *xy = b.u32 + d.coord;
+    const double2 *trig = b.f64 + d.trig;
+    double v[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i = threadIdx.x; i < d.n; i += kBlock) {
+        const double2 si = S[(int64_t)i * R + slot];
+        double e = 0.0;
+        for (int a = row[i]; a < row[i + 1]; ++a) {
+            const int j = col[a];
+            if (j >= i) break;                        // ascending rows: lower indices first
+            const double2 sj = S[(int64_t)j * R + slot];
+            e += si.x * sj.x + si.y * sj.y;
+        }
+        v[0] -= e;
+        if (full) {
+            const uint32_t p = xy[i];
+            const double2 ex = trig[p & 0xFFFFu], ey = trig[p >> 16];
+            v[1] += si.x; v[2] += si.y;
+            v[3] += si.x * ex.x; v[4] += si.x * ex.y; v[5] += si.y * ex.x; v[6] += si.y * ex.y;
+            v[7] += si.x * ey.x; v[8] += si.x * ey.y; v[9] += si.y * ey.x; v[10] += si.y * ey.y;
+        }
+    }
+    block_sum<11>(v, scratch);
+    if (threadIdx.x != 0) return;
+    b.E_slot[s * R + slot] = v[0];
+    if (!full) return;
+    const double N = (double)d.n;
+    const double mx = v[1] / N, my = v[2] / N, m2 = mx * mx + my * my;
+    double o[XY_NOBS];
+    o[0] = v[0];
+    o[1] = m2;
+    o[2] = m2 * m2;
+    o[3] = (v[3] * v[3] + v[4] * v[4] + v[5] * v[5] + v[6] * v[6]) / N;
+    o[4] = (v[7] * v[7] + v[8] * v[8] + v[9] * v[9] + v[10] * v[10]) / N;
+    o[5] = mx; o[6] = my; o[7] = 0.0;
+    double *dst = out_by_T ? out_by_T + ((int64_t)s * R + b.T_of_slot[s * R + slot]) * XY_NOBS
+                           : b.obs_slot + ((int64_t)s * R + slot) * XY_NOBS;
+    for (int q = 0; q < XY_NOBS; ++q) dst[q] = o[q];
+}
+
+// End of a sweep, one block for the whole batch (so the sweep counter is
+// advanced only after every sample has read it):
+//  - parallel tempering (App. B; Hukushima-Nemoto): pairs (k, k+1) with
+//    k = sweep mod 2, +2, ...; the temperature labels of the two slots are
+//    swapped with probability min(1, exp((beta_k - beta_{k+1})(E_k - E_{k+1})));
+//  - a record of the per-slot observables, reordered by temperature;
+//  - sweep counter (and record counter) advance.
+__global__ __launch_bounds__(kBlock) void k_end_sweep(DevBatch b, int do_pt, int do_record, int advance)
+{
+    const uint32_t sweep = b.ctl->sweep;
+    const uint32_t rec = b.ctl->n_records;
+    const int R = b.R;
+    for (int s = threadIdx.x; s < b.G; s += kBlock) {
+        const SampleDesc &d = b.desc[s];
+        int32_t *sot = b.slot_of_T + s * R;
+        int32_t *tos = b.T_of_slot + s * R;
+        if (do_pt) {
+            const double *beta = b.beta + s * R;
+            const double *E = b.E_slot + s * R;
+            for (int k = (int)(sweep & 1u); k + 1 < R; k += 2) {
+                const int lo = sot[k], hi = sot[k + 1];
+                const double delta = (beta[k] - beta[k + 1]) * (E[lo] - E[hi]);
+                const U4 w = draw(d, (uint32_t)k, sweep, 0u, tag(kPT));
+                const bool accept = delta >= 0.0 || unit53(w.x, w.y) < exp(delta);
+                b.pt_try[s * R + k] += 1;
+                if (accept) {
+                    sot[k] = hi; sot[k + 1] = lo;
+                    tos[hi] = k; tos[lo] = k + 1;
+                    b.pt_acc[s * R + k] += 1;
+                }
+            }
+        }
+        if (do_record && rec < (uint32_t)b.max_records) {
+            double *dst = b.records + (((int64_t)rec * b.G + s) * R) * XY_NOBS;
+            for (int k = 0; k < R; ++k)
+                for (int q = 0; q < XY_NOBS; ++q)
+                    dst[(int64_t)k * XY_NOBS + q] = b.obs_slot[((int64_t)s * R + sot[k]) * XY_NOBS + q];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (advance) b.ctl->sweep = sweep + 1;
+        if (do_record) b.ctl->n_records = rec + 1;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fp64_init(const DevBatch &b, int max_n, hipStream_t s)
+{
+    const int64_t threads = (int64_t)max_n * b.R;
+    dim3 grid((unsigned)((threads + kBlock - 1) / kBlock), (unsigned)b.G);
+    hipLaunchKernelGGL(k_fp64_init, grid, dim3(kBlock), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_fp64_phase(const DevBatch &b, int colour, int met, int max_class, hipStream_t s)
+{
+    const int64_t threads = (int64_t)max_class * b.R;
+    if (threads == 0) return hipSuccess;
+    dim3 grid((unsigned)((threads + kBlock - 1) / kBlock), (unsigned)b.G);
+    hipLaunchKernelGGL(k_fp64_phase, grid, dim3(kBlock), 0, s, b, colour, met);
+    return hipGetLastError();
+}
+
+hipError_t launch_fp64_observe(const DevBatch &b, int full, double *out_by_T, hipStream_t s)
+{
+    dim3 grid((unsigned)b.R, (unsigned)b.G);
+    hipLaunchKernelGGL(k_fp64_observe, grid, dim3(kBlock), 0, s, b, full, out_by_T);
+    return hipGetLastError();
+}
+
+hipError_t launch_end_sweep(const DevBatch &b, int do_pt, int do_record, int advance, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_end_sweep, dim3(1), dim3(kBlock), 0, s, b, do_pt, do_record, advance);
+    return hipGetLastError();
+}
+
+}  // namespace xy

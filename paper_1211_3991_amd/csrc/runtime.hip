@@ -1,0 +1,625 @@
+// Batch runtime: device layout, uploads, the sweep schedule and the C ABI
+// entry points of include/xy_levy.h that touch the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "kernels.hpp"
+
+using namespace xy;
+
+struct xy_batch {
+    int G = 0, R = 0, precision = 0, max_records = 0, max_n = 0, Qmax = 0;
+    std::vector<int> max_class;               // per colour, over samples
+    std::vector<std::vector<int32_t>> perm;   // per sample: colour-major -> lattice
+    std::vector<int> n;                       // per sample
+    std::vector<int64_t> state_off;           // per sample, elements
+    size_t state_bytes = 0;
+    void *d_state = nullptr, *d_graph = nullptr, *d_work = nullptr, *d_obs = nullptr;
+    DevBatch dev{};
+    WorkLayout wl{};
+    Item *items_lds = nullptr, *items_glob = nullptr;
+    int n_items_lds = 0, n_items_glob = 0;
+    size_t lds_bytes_lds = 0, lds_bytes_glob = 0;
+    uint32_t host_sweep = 0;
+    // HIP graph replay of `chunk` sweeps of one shape
+    int chunk = 0;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t gstream = nullptr;
+    int g_n_or = -1, g_pt = -1, g_meas = -1;
+    uint32_t g_phase = 0;   // host_sweep modulo the pattern period at capture time
+    // kernel timing (event pairs around the dominant kernel of each sweep)
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    size_t events_used = 0;
+    hipStream_t timed_stream = nullptr;
+};
+
+namespace {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+xy_status hip_err(hipError_t e, const char *where)
+{
+    return set_error(XY_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+struct Plan {
+    GraphLayout gl{};
+    WorkLayout wl{};
+    size_t state_bytes = 0, obs_bytes = 0;
+    std::vector<SampleDesc> desc;
+    int max_n = 0, Qmax = 0;
+    std::vector<int64_t> state_off;
+    size_t item_cap = 0;
+};
+
+xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int max_records, Plan &p)
+{
+    if (!g || G < 1) return set_error(XY_EINVAL, "batch: need at least one graph");
+    if (R < 1 || R > kMaxT) return set_error(XY_EINVAL, "batch: n_T must be in [1, 256]");
+    if (precision != XY_FP64 && precision != XY_FIX16) return set_error(XY_EINVAL, "batch: unknown precision");
+    if (max_records < 0) return set_error(XY_EINVAL, "batch: max_records < 0");
+    p.desc.assign(G, SampleDesc{});
+    p.state_off.assign(G, 0);
+    size_t n_i32 = 0, n_u32 = 0, n_f64 = 0, state_elems = 0;
+    for (int s = 0; s < G; ++s) {
+        if (!g[s]) return set_error(XY_EINVAL, "batch: NULL graph");
+        const xy_graph &gr = *g[s];
+        if (precision == XY_FIX16 && (65536 % gr.L) != 0)
+            return set_error(XY_EUNSUP, "batch: fix16 needs L to divide 65536");
+        SampleDesc &d = p.desc[s];
+        d.n = gr.n; d.Q = gr.Q; d.L = gr.L; d.max_deg = gr.max_deg;
+        d.row_ptr = (int64_t)n_i32; n_i32 += gr.n + 1;
+        d.col = (int64_t)n_i32;     n_i32 += 2 * (size_t)gr.m;
+        d.perm = (int64_t)n_i32;    n_i32 += gr.n;
+        n_i32 = align_up(n_i32, 4);
+        d.coord = (int64_t)n_u32;   n_u32 += align_up(gr.n, 4);
+        d.trig = (int64_t)n_f64;    n_f64 += gr.L;
+        for (int c = 0; c <= kMaxColours; ++c) d.colour_off[c] = gr.colour_off[std::min(c, gr.Q)];
+        d.state = (int64_t)state_elems;
+        p.state_off[s] = d.state;
+        state_elems += (precision == XY_FP64) ? (size_t)gr.n * R : (size_t)((gr.n + 7) & ~7) * R;
+        p.max_n = std::max(p.max_n, gr.n);
+        p.Qmax = std::max(p.Qmax, gr.Q);
+    }
+    p.item_cap = 8 * (size_t)G * R + 8;   // XCD interleave pads short queues
+    GraphLayout &gl = p.gl;
+    size_t off = 0;
+    gl.desc = off;      off = align_up(off + sizeof(SampleDesc) * G, 256);
+    gl.i32_pool = off;  off = align_up(off + 4 * n_i32, 256);
+    gl.u32_pool = off;  off = align_up(off + 4 * n_u32, 256);
+    gl.f64_pool = off;  off = align_up(off + 16 * n_f64, 256);
+    gl.items = off;     off = align_up(off + 2 * sizeof(Item) * p.item_cap, 256);
+    gl.tab32 = off;     off = align_up(off + 512 * 8, 256);
+    gl.tab64 = off;     off = align_up(off + 512 * 16, 256);
+    gl.total = off;
+    gl.n_i32 = n_i32; gl.n_u32 = n_u32; gl.n_f64 = n_f64;
+    WorkLayout &wl = p.wl;
+    const size_t GR = (size_t)G * R;
+    off = 0;
+    wl.ctl = off;       off = align_up(off + sizeof(Ctl), 256);
+    wl.beta = off;      off = align_up(off + 8 * GR, 256);
+    wl.slot_of_T = off; off = align_up(off + 4 * GR, 256);
+    wl.T_of_slot = off; off = align_up(off + 4 * GR, 256);
+    wl.E_slot = off;    off = align_up(off + 8 * GR, 256);
+    wl.obs_slot = off;  off = align_up(off + 8 * XY_NOBS * GR, 256);
+    wl.pt_acc = off;    off = align_up(off + 8 * GR, 256);
+    wl.pt_try = off;    off = align_up(off + 8 * GR, 256);
+    wl.total = off;
+    p.state_bytes = align_up(state_elems * (precision == XY_FP64 ? 16 : 2), 256);
+    p.obs_bytes = align_up((size_t)max_records * GR * XY_NOBS * 8, 256);
+    return XY_OK;
+}
+
+// Items of the fix16 sweep, ordered so that blockIdx b runs on XCD b % 8 and
+// all slots of one sample run on one XCD (they share its CSR in that L2).
+// Samples go to the least-loaded XCD in order of decreasing work.
+std::vector<Item> xcd_order(const std::vector<int> &samples, const std::vector<SampleDesc> &desc, int R)
+{
+    constexpr int kXcd = 8;
+    std::vector<int> order(samples);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return desc[a].n > desc[b].n; });
+    if (order.size() < (size_t)kXcd) {   // too few samples to spread: plain order
+        std::vector<Item> out;
+        for (int s : order)
+            for (int r = 0; r < R; ++r) out.push_back({s, r});
+        return out;
+    }
+    std::vector<std::vector<Item>> q(kXcd);
+    std::vector<double> load(kXcd, 0.0);
+    for (int s : order) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        for (int r = 0; r < R; ++r) q[x].push_back({s, r});
+        load[x] += (double)desc[s].n * R;
+    }
+    size_t longest = 0;
+    for (auto &v : q) longest = std::max(longest, v.size());
+    std::vector<Item> out;
+    for (size_t r = 0; r < longest; ++r)
+        for (int x = 0; x < kXcd; ++x) out.push_back(r < q[x].size() ? q[x][r] : Item{-1, -1});
+    while (!out.empty() && out.back().sample < 0) out.pop_back();
+    return out;
+}
+
+}  // namespace
+
+extern "C" xy_status xy_batch_sizes(const xy_graph *const *g, int n_graphs, int n_T, int precision,
+                                    int max_records, xy_sizes *out)
+{
+    if (!out) return set_error(XY_EINVAL, "xy_batch_sizes: out is NULL");
+    Plan p;
+    const xy_status st = plan_batch(g, n_graphs, n_T, precision, max_records, p);
+    if (st != XY_OK) return st;
+    out->state_bytes = p.state_bytes;
+    out->graph_bytes = p.gl.total;
+    out->work_bytes = p.wl.total;
+    out->obs_bytes = p.obs_bytes;
+    return XY_OK;
+}
+
+extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int n_graphs, int n_T,
+                                   const double *T, int precision, const uint64_t *seeds, int max_records,
+                                   void *d_state, void *d_graph, void *d_work, void *d_obs, void *stream)
+{
+    if (!out) return set_error(XY_EINVAL, "xy_batch_init: out is NULL");
+    *out = nullptr;
+    Plan p;
+    xy_status st = plan_batch(g, n_graphs, n_T, precision, max_records, p);
+    if (st != XY_OK) return st;
+    if (!T || !seeds) return set_error(XY_EINVAL, "xy_batch_init: T and seeds are required");
+    for (int k = 0; k < n_graphs * n_T; ++k)
+        if (!(T[k] > 0.0) || !std::isfinite(T[k])) return set_error(XY_EINVAL, "xy_batch_init: temperatures must be finite and > 0");
+    if (!d_state || !d_graph || !d_work || (max_records > 0 && !d_obs))
+        return set_error(XY_EINVAL, "xy_batch_init: NULL device buffer");
+    for (void *ptr : {d_state, d_graph, d_work})
+        if (reinterpret_cast<uintptr_t>(ptr) % 256 != 0) return set_error(XY_EINVAL, "xy_batch_init: buffers must be 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    xy_batch *b = new (std::nothrow) xy_batch;
+    if (!b) return set_error(XY_ENOMEM, "xy_batch_init: out of memory");
+    try {
+        const int G = n_graphs, R = n_T;
+        b->G = G; b->R = R; b->precision = precision; b->max_records = max_records;
+        b->max_n = p.max_n; b->Qmax = p.Qmax;
+        b->d_state = d_state; b->d_graph = d_graph; b->d_work = d_work; b->d_obs = d_obs;
+        b->wl = p.wl;
+        b->state_bytes = p.state_bytes;
+        b->state_off = p.state_off;
+        b->max_class.assign(p.Qmax, 0);
+        b->perm.resize(G);
+        b->n.resize(G);
+        for (int s_ = 0; s_ < G; ++s_) {
+            const xy_graph &gr = *g[s_];
+            for (int c = 0; c < gr.Q; ++c)
+                b->max_class[c] = std::max(b->max_class[c], gr.colour_off[c + 1] - gr.colour_off[c]);
+            b->perm[s_] = gr.perm;
+            b->n[s_] = gr.n;
+            p.desc[s_].seed_lo = (uint32_t)seeds[s_];
+            p.desc[s_].seed_hi = (uint32_t)(seeds[s_] >> 32);
+        }
+
+        // ---- graph region image
+        const GraphLayout &gl = p.gl;
+        std::vector<unsigned char> gimg(gl.total, 0);
+        std::memcpy(gimg.data() + gl.desc, p.desc.data(), sizeof(SampleDesc) * G);
+        int32_t *i32 = reinterpret_cast<int32_t *>(gimg.data() + gl.i32_pool);
+        uint32_t *u32 = reinterpret_cast<uint32_t *>(gimg.data() + gl.u32_pool);
+        double *f64 = reinterpret_cast<double *>(gimg.data() + gl.f64_pool);
+        const double two_pi = 6.283185307179586476925286766559;
+        for (int s_ = 0; s_ < G; ++s_) {
+            const xy_graph &gr = *g[s_];
+            const SampleDesc &d = p.desc[s_];
+            std::copy(gr.row_ptr.begin(), gr.row_ptr.end(), i32 + d.row_ptr);
+            std::copy(gr.col.begin(), gr.col.end(), i32 + d.col);
+            std::copy(gr.perm.begin(), gr.perm.end(), i32 + d.perm);
+            for (int k = 0; k < gr.n; ++k) {
+                const int v = gr.perm[k];
+                u32[d.coord + k] = (uint32_t)gr.cx[v] | ((uint32_t)gr.cy[v] << 16);
+            }
+            for (int x = 0; x < gr.L; ++x) {
+                f64[2 * (d.trig + x)] = std::cos(two_pi * x / gr.L);
+                f64[2 * (d.trig + x) + 1] = std::sin(two_pi * x / gr.L);
+            }
+        }
+        const size_t off_tab32 = gl.tab32, off_tab64 = gl.tab64;
+        float *t32 = reinterpret_cast<float *>(gimg.data() + off_tab32);
+        double *t64 = reinterpret_cast<double *>(gimg.data() + off_tab64);
+        for (int k = 0; k < 256; ++k) {
+            const double ahi = two_pi * (256.0 * k) / 65536.0, alo = two_pi * k / 65536.0;
+            t64[2 * k] = std::cos(ahi);          t64[2 * k + 1] = std::sin(ahi);
+            t64[512 + 2 * k] = std::cos(alo);    t64[512 + 2 * k + 1] = std::sin(alo);
+            t32[2 * k] = (float)t64[2 * k];      t32[2 * k + 1] = (float)t64[2 * k + 1];
+            t32[512 + 2 * k] = (float)t64[512 + 2 * k];
+            t32[512 + 2 * k + 1] = (float)t64[512 + 2 * k + 1];
+        }
+        // fix16 items: LDS-resident where the replica fits, else global state
+        if (precision == XY_FIX16) {
+            int dev = 0, lds_limit = 0;
+            (void)hipGetDevice(&dev);
+            if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+                lds_limit = 65536;
+            std::vector<int> in_lds, in_glob;
+            size_t lds_max = 0, glob_max = 0;
+            for (int s_ = 0; s_ < G; ++s_) {
+                const int n_pad = (p.desc[s_].n + 7) & ~7;
+                const size_t need = fix16_lds_bytes(n_pad, p.desc[s_].L);
+                if (need <= (size_t)lds_limit) { in_lds.push_back(s_); lds_max = std::max(lds_max, need); }
+                else { in_glob.push_back(s_); glob_max = std::max(glob_max, fix16_lds_bytes(0, p.desc[s_].L)); }
+            }
+            const std::vector<Item> a = xcd_order(in_lds, p.desc, R), c = xcd_order(in_glob, p.desc, R);
+            if (a.size() > p.item_cap || c.size() > p.item_cap) {
+                delete b;
+                return set_error(XY_EUNSUP, "xy_batch_init: work-item list exceeds its capacity");
+            }
+            Item *items = reinterpret_cast<Item *>(gimg.data() + gl.items);
+            std::copy(a.begin(), a.end(), items);
+            std::copy(c.begin(), c.end(), items + p.item_cap);
+            b->n_items_lds = (int)a.size();
+            b->n_items_glob = (int)c.size();
+            b->lds_bytes_lds = lds_max;
+            b->lds_bytes_glob = glob_max;
+            b->items_lds = reinterpret_cast<Item *>(static_cast<unsigned char *>(d_graph) + gl.items);
+            b->items_glob = b->items_lds + p.item_cap;
+        }
+
+        // ---- work region image
+        const WorkLayout &wl = p.wl;
+        std::vector<unsigned char> wimg(wl.total, 0);
+        double *beta = reinterpret_cast<double *>(wimg.data() + wl.beta);
+        int32_t *sot = reinterpret_cast<int32_t *>(wimg.data() + wl.slot_of_T);
+        int32_t *tos = reinterpret_cast<int32_t *>(wimg.data() + wl.T_of_slot);
+        for (int k = 0; k < G * R; ++k) {
+            beta[k] = 1.0 / T[k];
+            sot[k] = k % R;
+            tos[k] = k % R;
+        }
+
+        hipError_t e;
+        if ((e = hipMemcpyAsync(d_graph, gimg.data(), gimg.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(d_work, wimg.data(), wimg.size(), hipMemcpyHostToDevice, s)) != hipSuccess) {
+            delete b;
+            return hip_err(e, "xy_batch_init upload");
+        }
+
+        unsigned char *gbase = static_cast<unsigned char *>(d_graph);
+        unsigned char *wbase = static_cast<unsigned char *>(d_work);
+        DevBatch &dv = b->dev;
+        dv.desc = reinterpret_cast<const SampleDesc *>(gbase + gl.desc);
+        dv.i32 = reinterpret_cast<const int32_t *>(gbase + gl.i32_pool);
+        dv.u32 = reinterpret_cast<const uint32_t *>(gbase + gl.u32_pool);
+        dv.f64 = reinterpret_cast<const double2 *>(gbase + gl.f64_pool);
+        dv.tab32 = reinterpret_cast<const float2 *>(gbase + off_tab32);
+        dv.tab64 = reinterpret_cast<const double2 *>(gbase + off_tab64);
+        dv.state = d_state;
+        dv.ctl = reinterpret_cast<Ctl *>(wbase + wl.ctl);
+        dv.beta = reinterpret_cast<const double *>(wbase + wl.beta);
+        dv.slot_of_T = reinterpret_cast<int32_t *>(wbase + wl.slot_of_T);
+        dv.T_of_slot = reinterpret_cast<int32_t *>(wbase + wl.T_of_slot);
+        dv.E_slot = reinterpret_cast<double *>(wbase + wl.E_slot);
+        dv.obs_slot = reinterpret_cast<double *>(wbase + wl.obs_slot);
+        dv.pt_acc = reinterpret_cast<unsigned long long *>(wbase + wl.pt_acc);
+        dv.pt_try = reinterpret_cast<unsigned long long *>(wbase + wl.pt_try);
+        dv.records = static_cast<double *>(d_obs);
+        dv.G = G; dv.R = R; dv.max_records = max_records; dv.max_n = p.max_n;
+        dv.log = nullptr; dv.log_sweeps = 0;
+
+        e = (precision == XY_FP64) ? launch_fp64_init(dv, p.max_n, s) : launch_fix16_init(dv, p.max_n, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);   // host images must outlive the copies
+        if (e != hipSuccess) { delete b; return hip_err(e, "xy_batch_init"); }
+    } catch (const std::bad_alloc &) {
+        delete b;
+        return set_error(XY_ENOMEM, "xy_batch_init: out of memory");
+    }
+    *out = b;
+    return XY_OK;
+}
+
+namespace {
+
+// Event pair for the next timed sweep (created on first use, then reused).
+hipError_t next_events(xy_batch *b, hipEvent_t *start, hipEvent_t *stop)
+{
+    if (b->events_used == b->events.size()) {
+        hipEvent_t a = nullptr, c = nullptr;
+        hipError_t e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&c);
+        if (e != hipSuccess) return e;
+        b->events.emplace_back(a, c);
+    }
+    *start = b->events[b->events_used].first;
+    *stop = b->events[b->events_used].second;
+    b->events_used++;
+    return hipSuccess;
+}
+
+// Enqueues one sweep with the given flags.
+hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (b->timing) {
+        e = next_events(b, &ev0, &ev1);
+        if (e == hipSuccess) e = hipEventRecord(ev0, s);
+        if (e != hipSuccess) return e;
+        b->timed_stream = s;
+    }
+    if (b->precision == XY_FP64) {
+        for (int sub = 0; sub <= n_or && e == hipSuccess; ++sub)
+            for (int c = 0; c < b->Qmax && e == hipSuccess; ++c)
+                e = launch_fp64_phase(b->dev, c, sub == 0, b->max_class[c], s);
+        if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
+        if (e == hipSuccess && (do_pt || do_rec)) e = launch_fp64_observe(b->dev, do_rec, nullptr, s);
+    } else {
+        e = launch_fix16_sweep(b->dev, b->items_lds, b->n_items_lds, true, n_or, do_rec, b->lds_bytes_lds, s);
+        if (e == hipSuccess)
+            e = launch_fix16_sweep(b->dev, b->items_glob, b->n_items_glob, false, n_or, do_rec, b->lds_bytes_glob, s);
+        if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
+    }
+    if (e == hipSuccess) e = launch_end_sweep(b->dev, do_pt, do_rec, 1, s);
+    return e;
+}
+
+bool flag_at(uint32_t sweep, int every) { return every > 0 && (sweep + 1) % (uint32_t)every == 0; }
+
+}  // namespace
+
+extern "C" xy_status xy_sweep(xy_batch *b, int n_sweeps, int n_or, int pt_every, int meas_every, void *stream)
+{
+    if (!b) return set_error(XY_EINVAL, "xy_sweep: batch is NULL");
+    if (n_sweeps < 0 || n_or < 0 || n_or > 255 || pt_every < 0 || meas_every < 0)
+        return set_error(XY_EINVAL, "xy_sweep: bad arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int done = 0;
+    // HIP graph replay: the captured chunk starts at a sweep index congruent
+    // to the one it was captured at, modulo the PT/measurement period.
+    if (b->chunk > 0 && !b->timing) {
+        if (!s) return set_error(XY_EINVAL, "xy_sweep: HIP graph capture needs a non-null stream");
+        const uint32_t period = (uint32_t)std::max({2, pt_every, meas_every});
+        while (n_sweeps - done >= b->chunk) {
+            const bool shape_ok = b->gexec && b->g_n_or == n_or && b->g_pt == pt_every && b->g_meas == meas_every &&
+                                  b->gstream == s && (b->host_sweep % period) == b->g_phase;
+            if (!shape_ok) {
+                if ((b->host_sweep % period) != 0) break;   // align by direct launches first
+                if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+                hipGraph_t graph = nullptr;
+                hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+                if (e != hipSuccess) return hip_err(e, "xy_sweep capture");
+                uint32_t sw = b->host_sweep;
+                for (int k = 0; k < b->chunk && e == hipSuccess; ++k, ++sw)
+                    e = enqueue_sweep(b, n_or, flag_at(sw, pt_every), flag_at(sw, meas_every), s);
+                hipError_t e2 = hipStreamEndCapture(s, &graph);
+                if (e == hipSuccess) e = e2;
+                if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+                if (graph) (void)hipGraphDestroy(graph);
+                if (e != hipSuccess) { b->gexec = nullptr; return hip_err(e, "xy_sweep graph"); }
+                b->g_n_or = n_or; b->g_pt = pt_every; b->g_meas = meas_every; b->gstream = s;
+                b->g_phase = b->host_sweep % period;
+            }
+            const hipError_t e = hipGraphLaunch(b->gexec, s);
+            if (e != hipSuccess) return hip_err(e, "xy_sweep graph launch");
+            b->host_sweep += (uint32_t)b->chunk;
+            done += b->chunk;
+        }
+    }
+    for (; done < n_sweeps; ++done) {
+        const uint32_t sw = b->host_sweep;
+        const hipError_t e = enqueue_sweep(b, n_or, flag_at(sw, pt_every), flag_at(sw, meas_every), s);
+        if (e != hipSuccess) return hip_err(e, "xy_sweep");
+        b->host_sweep++;
+    }
+    return XY_OK;
+}
+
+extern "C" xy_status xy_batch_use_graph(xy_batch *b, int chunk)
+{
+    if (!b || chunk < 0) return set_error(XY_EINVAL, "xy_batch_use_graph: bad arguments");
+    if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+    b->chunk = chunk;
+    return XY_OK;
+}
+
+extern "C" xy_status xy_measure(xy_batch *b, double *d_out, void *stream)
+{
+    if (!b || !d_out) return set_error(XY_EINVAL, "xy_measure: bad arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipError_t e = (b->precision == XY_FP64) ? launch_fp64_observe(b->dev, 1, d_out, s)
+                                                   : launch_fix16_observe(b->dev, d_out, s);
+    return e == hipSuccess ? XY_OK : hip_err(e, "xy_measure");
+}
+
+extern "C" xy_status xy_pt_swap(xy_batch *b, void *stream)
+{
+    if (!b) return set_error(XY_EINVAL, "xy_pt_swap: batch is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = (b->precision == XY_FP64) ? launch_fp64_observe(b->dev, 0, nullptr, s)
+                                             : launch_fix16_observe(b->dev, nullptr, s);
+    if (e == hipSuccess) e = launch_end_sweep(b->dev, 1, 0, 0, s);
+    return e == hipSuccess ? XY_OK : hip_err(e, "xy_pt_swap");
+}
+
+extern "C" xy_status xy_get_state(xy_batch *b, void *h_state, int32_t *h_slot_of_T, uint32_t *sweep, void *stream)
+{
+    if (!b) return set_error(XY_EINVAL, "xy_get_state: batch is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int G = b->G, R = b->R;
+    try {
+        std::vector<unsigned char> raw(h_state ? b->state_bytes : 0);
+        std::vector<int32_t> sot(h_slot_of_T ? (size_t)G * R : 0);
+        Ctl ctl{};
+        hipError_t e = hipSuccess;
+        if (h_state) e = hipMemcpyAsync(raw.data(), b->d_state, raw.size(), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess && h_slot_of_T)
+            e = hipMemcpyAsync(sot.data(), b->dev.slot_of_T, sot.size() * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&ctl, b->dev.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_err(e, "xy_get_state");
+        if (h_state) {
+            size_t out_off = 0;
+            for (int g = 0; g < G; ++g) {
+                const int n = b->n[g];
+                const std::vector<int32_t> &pm = b->perm[g];
+                if (b->precision == XY_FP64) {
+                    const double *src = reinterpret_cast<const double *>(raw.data()) + 2 * b->state_off[g];
+                    double *dst = static_cast<double *>(h_state) + out_off;
+                    for (int r = 0; r < R; ++r)
+                        for (int k = 0; k < n; ++k) {
+                            dst[2 * ((size_t)r * n + pm[k])] = src[2 * ((size_t)k * R + r)];
+                            dst[2 * ((size_t)r * n + pm[k]) + 1] = src[2 * ((size_t)k * R + r) + 1];
+                        }
+                    out_off += 2 * (size_t)R * n;
+                } else {
+                    const int n_pad = (n + 7) & ~7;
+                    const uint16_t *src = reinterpret_cast<const uint16_t *>(raw.data()) + b->state_off[g];
+                    uint16_t *dst = static_cast<uint16_t *>(h_state) + out_off;
+                    for (int r = 0; r < R; ++r)
+                        for (int k = 0; k < n; ++k) dst[(size_t)r * n + pm[k]] = src[(size_t)r * n_pad + k];
+                    out_off += (size_t)R * n;
+                }
+            }
+        }
+        if (h_slot_of_T) std::copy(sot.begin(), sot.end(), h_slot_of_T);
+        if (sweep) *sweep = ctl.sweep;
+    } catch (const std::bad_alloc &) {
+        return set_error(XY_ENOMEM, "xy_get_state: out of memory");
+    }
+    return XY_OK;
+}
+
+extern "C" xy_status xy_set_state(xy_batch *b, const void *h_state, const int32_t *h_slot_of_T, uint32_t sweep,
+                                  void *stream)
+{
+    if (!b) return set_error(XY_EINVAL, "xy_set_state: batch is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int G = b->G, R = b->R;
+    try {
+        std::vector<int32_t> sot, tos;
+        if (h_slot_of_T) {
+            sot.assign(h_slot_of_T, h_slot_of_T + (size_t)G * R);
+            tos.assign((size_t)G * R, -1);
+            for (int g = 0; g < G; ++g)
+                for (int k = 0; k < R; ++k) {
+                    const int r = sot[(size_t)g * R + k];
+                    if (r < 0 || r >= R || tos[(size_t)g * R + r] >= 0)
+                        return set_error(XY_EINVAL, "xy_set_state: slot_of_T is not a permutation");
+                    tos[(size_t)g * R + r] = k;
+                }
+        }
+        std::vector<unsigned char> raw(h_state ? b->state_bytes : 0, 0);
+        if (h_state) {
+            size_t in_off = 0;
+            for (int g = 0; g < G; ++g) {
+                const int n = b->n[g];
+                const std::vector<int32_t> &pm = b->perm[g];
+                if (b->precision == XY_FP64) {
+                    double *dst = reinterpret_cast<double *>(raw.data()) + 2 * b->state_off[g];
+                    const double *src = static_cast<const double *>(h_state) + in_off;
+                    for (int r = 0; r < R; ++r)
+                        for (int k = 0; k < n; ++k) {
+                            dst[2 * ((size_t)k * R + r)] = src[2 * ((size_t)r * n + pm[k])];
+                            dst[2 * ((size_t)k * R + r) + 1] = src[2 * ((size_t)r * n + pm[k]) + 1];
+                        }
+                    in_off += 2 * (size_t)R * n;
+                } else {
+                    const int n_pad = (n + 7) & ~7;
+                    uint16_t *dst = reinterpret_cast<uint16_t *>(raw.data()) + b->state_off[g];
+                    const uint16_t *src = static_cast<const uint16_t *>(h_state) + in_off;
+                    for (int r = 0; r < R; ++r)
+                        for (int k = 0; k < n; ++k) dst[(size_t)r * n_pad + k] = src[(size_t)r * n + pm[k]];
+                    in_off += (size_t)R * n;
+                }
+            }
+        }
+        hipError_t e = hipSuccess;
+        if (h_state) e = hipMemcpyAsync(b->d_state, raw.data(), raw.size(), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && h_slot_of_T) {
+            e = hipMemcpyAsync(b->dev.slot_of_T, sot.data(), sot.size() * 4, hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(b->dev.T_of_slot, tos.data(), tos.size() * 4, hipMemcpyHostToDevice, s);
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(&b->dev.ctl->sweep, &sweep, 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_err(e, "xy_set_state");
+        b->host_sweep = sweep;
+        if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+    } catch (const std::bad_alloc &) {
+        return set_error(XY_ENOMEM, "xy_set_state: out of memory");
+    }
+    return XY_OK;
+}
+
+extern "C" xy_status xy_get_counters(xy_batch *b, int *n_records, uint64_t *pt_accepted, uint64_t *pt_attempted,
+                                     void *stream)
+{
+    if (!b) return set_error(XY_EINVAL, "xy_get_counters: batch is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t GR = (size_t)b->G * b->R;
+    Ctl ctl{};
+    hipError_t e = hipMemcpyAsync(&ctl, b->dev.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && pt_accepted) e = hipMemcpyAsync(pt_accepted, b->dev.pt_acc, 8 * GR, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && pt_attempted) e = hipMemcpyAsync(pt_attempted, b->dev.pt_try, 8 * GR, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_err(e, "xy_get_counters");
+    if (n_records) *n_records = (int)std::min<uint32_t>(ctl.n_records, (uint32_t)b->max_records);
+    return XY_OK;
+}
+
+extern "C" xy_status xy_decision_log(xy_batch *b, uint8_t *d_log, int max_sweeps)
+{
+    if (!b) return set_error(XY_EINVAL, "xy_decision_log: batch is NULL");
+    if (b->precision != XY_FP64) return set_error(XY_EUNSUP, "xy_decision_log: FP64 batches only");
+    if (d_log && max_sweeps < 0) return set_error(XY_EINVAL, "xy_decision_log: max_sweeps < 0");
+    // the log base is the sweep counter now; it is written synchronously
+    const uint32_t base = b->host_sweep;
+    const hipError_t e = hipMemcpy(&b->dev.ctl->log_base, &base, 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_err(e, "xy_decision_log");
+    b->dev.log = d_log;
+    b->dev.log_sweeps = d_log ? max_sweeps : 0;
+    if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+    return XY_OK;
+}
+
+extern "C" xy_status xy_kernel_timing(xy_batch *b, int enable)
+{
+    if (!b) return set_error(XY_EINVAL, "xy_kernel_timing: batch is NULL");
+    if (b->timed_stream || b->events_used) {
+        const hipError_t e = hipStreamSynchronize(b->timed_stream);
+        if (e != hipSuccess) return hip_err(e, "xy_kernel_timing");
+    }
+    b->timing = enable != 0;
+    b->events_used = 0;
+    return XY_OK;
+}
+
+extern "C" xy_status xy_kernel_time(xy_batch *b, double *ms_total, int *n_timed)
+{
+    if (!b) return set_error(XY_EINVAL, "xy_kernel_time: batch is NULL");
+    double total = 0.0;
+    if (b->events_used) {
+        hipError_t e = hipStreamSynchronize(b->timed_stream);
+        for (size_t k = 0; k < b->events_used && e == hipSuccess; ++k) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, b->events[k].first, b->events[k].second);
+            total += ms;
+        }
+        if (e != hipSuccess) return hip_err(e, "xy_kernel_time");
+    }
+    if (ms_total) *ms_total = total;
+    if (n_timed) *n_timed = (int)b->events_used;
+    return XY_OK;
+}
+
+extern "C" void xy_batch_free(xy_batch *b)
+{
+    if (!b) return;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    for (auto &pr : b->events) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    delete b;
+}

@@ -1,0 +1,130 @@
+// Internal definitions shared by the library's host and device sources.
+// Nothing here is part of the public ABI (include/xy_levy.h).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/xy_levy.h"
+
+#if defined(__HIPCC__)
+#define XY_HD __host__ __device__ __forceinline__
+#else
+#define XY_HD inline
+#endif
+
+namespace xy {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11).  The counter-based
+// generator replaces the paper's per-thread lagged-Fibonacci streams (App. B,
+// "Memory management"): a draw is a pure function of (key, counter), so no
+// generator state is stored and any draw can be recomputed anywhere.
+// ---------------------------------------------------------------------------
+struct U4 { uint32_t x, y, z, w; };
+
+XY_HD U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
+{
+    const uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+    const uint32_t kBumpA = 0x9E3779B9u, kBumpB = 0xBB67AE85u;
+#if defined(__HIPCC__)
+#pragma unroll
+#endif
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t pa = (uint64_t)kMulA * c.x;
+        const uint64_t pb = (uint64_t)kMulB * c.z;
+        U4 n;
+        n.x = (uint32_t)(pb >> 32) ^ c.y ^ k0;
+        n.y = (uint32_t)pb;
+        n.z = (uint32_t)(pa >> 32) ^ c.w ^ k1;
+        n.w = (uint32_t)pa;
+        c = n;
+        k0 += kBumpA;
+        k1 += kBumpB;
+    }
+    return c;
+}
+
+// Draw purposes: top byte of counter word w.  Word z carries the slot,
+// word y the sweep, word x the site (or the draw index).
+enum Purpose : uint32_t { kGraph = 1, kInit = 2, kMet = 3, kMetAcc = 4, kOR = 5, kPT = 6 };
+
+XY_HD uint32_t tag(Purpose p, uint32_t sub = 0, uint32_t attempt = 0)
+{
+    return ((uint32_t)p << 24) | (sub << 16) | attempt;
+}
+
+// 53-bit uniform in [0,1): 32 bits of `hi` above the top 21 bits of `lo`.
+XY_HD double unit53(uint32_t hi, uint32_t lo)
+{
+    const uint64_t bits = ((uint64_t)hi << 21) | (uint64_t)(lo >> 11);
+    return (double)bits * 0x1.0p-53;
+}
+
+// ---------------------------------------------------------------------------
+// Host graph object.
+// ---------------------------------------------------------------------------
+}  // namespace xy
+
+struct xy_graph {
+    int n = 0, m = 0, L = 0, Q = 0, max_deg = 0;
+    int64_t attempts = 0;
+    std::vector<int32_t> edges;       // 2m, acceptance order (i, j)
+    std::vector<int32_t> colour;      // by lattice index
+    std::vector<int32_t> perm;        // colour-major index -> lattice index
+    std::vector<int32_t> inv;         // lattice index -> colour-major index
+    std::vector<int32_t> colour_off;  // Q + 1
+    std::vector<int32_t> row_ptr;     // n + 1, colour-major
+    std::vector<int32_t> col;         // 2m, colour-major neighbours, ascending per row
+    std::vector<int32_t> cx, cy;      // lattice coordinates by lattice index
+};
+
+namespace xy {
+
+constexpr int kMaxColours = 31;
+constexpr int kMaxT = 256;
+
+xy_status set_error(xy_status code, const std::string &msg);
+
+// Builds colouring + colour-sorted CSR of a graph whose n, m, L, edges, cx,
+// cy are filled.  Returns XY_OK or an error status.
+xy_status finish_graph(xy_graph &g);
+
+// ---------------------------------------------------------------------------
+// Device-side descriptors (plain data, copied into the graph region).
+// ---------------------------------------------------------------------------
+struct SampleDesc {
+    int32_t n, Q, L, max_deg;
+    int64_t row_ptr;      // element offsets into the graph region's int32 pool
+    int64_t col;
+    int64_t perm;
+    int64_t coord;        // uint32 pool: x | y << 16, by colour-major index
+    int64_t trig;         // double2 pool: (cos, sin)(2 pi x / L), x < L
+    int64_t state;        // element offset into the state region (double2 or uint16)
+    uint32_t seed_lo, seed_hi;
+    int32_t colour_off[kMaxColours + 1];
+};
+
+struct Ctl {
+    uint32_t sweep;        // sweeps completed
+    uint32_t n_records;    // records written (may exceed max_records: then dropped)
+    uint32_t log_base;     // sweep at which the decision log was enabled
+    uint32_t pad;
+};
+
+// Work region layout (byte offsets computed by layout_work()).
+struct WorkLayout {
+    size_t ctl, beta, slot_of_T, T_of_slot, E_slot, obs_slot, pt_acc, pt_try, total;
+};
+
+struct GraphLayout {
+    size_t desc, i32_pool, u32_pool, f64_pool, items, tab32, tab64, total;
+    size_t n_i32, n_u32, n_f64;
+};
+
+// One fix16 work item: a (sample, slot) pair run by one workgroup.
+struct Item { int32_t sample, slot; };
+
+}  // namespace xy

@@ -1,0 +1,178 @@
+"""GPU tests of the fixed-point (16-bit angle) batched path, through the C ABI.
+
+The fixed-point sweep samples the 2^16-state clock model with FP32 table
+energies, so its bar is statistical: observables within 3 sigma (jackknife
+over time bins) of
+* the exact tiny-graph values (Bessel closed forms; the clock model's
+  thermodynamics equal the XY model's up to aliasing terms ~ I_65536(beta)),
+* the FP64 oracle on the L=16 plain workload (4 T),
+* the FP64 GPU path on a PT batch.
+Its measurement kernel is checked element by element against the oracle's
+measurement of the same state (angles converted to FP64 unit vectors).
+"""
+import numpy as np
+import pytest
+from scipy import special
+
+import oracle
+import workloads
+from stats_helpers import batch_mean_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1211_3991_amd as xy  # noqa: E402
+
+TWO_PI = 2 * np.pi
+
+
+def _unit(theta_u16):
+    a = TWO_PI * theta_u16.astype(np.float64) / 65536.0
+    return np.stack([np.cos(a), np.sin(a)], axis=-1)
+
+
+def test_init_and_state_roundtrip():
+    g = xy.Graph.levy(16, 6, 3.5, 1)
+    b = xy.Batch([g, g], [1.0, 2.0, 3.0], precision="fix16", seeds=[1, 2])
+    st, sot, sw = b.get_state()
+    assert sw == 0 and st[0].shape == (3, 256) and st[0].dtype == np.uint16
+    assert not np.array_equal(st[0], st[1])
+    # uniform 16-bit angles: mean ~ 32767.5
+    allv = np.concatenate([s.ravel() for s in st]).astype(float)
+    assert abs(allv.mean() - 32767.5) < 5 * 18918 / np.sqrt(allv.size)
+    new = [np.arange(3 * 256, dtype=np.uint16).reshape(3, 256) * 7, st[1]]
+    b.set_state(new, [[2, 0, 1], [0, 1, 2]], sweep=11)
+    st2, sot2, sw2 = b.get_state()
+    assert sw2 == 11 and np.array_equal(st2[0], new[0]) and np.array_equal(sot2[0], [2, 0, 1])
+
+
+def test_measure_matches_oracle_on_same_state():
+    g = xy.Graph.levy(16, 6, 3.5, 1)
+    T = np.array([0.8, 1.2, 1.6, 2.0])
+    b = xy.Batch([g], T, precision="fix16", seeds=[1])
+    b.sweep(9, pt_every=1, meas_every=0)
+    o = b.measure().cpu().numpy()[0]
+    st, sot, sw = b.get_state()
+    e, _ = oracle.levy_graph(16, 6, 3.5, 1)
+    col, _ = oracle.slo_colour(256, e)
+    sim = oracle.Sim(256, e, col, 16, T, 1)
+    sim.set_state(_unit(st[0]), sot[0], sw)
+    ref = sim.measure()
+    assert np.allclose(o[:, :7], ref[:, :7], rtol=1e-11, atol=1e-12)
+
+
+def _fused_records_match_measure(precision):
+    g = xy.Graph.levy(32, 6, 2.5, 3)
+    b = xy.Batch([g], workloads.linear_ladder(1.0, 2.5, 5), precision=precision, seeds=[3], max_records=4)
+    b.sweep(8, pt_every=0, meas_every=2)
+    rec = b.records().cpu().numpy()
+    last = b.measure().cpu().numpy()
+    assert rec.shape[0] == 4
+    assert np.allclose(rec[-1], last, rtol=1e-12, atol=1e-12)
+
+
+def test_fused_measurement_equals_standalone():
+    _fused_records_match_measure("fix16")
+    _fused_records_match_measure("fp64")
+
+
+def _tiny_exact(name, beta):
+    t = special.iv(1, beta) / special.iv(0, beta)
+    if name == "link":
+        return -t
+    k = np.arange(-40, 41)
+    f = special.iv(k, beta)
+    f1 = 0.5 * (special.iv(k - 1, beta) + special.iv(k + 1, beta))
+    n = {"triangle": 3, "cycle4": 4}[name]
+    return -np.sum(n * f ** (n - 1) * f1) / np.sum(f ** n)
+
+
+@pytest.mark.parametrize("name,n,edges", [("link", 2, [(0, 1)]), ("triangle", 3, [(0, 1), (1, 2), (2, 0)]),
+                                          ("cycle4", 4, [(0, 1), (1, 2), (2, 3), (3, 0)])])
+def test_tiny_graphs_exact_energy(name, n, edges):
+    T = np.array([0.8, 1.2, 1.6, 2.0])
+    n_samples = 256
+    g = xy.Graph.from_edges(n, edges)
+    b = xy.Batch([g] * n_samples, T, precision="fix16", seeds=np.arange(n_samples) + 100,
+                 max_records=1000)
+    b.sweep(200, pt_every=1, meas_every=0)
+    b.sweep(4000, pt_every=1, meas_every=4)
+    rec = b.records().cpu().numpy()            # [1000, samples, T, 8]
+    for k, t in enumerate(T):
+        per_sample = rec[:, :, k, 0].mean(axis=0)   # independent chains
+        m, err = per_sample.mean(), per_sample.std(ddof=1) / np.sqrt(n_samples)
+        assert abs(m - _tiny_exact(name, 1 / t)) < 4 * err, (name, t, m, _tiny_exact(name, 1 / t), err)
+
+
+def test_l16_observables_match_oracle():
+    """fix16 on 128 independent chains of the L=16 graph vs the FP64 oracle (1e4 sweeps)."""
+    wl = workloads.plain_fp64_l16()
+    s = wl.samples[0]
+    e, _ = oracle.levy_graph(s.L, s.z, s.rho, s.seed)
+    col, _ = oracle.slo_colour(256, e)
+    sim = oracle.Sim(256, e, col, s.L, wl.T, s.seed)
+    sim.init_random()
+    orec = sim.run(wl.n_sweeps, n_or=5, pt_every=0, meas_every=1)["records"][wl.n_sweeps // 2:]
+
+    n_chains = 128
+    g = xy.Graph.levy(s.L, s.z, s.rho, s.seed)
+    b = xy.Batch([g] * n_chains, wl.T, precision="fix16", seeds=np.arange(n_chains) + 1000, max_records=500)
+    b.sweep(1000, pt_every=0, meas_every=0)
+    b.sweep(4000, pt_every=0, meas_every=8)
+    grec = b.records().cpu().numpy()
+    zs = []
+    for q in (0, 1, 2, 3, 4):
+        for k in range(4):
+            mo, eo = batch_mean_err(orec[:, k, q], 25)
+            per = grec[:, :, k, q].mean(axis=0)
+            mg, eg = per.mean(), per.std(ddof=1) / np.sqrt(n_chains)
+            zs.append((mg - mo) / np.hypot(eo, eg))
+    zs = np.array(zs)
+    assert np.max(np.abs(zs)) < 4.0, zs
+    assert np.mean(np.abs(zs) > 3) <= 0.05, zs
+
+
+def test_pt_batch_matches_fp64_gpu():
+    """64 samples of L=32 with PT: fix16 vs the FP64 GPU path, disorder-averaged per T."""
+    T = workloads.linear_ladder(1.0, 2.5, 8)
+    graphs = [xy.Graph.levy(32, 6, 3.5, s) for s in range(64)]
+    res = {}
+    for prec in ("fp64", "fix16"):
+        b = xy.Batch(graphs, T, precision=prec, seeds=np.arange(64), max_records=200)
+        b.sweep(400, pt_every=1, meas_every=0)
+        b.sweep(1600, pt_every=1, meas_every=8)
+        rec = b.records().cpu().numpy()
+        res[prec] = rec.mean(axis=0)           # [samples, T, 8] thermal averages
+        _, acc, tries = b.counters()
+        assert tries.sum() > 0 and acc.sum() > 0
+    zs = []
+    for q in (0, 1, 3):
+        for k in range(len(T)):
+            d = res["fix16"][:, k, q] - res["fp64"][:, k, q]   # paired by sample (same graph)
+            zs.append(d.mean() / (d.std(ddof=1) / np.sqrt(len(d))))
+    zs = np.array(zs)
+    assert np.max(np.abs(zs)) < 4.0, zs
+
+
+def test_graph_replay_equals_direct_launches():
+    """A captured chunk of 8 sweeps replayed 4 times, with eager work and a
+    synchronisation between replays, equals direct launches after every replay."""
+    g = [xy.Graph.levy(32, 6, 3.5, s) for s in range(4)]
+    T = workloads.linear_ladder(1.0, 2.5, 6)
+    eager = xy.Batch(g, T, precision="fix16", seeds=np.arange(4), max_records=8)
+    graph = xy.Batch(g, T, precision="fix16", seeds=np.arange(4), max_records=8, stream=torch.cuda.Stream())
+    graph.use_graph(8)
+    for rep in range(4):
+        eager.sweep(8, pt_every=1, meas_every=4)
+        graph.sweep(8, pt_every=1, meas_every=4)
+        a, b_ = eager.get_state(), graph.get_state()
+        assert a[2] == b_[2] == 8 * (rep + 1)
+        assert all(np.array_equal(x, y) for x, y in zip(a[0], b_[0])), rep
+        assert np.array_equal(a[1], b_[1]), rep
+        assert np.array_equal(eager.records().cpu().numpy(), graph.records().cpu().numpy()), rep
+    graph.sweep(3, pt_every=1, meas_every=4)      # a remainder that is not a whole chunk
+    eager.sweep(3, pt_every=1, meas_every=4)
+    assert all(np.array_equal(x, y) for x, y in zip(eager.get_state()[0], graph.get_state()[0]))

@@ -1,0 +1,147 @@
+"""GPU parity of the FP64 plain path against the oracle (through the C ABI).
+
+The FP64 path evaluates the same correctly rounded operations in the same
+order as the oracle, so the bar is exact: bit-identical spins, identical
+Metropolis and parallel-tempering decisions, and E/N within 1e-12 relative
+(the energy sums are reduced in a different order).  Cases: the L=16 plain
+workload (4 T, no PT) for 100 sweeps, the same with PT, a batch of uneven
+samples, tiny graphs, and sampled samples of the full 64 x L=256 x 24 T shape.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1211_3991_amd as xy  # noqa: E402
+
+
+def _oracle_sim(L, z, rho, seed, T, graph=None):
+    if graph is None:
+        e, _ = oracle.levy_graph(L, z, rho, seed)
+        n = L * L
+    else:
+        n, e = graph
+        e = np.asarray(e, dtype=np.int32)
+    col, _ = oracle.slo_colour(n, e)
+    sim = oracle.Sim(n, e, col, L, np.asarray(T, float), seed)
+    sim.init_random()
+    return sim
+
+
+def _bits(a):
+    return np.ascontiguousarray(a).view(np.uint64)
+
+
+def test_initial_state_bitwise():
+    wl = workloads.plain_fp64_l16()
+    s = wl.samples[0]
+    g = xy.Graph.levy(s.L, s.z, s.rho, s.seed)
+    b = xy.Batch([g], wl.T, precision="fp64", seeds=[s.seed])
+    st, sot, sw = b.get_state()
+    sim = _oracle_sim(s.L, s.z, s.rho, s.seed, wl.T)
+    ref, _, _ = sim.get_state()
+    assert sw == 0 and np.array_equal(sot[0], np.arange(4))
+    assert np.array_equal(_bits(st[0]), _bits(ref))
+
+
+@pytest.mark.parametrize("pt_every", [0, 1])
+def test_l16_100_sweeps_exact(pt_every):
+    wl = workloads.plain_fp64_l16()
+    s = wl.samples[0]
+    n_sw = 100
+    g = xy.Graph.levy(s.L, s.z, s.rho, s.seed)
+    b = xy.Batch([g], wl.T, precision="fp64", seeds=[s.seed], max_records=n_sw)
+    log = b.decision_log(n_sw)
+    b.sweep(n_sw, n_or=5, pt_every=pt_every, meas_every=1)
+    torch.cuda.synchronize()
+    st, sot, sw = b.get_state()
+    rec = b.records().cpu().numpy()[:, 0]
+    gl = log.cpu().numpy()[:, 0]
+    nrec, acc, tries = b.counters()
+
+    sim = _oracle_sim(s.L, s.z, s.rho, s.seed, wl.T)
+    out = sim.run(n_sw, n_or=5, pt_every=pt_every, meas_every=1, met_log=True, pt_log=True)
+    ref, ref_sot, ref_sw = sim.get_state()
+    assert sw == ref_sw == n_sw and nrec == n_sw
+    first_bad = np.nonzero(np.any(gl != out["met_log"], axis=(1, 2)))[0]
+    assert first_bad.size == 0, f"first differing Metropolis decision in sweep {first_bad[:1]}"
+    assert np.array_equal(sot[0], ref_sot)
+    assert np.array_equal(_bits(st[0]), _bits(ref))
+    E, Eref = rec[:, :, 0], out["records"][:, :, 0]
+    assert np.all(np.abs(E - Eref) <= 1e-12 * np.abs(Eref))
+    assert np.allclose(rec[:, :, 1:5], out["records"][:, :, 1:5], rtol=1e-11, atol=1e-14)
+    if pt_every:
+        oacc, otry = sim.pt_counts()
+        assert np.array_equal(tries[0].astype(np.int64), otry) and np.array_equal(acc[0].astype(np.int64), oacc)
+        assert otry.sum() == 100 * 3 // 2
+
+
+def test_uneven_batch_exact():
+    """Three samples of different L and rho in one batch, each against its own oracle run."""
+    specs = [(16, 2.5, 4), (32, 4.5, 9), (8, 3.5, 2)]
+    T = workloads.linear_ladder(0.8, 3.0, 6)
+    graphs = [xy.Graph.levy(L, 6, rho, sd) for L, rho, sd in specs]
+    b = xy.Batch(graphs, T, precision="fp64", seeds=[sd for _, _, sd in specs])
+    b.sweep(12, n_or=5, pt_every=1, meas_every=0)
+    st, sot, sw = b.get_state()
+    for k, (L, rho, sd) in enumerate(specs):
+        sim = _oracle_sim(L, 6, rho, sd, T)
+        sim.run(12, n_or=5, pt_every=1, meas_every=0)
+        ref, ref_sot, _ = sim.get_state()
+        assert np.array_equal(sot[k], ref_sot)
+        assert np.array_equal(_bits(st[k]), _bits(ref)), f"sample {k}"
+
+
+def test_tiny_graphs_and_isolated_site_exact():
+    cases = {"link": (2, [(0, 1)]), "triangle": (3, [(0, 1), (1, 2), (2, 0)]),
+             "K4": (4, [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]),
+             "isolated": (5, [(0, 1), (1, 2)])}
+    T = np.array([0.8, 1.6])
+    for name, (n, e) in cases.items():
+        g = xy.Graph.from_edges(n, e)
+        b = xy.Batch([g], T, precision="fp64", seeds=[5])
+        b.sweep(50, n_or=5, pt_every=1, meas_every=0)
+        st, sot, _ = b.get_state()
+        sim = _oracle_sim(n, 0, 0, 5, T, graph=(n, e))
+        sim.run(50, n_or=5, pt_every=1, meas_every=0)
+        ref, ref_sot, _ = sim.get_state()
+        assert np.array_equal(sot[0], ref_sot), name
+        assert np.array_equal(_bits(st[0]), _bits(ref)), name
+
+
+def test_measure_matches_oracle_on_same_state():
+    wl = workloads.plain_fp64_l16()
+    s = wl.samples[0]
+    g = xy.Graph.levy(s.L, s.z, s.rho, s.seed)
+    b = xy.Batch([g], wl.T, precision="fp64", seeds=[s.seed])
+    b.sweep(7, pt_every=1, meas_every=0)
+    o = b.measure().cpu().numpy()[0]
+    st, sot, sw = b.get_state()
+    sim = _oracle_sim(s.L, s.z, s.rho, s.seed, wl.T)
+    sim.set_state(st[0], sot[0], sw)
+    ref = sim.measure()
+    assert np.allclose(o[:, :7], ref[:, :7], rtol=1e-12, atol=1e-13)
+
+
+def test_full_shape_sampled_exact():
+    """64 x L=256 x 24 T, PT every sweep: samples 0 and 37 vs the oracle, 2 sweeps."""
+    wl = workloads.headline_l256()
+    graphs = [xy.Graph.levy(s.L, s.z, s.rho, s.seed) for s in wl.samples]
+    b = xy.Batch(graphs, wl.T, precision="fp64", seeds=[s.seed for s in wl.samples])
+    b.sweep(2, n_or=5, pt_every=1, meas_every=0)
+    st, sot, sw = b.get_state()
+    assert sw == 2
+    for k in (0, 37):
+        s = wl.samples[k]
+        sim = _oracle_sim(s.L, s.z, s.rho, s.seed, wl.T)
+        sim.run(2, n_or=5, pt_every=1, meas_every=0)
+        ref, ref_sot, _ = sim.get_state()
+        assert np.array_equal(sot[k], ref_sot)
+        assert np.array_equal(_bits(st[k]), _bits(ref)), f"sample {k}"

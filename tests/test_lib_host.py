@@ -1,0 +1,86 @@
+"""Host-side tests of the library (no GPU): the C ABI loads and exports every
+symbol its header declares; the library's graph path (Levy sampling, SLO
+colouring) is bit-identical to the oracle's; the colour-sorted CSR is a
+faithful relabelling of the edge list; argument errors are reported."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1211_3991_amd as xy
+from paper_1211_3991_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_every_declared_symbol_is_exported():
+    hdr = open(os.path.join(ROOT, "include", "xy_levy.h")).read()
+    declared = set(re.findall(r"^\s*(?:xy_status|void|const char \*)\s*(xy_\w+)\s*\(", hdr, re.M))
+    assert len(declared) >= 17
+    assert declared == set(_lib.EXPORTS)
+    for name in declared:
+        assert hasattr(_lib.raw(), name), name
+
+
+@pytest.mark.parametrize("L,z,rho,seed", [(16, 6, 3.5, 1), (128, 6, 3.5, 0), (128, 6, 3.5, 63), (256, 6, 3.5, 7),
+                                          (32, 6, 2.5, 2), (64, 6, 4.5, 33), (512, 6, 2.5, 0), (16, 4, 60.0, 3),
+                                          (32, 6, 0.0, 5)])
+def test_graph_bitwise_equal_to_oracle(L, z, rho, seed):
+    g = xy.Graph.levy(L, z, rho, seed)
+    ex = g.export()
+    e, att = oracle.levy_graph(L, z, rho, seed)
+    assert g.attempts == att
+    assert np.array_equal(ex["edges"], e)
+    col, q = oracle.slo_colour(L * L, e)
+    assert g.n_colours == q
+    assert np.array_equal(ex["colour"], col)
+
+
+def test_colour_sorted_csr_is_a_relabelling():
+    L = 64
+    n = L * L
+    g = xy.Graph.levy(L, 6, 3.5, 11)
+    ex = g.export()
+    perm, off, rp, col, colour = ex["perm"], ex["colour_off"], ex["row_ptr"], ex["col"], ex["colour"]
+    assert sorted(perm) == list(range(n))
+    # colour-major: class c occupies [off[c], off[c+1]) in lattice order
+    for c in range(g.n_colours):
+        cls = perm[off[c]:off[c + 1]]
+        assert np.all(colour[cls] == c) and np.all(np.diff(cls) > 0)
+    inv = np.empty(n, np.int64)
+    inv[perm] = np.arange(n)
+    got = set()
+    for k in range(n):
+        row = col[rp[k]:rp[k + 1]]
+        assert np.all(np.diff(row) > 0)                       # ascending, no repeats
+        for j in row:
+            got.add((min(perm[k], perm[j]), max(perm[k], perm[j])))
+    want = {(min(a, b), max(a, b)) for a, b in ex["edges"]}
+    assert got == want and rp[-1] == 2 * g.m
+    # same-colour sites are never linked (the colouring is proper)
+    cm = np.repeat(np.arange(g.n_colours), np.diff(off))
+    src = np.repeat(np.arange(n), np.diff(rp))
+    assert np.all(cm[src] != cm[col])
+
+
+def test_from_edges_and_errors():
+    g = xy.Graph.from_edges(4, [(0, 1), (1, 2), (2, 3), (3, 0)])
+    assert (g.n, g.m, g.n_colours) == (4, 4, 2)
+    with pytest.raises(xy.XYError, match="EINVAL"):
+        xy.Graph.from_edges(3, [(0, 1), (1, 0)])
+    with pytest.raises(xy.XYError, match="EINVAL"):
+        xy.Graph.from_edges(3, [(0, 0)])
+    with pytest.raises(xy.XYError, match="EINVAL"):
+        xy.Graph.from_edges(3, [(0, 5)])
+    with pytest.raises(xy.XYError, match="EINVAL"):
+        xy.Graph.levy(15, 6, 3.5, 0)          # odd L
+    with pytest.raises(xy.XYError, match="EINVAL"):
+        xy.Graph.levy(16, 6, -1.0, 0)
+    with pytest.raises(xy.XYError, match="EINVAL"):
+        xy.Graph.levy(4, 15, 1.0, 0)          # z >= N - 1
+    with pytest.raises(xy.XYError, match="EINVAL"):
+        xy.Graph.levy(2, 3, 1.0, 0)           # z >= N - 1 with N = 4
+    with pytest.raises(xy.XYError, match="EINVAL"):
+        xy.Graph.from_edges(2, [(0, 1)], L=4, coords=[(0, 0), (4, 0)])   # coordinate outside [0, L)
