@@ -115,7 +115,7 @@ typedef struct {
 } xy_sizes;
 
 /* Device bytes needed for a batch.  n_T in [1, 256]; precision XY_FP64 or
- * XY_FIX16 (fix16 needs L to divide 65536); max_records >= 0. */
+ * XY_FIX16; max_records >= 0. */
 xy_status xy_batch_sizes(const xy_graph *const *g, int n_graphs, int n_T, int precision,
                          int max_records, xy_sizes *out);
 

@@ -71,8 +71,6 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
     for (int s = 0; s < G; ++s) {
         if (!g[s]) return set_error(XY_EINVAL, "batch: NULL graph");
         const xy_graph &gr = *g[s];
-        if (precision == XY_FIX16 && (65536 % gr.L) != 0)
-            return set_error(XY_EUNSUP, "batch: fix16 needs L to divide 65536");
         SampleDesc &d = p.desc[s];
         d.n = gr.n; d.Q = gr.Q; d.L = gr.L; d.max_deg = gr.max_deg;
         d.row_ptr = (int64_t)n_i32; n_i32 += gr.n + 1;
