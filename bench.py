@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--precision", default="fix16", choices=["fix16", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=8, help="sweeps of the FP64 plain comparison (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle time budget (0 = skip)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the samples are independent and a multi-GPU "
@@ -108,8 +110,18 @@ def main():
         sys.exit(2)
 
     import torch
-    import paper_1211_3991_amd as xy
     assert torch.cuda.is_available(), "bench.py needs the GPU"
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n, "copies": 5}))
+        return
+    import paper_1211_3991_amd as xy
 
     wl = workloads.ALL[args.workload]()
     t = time.perf_counter()

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <new>
+#include <numeric>
 #include <set>
 #include <unordered_set>
 #include <utility>
@@ -87,6 +88,8 @@ xy_status finish_graph(xy_graph &g)
     if (n == 0) Q = 0;
     if (Q > kMaxColours)
         return set_error(XY_EUNSUP, "graph needs more than 31 colours");
+    if (g.max_deg > 255)
+        return set_error(XY_EUNSUP, "graph has a site of degree above 255");
     g.Q = Q;
 
     // colour-major renumbering (counting sort, stable in lattice index)
@@ -113,6 +116,59 @@ xy_status finish_graph(xy_graph &g)
         std::sort(g.col.data() + g.row_ptr[k], g.col.data() + g.row_ptr[k + 1]);
     }
     return XY_OK;
+}
+
+Sell build_sell(const xy_graph &g)
+{
+    Sell S;
+    const int n = g.n, Q = g.Q;
+    S.order.resize(n);
+    S.deg.resize(n);
+    S.chunk_off.assign(Q + 1, 0);
+    std::vector<int32_t> inv(n);
+    for (int c = 0; c < Q; ++c) {
+        const int c0 = g.colour_off[c], c1 = g.colour_off[c + 1];
+        std::iota(S.order.begin() + c0, S.order.begin() + c1, c0);
+        std::stable_sort(S.order.begin() + c0, S.order.begin() + c1, [&](int a, int b) {
+            return g.row_ptr[a + 1] - g.row_ptr[a] > g.row_ptr[b + 1] - g.row_ptr[b];
+        });
+        S.chunk_off[c + 1] = S.chunk_off[c] + (c1 - c0 + 63) / 64;
+    }
+    for (int k = 0; k < n; ++k) {
+        inv[S.order[k]] = k;
+        S.deg[k] = (uint8_t)(g.row_ptr[S.order[k] + 1] - g.row_ptr[S.order[k]]);
+    }
+    const int n_chunks = S.chunk_off[Q];
+    S.chunk_ptr.assign(n_chunks + 1, 0);
+    S.chunk_w.assign(n_chunks, 0);
+    for (int c = 0; c < Q; ++c)
+        for (int ch = S.chunk_off[c]; ch < S.chunk_off[c + 1]; ++ch) {
+            const int first = g.colour_off[c] + (ch - S.chunk_off[c]) * 64;
+            const int last = std::min(first + 64, g.colour_off[c + 1]);
+            int w = 0, wmin = 255;
+            for (int k = first; k < last; ++k) {
+                w = std::max(w, (int)S.deg[k]);
+                wmin = std::min(wmin, (int)S.deg[k]);
+            }
+            S.chunk_ptr[ch + 1] = S.chunk_ptr[ch] + 64 * w;
+            S.chunk_w[ch] = wmin | (w << 8);
+        }
+    // 8 trailing padding rows let a kernel read 8 column rows past any chunk
+    S.col.assign((size_t)S.chunk_ptr[n_chunks] + 8 * 64, 0);
+    std::vector<int32_t> row;
+    for (int c = 0; c < Q; ++c)
+        for (int ch = S.chunk_off[c]; ch < S.chunk_off[c + 1]; ++ch) {
+            const int first = g.colour_off[c] + (ch - S.chunk_off[c]) * 64;
+            const int last = std::min(first + 64, g.colour_off[c + 1]);
+            for (int k = first; k < last; ++k) {
+                const int cm = S.order[k];
+                row.assign(g.col.begin() + g.row_ptr[cm], g.col.begin() + g.row_ptr[cm + 1]);
+                for (int32_t &j : row) j = inv[j];
+                std::sort(row.begin(), row.end());
+                for (size_t a = 0; a < row.size(); ++a) S.col[S.chunk_ptr[ch] + a * 64 + (k - first)] = row[a];
+            }
+        }
+    return S;
 }
 
 }  // namespace xy

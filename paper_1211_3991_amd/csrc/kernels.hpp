@@ -13,8 +13,11 @@ struct DevBatch {
     const int32_t *i32;       // row_ptr / col / perm pool
     const uint32_t *u32;      // packed coordinates pool
     const double2 *f64;       // (cos, sin)(2 pi x / L) pool
+    const uint16_t *u16;      // fix16 sliced-ELL columns (graphs with at most 65536 sites)
+    const uint8_t *u8;        // fix16 degrees
     const float2 *tab32;      // [512]: (cos, sin)(2 pi * 256a / 2^16) then (cos, sin)(2 pi * b / 2^16)
-    const double2 *tab64;     // [512]: same angles in FP64
+    const float2 *tab2k;      // [2048]: (cos, sin)(2 pi * 32a / 2^16)
+    const double2 *tab64;     // [512]: same angles as tab32 in FP64
     void *state;              // fp64: double2 [site][slot]; fix16: uint16 [slot][site_pad]
     Ctl *ctl;
     const double *beta;       // [G][R] by temperature index
@@ -22,9 +25,12 @@ struct DevBatch {
     int32_t *T_of_slot;       // [G][R]
     double *E_slot;           // [G][R]
     double *obs_slot;         // [G][R][XY_NOBS]
+    double *partial;          // fp64: [G][64][R][11] block partial sums of the observables
     unsigned long long *pt_acc, *pt_try;  // [G][R]
     double *records;          // [max_records][G][R][XY_NOBS]
     int G, R, max_records, max_n;
+    int idx16;                // fix16 columns are uint16 (else int32)
+    int trig;                 // fix16 (cos, sin) evaluation: 0 two-level table, 1 2048-table + rotation, 2 hardware
     uint8_t *log;             // Metropolis decision log (fp64) or NULL
     int log_sweeps;
 };
@@ -40,6 +46,6 @@ hipError_t launch_fix16_init(const DevBatch &b, int max_n, hipStream_t s);
 hipError_t launch_fix16_sweep(const DevBatch &b, const Item *items, int n_items, bool lds,
                               int n_or, int measure, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fix16_observe(const DevBatch &b, double *out_by_T, hipStream_t s);
-size_t fix16_lds_bytes(int n_pad, int L);
+size_t fix16_lds_bytes(int n_pad, int trig);
 
 }  // namespace xy

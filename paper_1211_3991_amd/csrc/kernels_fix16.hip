@@ -1,14 +1,18 @@
 // Fixed-point path: each spin is an angle theta = k * 2pi / 2^16 stored as
 // uint16 (an exact representation of the 2^16-state clock model), local
-// fields are accumulated in FP32 from (cos, sin) tables held in LDS, and
-// energies / observables are accumulated in FP64.
+// fields are accumulated in FP32, and energies / observables in FP64.
 //
 // One workgroup runs one whole sweep of one (sample, temperature slot): the
 // replica's angles are staged in LDS (when they fit) and the colour phases of
 // App. B become workgroup barriers, so a sweep needs no grid-wide
-// synchronisation and no host round trip.  The CSR is streamed from L2; the
-// workgroups of one sample are placed on one XCD by the item order the host
-// builds, so they share its CSR in that XCD's L2.
+// synchronisation and no host round trip.  The graph is read in sliced-ELL
+// form (64-site chunks, columns stored [k][lane], sites degree-sorted inside
+// each colour class): a wave's k-th neighbour indices are one contiguous
+// load, and all indices of a site are in flight before the first is used.
+// Each lane updates four sites of one colour at a time (four chunks), which
+// overlaps their latencies and lets one Philox4x32-10 call supply the random
+// words of all four updates.  The workgroups of one sample are placed on one
+// XCD by the item order the host builds, so they share its graph in that L2.
 //
 // Over-relaxation on the clock model: theta' = (q - theta) mod 2^16 with
 // q = round(2 phi_h * 2^16 / 2pi), phi_h the angle of the local field.  The
@@ -23,19 +27,92 @@ namespace xy {
 namespace {
 
 constexpr int kSweepBlock = 1024;
+constexpr int kWaves = kSweepBlock / 64;
+constexpr int kGroup = 4;      // sites (chunks) per lane at a time
+constexpr int kUnroll = 8;     // neighbour indices loaded up front per site
 constexpr int kObsBlock = 256;
-constexpr int kNRed = 11;   // E, m_x, m_y, 4 Fourier sums along x, 4 along y
+constexpr int kNRed = 11;      // E, m_x, m_y, 4 Fourier sums along x, 4 along y
 constexpr float kTwoPhiScale = 20860.756700940907f;   // 2^16 / pi: 2*phi in angle units
+constexpr float kAngle = 9.587379924285257e-05f;      // 2 pi / 2^16
 
-__device__ __forceinline__ float2 unit32(uint32_t th, const float2 *hi, const float2 *lo)
+// (cos, sin) of a 16-bit angle in FP32.  The three forms are different
+// deterministic functions of the angle (each within a few ulp of the exact
+// value); whichever is compiled in defines the energy the sweep samples.
+//   0: two-level table, (cos, sin)(256 a) rotated by (cos, sin)(b), 2 x 256 entries
+//   1: 2048-entry table of (cos, sin)(32 a), rotated by the small angle of the
+//      low 5 bits, delta <= 3.1e-3, with cos = 1 - delta^2/2 and sin = delta
+//      (truncation errors 4e-12 and 5e-9)
+//   2: the hardware sine/cosine of theta / 2^16 revolutions (no table)
+template <int kTrig> struct Trig;
+
+template <> struct Trig<0> {
+    static constexpr size_t kBytes = 512 * 8;
+    static __device__ __forceinline__ void load(float2 *t, const DevBatch &b, int tid)
+    {
+        for (int k = tid; k < 512; k += kSweepBlock) t[k] = b.tab32[k];
+    }
+    static __device__ __forceinline__ float2 unit(uint32_t th, const float2 *t)
+    {
+        const float2 a = t[th >> 8], c = t[256 + (th & 255u)];
+        return make_float2(a.x * c.x - a.y * c.y, a.y * c.x + a.x * c.y);
+    }
+};
+
+template <> struct Trig<1> {
+    static constexpr size_t kBytes = 2048 * 8;
+    static __device__ __forceinline__ void load(float2 *t, const DevBatch &b, int tid)
+    {
+        for (int k = tid; k < 2048; k += kSweepBlock) t[k] = b.tab2k[k];
+    }
+    static __device__ __forceinline__ float2 unit(uint32_t th, const float2 *t)
+    {
+        const float2 a = t[th >> 5];
+        const float d = (float)(th & 31u) * kAngle;
+        const float c = 1.0f - 0.5f * d * d;
+        return make_float2(a.x * c - a.y * d, a.y * c + a.x * d);
+    }
+};
+
+template <> struct Trig<2> {
+    static constexpr size_t kBytes = 0;
+    static __device__ __forceinline__ void load(float2 *, const DevBatch &, int) {}
+    static __device__ __forceinline__ float2 unit(uint32_t th, const float2 *)
+    {
+        // 1 + theta / 2^16 revolutions, built from the bits (exact); one whole
+        // turn more than theta, which sine and cosine do not see
+        const float r = __uint_as_float(0x3F800000u | (th << 7));
+        return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
+    }
+};
+
+// 2 phi in units of 2pi/2^16, rounded, for phi = atan2(hy, hx): the axis of
+// the over-relaxation reflection.  atan on [0, 1] by an odd polynomial of
+// degree 11, least-squares fitted on 4000 Chebyshev nodes (|error| < 2e-6
+// rad in FP32), then the octant is restored.
+// The accuracy only affects the acceptance rate of the reflection, not the
+// detailed balance (the reflection is accepted by a Metropolis test).
+__device__ __forceinline__ uint32_t field_axis2(float hx, float hy)
 {
-    const float2 a = hi[th >> 8], c = lo[th & 255u];
-    return make_float2(a.x * c.x - a.y * c.y, a.y * c.x + a.x * c.y);
+    const float ax = fabsf(hx), ay = fabsf(hy);
+    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+    const float t = mx > 0.f ? mn * __builtin_amdgcn_rcpf(mx) : 0.f;
+    const float t2 = t * t;
+    float p = -0.011770499870181084f;
+    p = fmaf(p, t2, 0.05282348766922951f);
+    p = fmaf(p, t2, -0.11665111780166626f);
+    p = fmaf(p, t2, 0.19367031753063202f);
+    p = fmaf(p, t2, -0.33265548944473267f);
+    p = fmaf(p, t2, 0.9999798536300659f);
+    float a = p * t;                                   // atan(t), t in [0, 1]
+    a = ay > ax ? 1.5707963267948966f - a : a;
+    a = hx < 0.f ? 3.141592653589793f - a : a;
+    a = hy < 0.f ? -a : a;
+    return (uint32_t)__float2int_rn(a * kTwoPhiScale);
 }
 
-__device__ __forceinline__ double2 unit64(uint32_t th, const double2 *hi, const double2 *lo)
+__device__ __forceinline__ double2 unit64(uint32_t th, const double2 *t64)
 {
-    const double2 a = hi[th >> 8], c = lo[th & 255u];
+    const double2 a = t64[th >> 8], c = t64[256 + (th & 255u)];
     return make_double2(a.x * c.x - a.y * c.y, a.y * c.x + a.x * c.y);
 }
 
@@ -57,30 +134,41 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *scratch)
 
 // Observables of Sec. 3 from the angles `ang` of one (sample, slot), FP64:
 // E = -sum_links cos(theta_i - theta_j) (each link once, at its higher
-// colour-major endpoint), m = (1/N) sum S_j, F_a = |sum_j S_j e^{i 2pi a_j/L}|^2/N.
+// endpoint), m = (1/N) sum S_j, F_a = |sum_j S_j e^{i 2pi a_j/L}|^2/N.
+template <typename Idx>
 __device__ __forceinline__ void observe(const DevBatch &b, const SampleDesc &d, const uint16_t *ang,
-                                        const double2 *dhi, const double2 *dlo, const double2 *trig,
                                         double *scratch, double *dst)
 {
-    const int32_t *row = b.i32 + d.row_ptr;
-    const int32_t *col = b.i32 + d.col;
+    const int32_t *cptr = b.i32 + d.sell_ptr;
+    const Idx *col = reinterpret_cast<const Idx *>(sizeof(Idx) == 2 ? (const void *)b.u16 : (const void *)b.i32) + d.sell_col;
+    const uint8_t *deg = b.u8 + d.deg;
     const uint32_t *xy = b.u32 + d.coord;
+    const double2 *trig = b.f64 + d.trig;
+    const double2 *t64 = b.tab64;
     double v[kNRed] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int i = threadIdx.x; i < d.n; i += blockDim.x) {
-        const double2 si = unit64(ang[i], dhi, dlo);
-        double e = 0.0;
-        for (int a = row[i]; a < row[i + 1]; ++a) {
-            const int j = col[a];
-            if (j >= i) break;
-            const double2 sj = unit64(ang[j], dhi, dlo);
-            e += si.x * sj.x + si.y * sj.y;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int c = 0; c < d.Q; ++c) {
+        const int c0 = d.colour_off[c], c1 = d.colour_off[c + 1], ch0 = d.chunk_off[c];
+        for (int ch = wave; ch < d.chunk_off[c + 1] - ch0; ch += nw) {
+            const int i = c0 + ch * 64 + lane;
+            if (i >= c1) continue;
+            const double2 si = unit64(ang[i], t64);
+            const int base = cptr[ch0 + ch], dg = deg[i];
+            double e = 0.0;
+            for (int k = 0; k < dg; ++k) {
+                const int j = (int)col[base + k * 64 + lane];
+                if (j < i) {
+                    const double2 sj = unit64(ang[j], t64);
+                    e += si.x * sj.x + si.y * sj.y;
+                }
+            }
+            v[0] -= e;
+            const uint32_t p = xy[i];
+            const double2 ex = trig[p & 0xFFFFu], ey = trig[p >> 16];
+            v[1] += si.x; v[2] += si.y;
+            v[3] += si.x * ex.x; v[4] += si.x * ex.y; v[5] += si.y * ex.x; v[6] += si.y * ex.y;
+            v[7] += si.x * ey.x; v[8] += si.x * ey.y; v[9] += si.y * ey.x; v[10] += si.y * ey.y;
         }
-        v[0] -= e;
-        const uint32_t p = xy[i];
-        const double2 ex = trig[p & 0xFFFFu], ey = trig[p >> 16];
-        v[1] += si.x; v[2] += si.y;
-        v[3] += si.x * ex.x; v[4] += si.x * ex.y; v[5] += si.y * ex.x; v[6] += si.y * ex.y;
-        v[7] += si.x * ey.x; v[8] += si.x * ey.y; v[9] += si.y * ey.x; v[10] += si.y * ey.y;
     }
     block_sum<kNRed>(v, scratch);
     if (threadIdx.x != 0) return;
@@ -94,12 +182,116 @@ __device__ __forceinline__ void observe(const DevBatch &b, const SampleDesc &d, 
     dst[5] = mx; dst[6] = my; dst[7] = 0.0;
 }
 
-// LDS map: [float2 hi 256][float2 lo 256][double2 hi 256][double2 lo 256]
-//          [double scratch 16*kNRed][double2 trig L][uint16 angles n_pad (LDS variant)]
-constexpr size_t kOffT32 = 0, kOffT64 = 4096, kOffRed = 12288;
-constexpr size_t kOffTrig = kOffRed + 16 * kNRed * 8;   // 13696, multiple of 16
+// One colour phase of one sub-sweep for this workgroup's replica: every site
+// of colour class [c0, c1) is updated once (Metropolis when sub == 0, else
+// over-relaxation).  Returns, when kLast, the energy of the links from the
+// updated sites to lower colours (their final values in the last sub-sweep).
+template <bool kLast, typename Idx, int kTrig>
+__device__ __forceinline__ double colour_phase(const SampleDesc &d, uint16_t *ang, const float2 *tab,
+                                               const int32_t *cptr, const int32_t *cw, const Idx *col,
+                                               const uint8_t *deg, int c0, int c1, int ch0, int nch, int wave,
+                                               int lane, uint32_t sweep, int slot, int sub, float beta)
+{
+    double e_acc = 0.0;
+    for (int g0 = wave * kGroup; g0 < nch; g0 += kWaves * kGroup) {
+        // chunk records are the same for the whole wave: scalar loads
+        int site[kGroup], dg[kGroup], base[kGroup], wmin[kGroup];
+        Idx jj[kGroup][kUnroll];
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r) {
+            const int ch = g0 + r;
+            site[r] = c0 + ch * 64 + lane;
+            const bool have = ch < nch;
+            base[r] = have ? __builtin_amdgcn_readfirstlane(cptr[ch0 + ch]) : 0;
+            wmin[r] = have ? __builtin_amdgcn_readfirstlane(cw[ch0 + ch]) & 255 : 0;
+            dg[r] = (have && site[r] < c1) ? (int)deg[site[r]] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r)
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) jj[r][k] = col[base[r] + k * 64 + lane];
 
-template <bool kLds>
+        // local fields: the first wmin neighbours of every lane of a chunk are
+        // real (uniform loop, no masking); lanes of higher degree finish alone
+        float hx[kGroup], hy[kGroup], lx[kGroup], ly[kGroup];
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r) {
+            hx[r] = hy[r] = lx[r] = ly[r] = 0.f;
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) {
+                if (k < wmin[r]) {
+                    const int j = (int)jj[r][k];
+                    const float2 u = Trig<kTrig>::unit(ang[j], tab);
+                    hx[r] += u.x; hy[r] += u.y;
+                    if (kLast && j < c0) { lx[r] += u.x; ly[r] += u.y; }
+                }
+            }
+            for (int k = kUnroll; k < wmin[r]; ++k) {                // wide chunks (uniform)
+                const int j = (int)col[base[r] + k * 64 + lane];
+                const float2 u = Trig<kTrig>::unit(ang[j], tab);
+                hx[r] += u.x; hy[r] += u.y;
+                if (kLast && j < c0) { lx[r] += u.x; ly[r] += u.y; }
+            }
+            for (int k = wmin[r]; k < dg[r]; ++k) {                   // lanes above the chunk minimum
+                const int j = (int)col[base[r] + k * 64 + lane];
+                const float2 u = Trig<kTrig>::unit(ang[j], tab);
+                hx[r] += u.x; hy[r] += u.y;
+                if (kLast && j < c0) { lx[r] += u.x; ly[r] += u.y; }
+            }
+        }
+
+        // one Philox call: word r drives the update of site r
+        const U4 w = philox4x32_10({(uint32_t)site[0], sweep, (uint32_t)slot,
+                                    tag(sub == 0 ? kMet : kOR, (uint32_t)sub)}, d.seed_lo, d.seed_hi);
+        const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+        float e_grp = 0.f;
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r) {
+            if (site[r] >= c1 || g0 + r >= nch) continue;
+            const uint32_t th = ang[site[r]];
+            const float2 cur = Trig<kTrig>::unit(th, tab);
+            uint32_t th_new;
+            if (sub == 0) {
+                th_new = words[r] & 0xFFFFu;                          // uniform proposal
+            } else {
+                th_new = (field_axis2(hx[r], hy[r]) - th) & 0xFFFFu;   // reflection
+            }
+            const float2 nu = Trig<kTrig>::unit(th_new, tab);
+            const float dE = hx[r] * (cur.x - nu.x) + hy[r] * (cur.y - nu.y);
+            bool accept = dE <= 0.f;
+            if (!accept) {
+                const float p = __expf(-beta * dE);
+                if (sub != 0) {
+                    accept = (float)(words[r] >> 8) * 0x1.0p-24f < p;
+                } else {
+                    // 16 uniform bits, extended by 32 more only on a tie:
+                    // accept iff U < p exactly for p in FP32
+                    const float p16 = p * 65536.0f;
+                    const uint32_t u16 = words[r] >> 16, f = (uint32_t)p16;
+                    if (u16 != f) {
+                        accept = u16 < f;
+                    } else {
+                        const U4 x = philox4x32_10({(uint32_t)site[r], sweep, (uint32_t)slot, tag(kMetAcc)},
+                                                   d.seed_lo, d.seed_hi);
+                        accept = (double)x.x < (double)(p16 - (float)f) * 4294967296.0;
+                    }
+                }
+            }
+            if (accept) ang[site[r]] = (uint16_t)th_new;
+            if (kLast) {
+                const float2 f = accept ? nu : cur;
+                e_grp -= f.x * lx[r] + f.y * ly[r];
+            }
+        }
+        if (kLast) e_acc += (double)e_grp;
+    }
+    return e_acc;
+}
+
+// LDS map: [double scratch kWaves*kNRed][trig table][uint16 angles n_pad (LDS variant)]
+constexpr size_t kOffTab = 1536;
+
+template <bool kLds, typename Idx, int kTrig>
 __global__ __launch_bounds__(kSweepBlock) void k_fix16_sweep(DevBatch b, const Item *items, int n_or, int measure)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -108,18 +300,14 @@ __global__ __launch_bounds__(kSweepBlock) void k_fix16_sweep(DevBatch b, const I
     const int s = it.sample, slot = it.slot, R = b.R;
     const SampleDesc &d = b.desc[s];
     const int n = d.n, n_pad = (n + 7) & ~7, tid = threadIdx.x;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
-    float2 *t32 = reinterpret_cast<float2 *>(smem + kOffT32);
-    double2 *t64 = reinterpret_cast<double2 *>(smem + kOffT64);
-    double *scratch = reinterpret_cast<double *>(smem + kOffRed);
-    double2 *trig = reinterpret_cast<double2 *>(smem + kOffTrig);
+    double *scratch = reinterpret_cast<double *>(smem);
+    float2 *tab = reinterpret_cast<float2 *>(smem + kOffTab);
     uint16_t *g_ang = static_cast<uint16_t *>(b.state) + d.state + (int64_t)slot * n_pad;
-    uint16_t *ang = kLds ? reinterpret_cast<uint16_t *>(smem + kOffTrig + 16 * (size_t)d.L) : g_ang;
-    const float2 *hi32 = t32, *lo32 = t32 + 256;
-    const double2 *hi64 = t64, *lo64 = t64 + 256;
+    uint16_t *ang = kLds ? reinterpret_cast<uint16_t *>(smem + kOffTab + Trig<kTrig>::kBytes) : g_ang;
 
-    for (int k = tid; k < 512; k += kSweepBlock) { t32[k] = b.tab32[k]; t64[k] = b.tab64[k]; }
-    for (int x = tid; x < d.L; x += kSweepBlock) trig[x] = b.f64[d.trig + x];
+    Trig<kTrig>::load(tab, b, tid);
     if (kLds) {
         const uint4 *src = reinterpret_cast<const uint4 *>(g_ang);
         uint4 *dst = reinterpret_cast<uint4 *>(ang);
@@ -129,49 +317,23 @@ __global__ __launch_bounds__(kSweepBlock) void k_fix16_sweep(DevBatch b, const I
 
     const float beta = (float)b.beta[s * R + b.T_of_slot[s * R + slot]];
     const uint32_t sweep = b.ctl->sweep;
-    const int32_t *row = b.i32 + d.row_ptr;
-    const int32_t *col = b.i32 + d.col;
+    const int32_t *cptr = b.i32 + d.sell_ptr;
+    const int32_t *cw = b.i32 + d.sell_w;
+    const Idx *col = reinterpret_cast<const Idx *>(sizeof(Idx) == 2 ? (const void *)b.u16 : (const void *)b.i32) + d.sell_col;
+    const uint8_t *deg = b.u8 + d.deg;
     double e_acc = 0.0;
 
     for (int sub = 0; sub <= n_or; ++sub) {
         const bool last = (sub == n_or);
         for (int c = 0; c < d.Q; ++c) {
             const int c0 = d.colour_off[c], c1 = d.colour_off[c + 1];
-            for (int i = c0 + tid; i < c1; i += kSweepBlock) {
-                // local field; the lower-colour part is final in the last sub-sweep
-                float hx = 0.f, hy = 0.f, lx = 0.f, ly = 0.f;
-                const int a1 = row[i + 1];
-                for (int a = row[i]; a < a1; ++a) {
-                    const int j = col[a];
-                    const float2 u = unit32(ang[j], hi32, lo32);
-                    hx += u.x; hy += u.y;
-                    if (j < c0) { lx += u.x; ly += u.y; }
-                }
-                const uint32_t th = ang[i];
-                uint32_t th_new, ubits;
-                if (sub == 0) {
-                    // Metropolis: uniform proposal
-                    const U4 w = philox4x32_10({(uint32_t)i, sweep, (uint32_t)slot, tag(kMet)}, d.seed_lo, d.seed_hi);
-                    th_new = w.x & 0xFFFFu;
-                    ubits = w.y;
-                } else {
-                    // over-relaxation: reflection about the quantised field axis
-                    const int q = __float2int_rn(atan2f(hy, hx) * kTwoPhiScale);
-                    th_new = (uint32_t)(q - (int)th) & 0xFFFFu;
-                    const U4 w = philox4x32_10({(uint32_t)i, sweep, (uint32_t)slot, tag(kOR, (uint32_t)sub)},
-                                               d.seed_lo, d.seed_hi);
-                    ubits = w.x;
-                }
-                const float2 cur = unit32(th, hi32, lo32);
-                const float2 nu = unit32(th_new, hi32, lo32);
-                const float dE = hx * (cur.x - nu.x) + hy * (cur.y - nu.y);
-                const bool accept = dE <= 0.f || (float)(ubits >> 8) * 0x1.0p-24f < __expf(-beta * dE);
-                if (accept) ang[i] = (uint16_t)th_new;
-                if (last) {
-                    const float2 f = accept ? nu : cur;
-                    e_acc -= (double)(f.x * lx + f.y * ly);
-                }
-            }
+            const int ch0 = d.chunk_off[c], nch = d.chunk_off[c + 1] - ch0;
+            if (last)
+                e_acc += colour_phase<true, Idx, kTrig>(d, ang, tab, cptr, cw, col, deg, c0, c1, ch0, nch, wave,
+                                                        lane, sweep, slot, sub, beta);
+            else
+                colour_phase<false, Idx, kTrig>(d, ang, tab, cptr, cw, col, deg, c0, c1, ch0, nch, wave, lane,
+                                                sweep, slot, sub, beta);
             __syncthreads();
         }
     }
@@ -181,7 +343,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_fix16_sweep(DevBatch b, const I
         block_sum<1>(v, scratch);
         if (tid == 0) b.E_slot[s * R + slot] = v[0];
     }
-    if (measure) observe(b, d, ang, hi64, lo64, trig, scratch, b.obs_slot + ((int64_t)s * R + slot) * XY_NOBS);
+    if (measure) observe<Idx>(b, d, ang, scratch, b.obs_slot + ((int64_t)s * R + slot) * XY_NOBS);
     if (kLds) {
         __syncthreads();
         const uint4 *src = reinterpret_cast<const uint4 *>(ang);
@@ -209,18 +371,16 @@ __global__ __launch_bounds__(256) void k_fix16_init(DevBatch b)
 }
 
 // Stand-alone measurement from the state in global memory.
+template <typename Idx>
 __global__ __launch_bounds__(kObsBlock) void k_fix16_observe(DevBatch b, double *out_by_T)
 {
-    __shared__ double2 t64[512];
     __shared__ double scratch[(kObsBlock / 64) * kNRed];
     const int slot = blockIdx.x, s = blockIdx.y, R = b.R;
     const SampleDesc &d = b.desc[s];
-    for (int k = threadIdx.x; k < 512; k += kObsBlock) t64[k] = b.tab64[k];
-    __syncthreads();
     const int n_pad = (d.n + 7) & ~7;
     const uint16_t *ang = static_cast<const uint16_t *>(b.state) + d.state + (int64_t)slot * n_pad;
     double o[XY_NOBS];
-    observe(b, d, ang, t64, t64 + 256, b.f64 + d.trig, scratch, o);
+    observe<Idx>(b, d, ang, scratch, o);
     if (threadIdx.x != 0) return;
     double *dst = out_by_T ? out_by_T + ((int64_t)s * R + b.T_of_slot[s * R + slot]) * XY_NOBS
                            : b.obs_slot + ((int64_t)s * R + slot) * XY_NOBS;
@@ -228,11 +388,38 @@ __global__ __launch_bounds__(kObsBlock) void k_fix16_observe(DevBatch b, double 
     b.E_slot[s * R + slot] = o[0];
 }
 
+template <bool kLds, typename Idx, int kTrig>
+hipError_t launch_sweep_t(const DevBatch &b, const Item *items, int n_items, int n_or, int measure, size_t lds,
+                          hipStream_t s)
+{
+    static bool attr_set = false;
+    if (kLds && !attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fix16_sweep<kLds, Idx, kTrig>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_fix16_sweep<kLds, Idx, kTrig>), dim3(n_items), dim3(kSweepBlock), lds, s, b, items,
+                       n_or, measure);
+    return hipGetLastError();
+}
+
+template <bool kLds, typename Idx>
+hipError_t launch_sweep_i(const DevBatch &b, const Item *items, int n_items, int n_or, int measure, size_t lds,
+                          hipStream_t s)
+{
+    switch (b.trig) {
+    case 0: return launch_sweep_t<kLds, Idx, 0>(b, items, n_items, n_or, measure, lds, s);
+    case 2: return launch_sweep_t<kLds, Idx, 2>(b, items, n_items, n_or, measure, lds, s);
+    default: return launch_sweep_t<kLds, Idx, 1>(b, items, n_items, n_or, measure, lds, s);
+    }
+}
+
 }  // namespace
 
-size_t fix16_lds_bytes(int n_pad, int L)
+size_t fix16_lds_bytes(int n_pad, int trig)
 {
-    return kOffTrig + 16 * (size_t)L + 2 * (size_t)n_pad;
+    const size_t tab = trig == 0 ? Trig<0>::kBytes : trig == 2 ? Trig<2>::kBytes : Trig<1>::kBytes;
+    return kOffTab + tab + 2 * (size_t)n_pad;
 }
 
 hipError_t launch_fix16_init(const DevBatch &b, int max_n, hipStream_t s)
@@ -248,24 +435,21 @@ hipError_t launch_fix16_sweep(const DevBatch &b, const Item *items, int n_items,
 {
     if (n_items == 0) return hipSuccess;
     if (lds) {
-        static bool attr_set = false;
-        if (!attr_set) {
-            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fix16_sweep<true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            attr_set = true;
-        }
-        hipLaunchKernelGGL(k_fix16_sweep<true>, dim3(n_items), dim3(kSweepBlock), lds_bytes, s, b, items, n_or,
-                           measure);
-    } else {
-        hipLaunchKernelGGL(k_fix16_sweep<false>, dim3(n_items), dim3(kSweepBlock), lds_bytes, s, b, items, n_or,
-                           measure);
+        return b.idx16 ? launch_sweep_i<true, uint16_t>(b, items, n_items, n_or, measure, lds_bytes, s)
+                       : launch_sweep_i<true, int32_t>(b, items, n_items, n_or, measure, lds_bytes, s);
     }
-    return hipGetLastError();
+    return b.idx16 ? launch_sweep_i<false, uint16_t>(b, items, n_items, n_or, measure, lds_bytes, s)
+                   : launch_sweep_i<false, int32_t>(b, items, n_items, n_or, measure, lds_bytes, s);
 }
 
 hipError_t launch_fix16_observe(const DevBatch &b, double *out_by_T, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fix16_observe, dim3((unsigned)b.R, (unsigned)b.G), dim3(kObsBlock), 0, s, b, out_by_T);
+    if (b.idx16)
+        hipLaunchKernelGGL(k_fix16_observe<uint16_t>, dim3((unsigned)b.R, (unsigned)b.G), dim3(kObsBlock), 0, s, b,
+                           out_by_T);
+    else
+        hipLaunchKernelGGL(k_fix16_observe<int32_t>, dim3((unsigned)b.R, (unsigned)b.G), dim3(kObsBlock), 0, s, b,
+                           out_by_T);
     return hipGetLastError();
 }
 

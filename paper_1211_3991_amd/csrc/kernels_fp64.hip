@@ -103,55 +103,74 @@ __global__ __launch_bounds__(kBlock) void k_fp64_phase(DevBatch b, int colour, i
     }
 }
 
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double *scratch)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < NV; ++q)
-        for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_down(v[q], off, 64);
-    if (lane == 0)
-        for (int q = 0; q < NV; ++q) scratch[wave * NV + q] = v[q];
-    __syncthreads();
-    if (threadIdx.x == 0)
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
-            for (int q = 0; q < NV; ++q) v[q] += scratch[w * NV + q];
-}
+// Energy (and, when full, the observables) of every (sample, slot), in two
+// deterministic stages.  Stage 1: block b of sample s covers a contiguous
+// range of sites for all slots; thread t handles slot t % R of sites
+// t / R, t / R + nsl, ... so that a warp reads whole [site][slot] rows, and
+// accumulates E = -sum over links S_i.S_j (each link once, at its higher
+// colour-major endpoint), m and the Fourier sums of Sec. 3; the per-slot sums
+// of the block go to partial[s][b][slot][11].  Stage 2 adds the kObsBlocks
+// partials of each (sample, slot) in block order.
+constexpr int kObsBlocks = 64;
+constexpr int kNRed = 11;
 
-// Energy (and, when full, the observables) of one (sample, slot).
-// E = -sum over links S_i.S_j, each link counted once at its higher
-// colour-major endpoint; m and the Fourier sums of Sec. 3.
-__global__ __launch_bounds__(kBlock) void k_fp64_observe(DevBatch b, int full, double *out_by_T)
+__global__ __launch_bounds__(kBlock) void k_fp64_observe_partial(DevBatch b, int full)
 {
-    __shared__ double scratch[(kBlock / 64) * 11];
-    const int slot = blockIdx.x, s = blockIdx.y, R = b.R;
+    __shared__ double red[kBlock * kNRed];
+    const int s = blockIdx.y, R = b.R;
     const SampleDesc &d = b.desc[s];
-    const double2 *S = static_cast<const double2 *>(b.state) + d.state;
-    const int32_t *row = b.i32 + d.row_ptr;
-    const int32_t *col = b.i32 + d.col;
-    const uint32_t *xy = b.u32 + d.coord;
-    const double2 *trig = b.f64 + d.trig;
-    double v[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int i = threadIdx.x; i < d.n; i += kBlock) {
-        const double2 si = S[(int64_t)i * R + slot];
-        double e = 0.0;
-        for (int a = row[i]; a < row[i + 1]; ++a) {
-            const int j = col[a];
-            if (j >= i) break;                        // ascending rows: lower indices first
-            const double2 sj = S[(int64_t)j * R + slot];
-            e += si.x * sj.x + si.y * sj.y;
-        }
-        v[0] -= e;
-        if (full) {
-            const uint32_t p = xy[i];
-            const double2 ex = trig[p & 0xFFFFu], ey = trig[p >> 16];
-            v[1] += si.x; v[2] += si.y;
-            v[3] += si.x * ex.x; v[4] += si.x * ex.y; v[5] += si.y * ex.x; v[6] += si.y * ex.y;
-            v[7] += si.x * ey.x; v[8] += si.x * ey.y; v[9] += si.y * ey.x; v[10] += si.y * ey.y;
+    const int nsl = kBlock / R;                         // site lanes per block (R <= 256)
+    const int t = threadIdx.x, slot = t % R, sl = t / R;
+    const int per = (d.n + kObsBlocks - 1) / kObsBlocks;
+    const int i0 = blockIdx.x * per, i1 = min(d.n, i0 + per);
+    double v[kNRed] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (sl < nsl) {
+        const double2 *S = static_cast<const double2 *>(b.state) + d.state;
+        const int32_t *row = b.i32 + d.row_ptr;
+        const int32_t *col = b.i32 + d.col;
+        const uint32_t *xy = b.u32 + d.coord;
+        const double2 *trig = b.f64 + d.trig;
+        for (int i = i0 + sl; i < i1; i += nsl) {
+            const double2 si = S[(int64_t)i * R + slot];
+            double e = 0.0;
+            for (int a = row[i]; a < row[i + 1]; ++a) {
+                const int j = col[a];
+                if (j >= i) break;                      // ascending rows: lower indices first
+                const double2 sj = S[(int64_t)j * R + slot];
+                e += si.x * sj.x + si.y * sj.y;
+            }
+            v[0] -= e;
+            if (full) {
+                const uint32_t p = xy[i];
+                const double2 ex = trig[p & 0xFFFFu], ey = trig[p >> 16];
+                v[1] += si.x; v[2] += si.y;
+                v[3] += si.x * ex.x; v[4] += si.x * ex.y; v[5] += si.y * ex.x; v[6] += si.y * ex.y;
+                v[7] += si.x * ey.x; v[8] += si.x * ey.y; v[9] += si.y * ey.x; v[10] += si.y * ey.y;
+            }
         }
     }
-    block_sum<11>(v, scratch);
-    if (threadIdx.x != 0) return;
+    for (int q = 0; q < kNRed; ++q) red[t * kNRed + q] = v[q];
+    __syncthreads();
+    if (t < R) {
+        for (int q = 0; q < kNRed; ++q) {
+            double acc = 0.0;
+            for (int k = 0; k < nsl; ++k) acc += red[(k * R + t) * kNRed + q];
+            b.partial[(((int64_t)s * kObsBlocks + blockIdx.x) * R + t) * kNRed + q] = acc;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fp64_observe_final(DevBatch b, int full, double *out_by_T)
+{
+    const int R = b.R;
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)b.G * R) return;
+    const int s = (int)(t / R), slot = (int)(t % R);
+    const SampleDesc &d = b.desc[s];
+    double v[kNRed];
+    for (int q = 0; q < kNRed; ++q) v[q] = 0.0;
+    for (int blk = 0; blk < kObsBlocks; ++blk)
+        for (int q = 0; q < kNRed; ++q) v[q] += b.partial[(((int64_t)s * kObsBlocks + blk) * R + slot) * kNRed + q];
     b.E_slot[s * R + slot] = v[0];
     if (!full) return;
     const double N = (double)d.n;
@@ -235,8 +254,12 @@ hipError_t launch_fp64_phase(const DevBatch &b, int colour, int met, int max_cla
 
 hipError_t launch_fp64_observe(const DevBatch &b, int full, double *out_by_T, hipStream_t s)
 {
-    dim3 grid((unsigned)b.R, (unsigned)b.G);
-    hipLaunchKernelGGL(k_fp64_observe, grid, dim3(kBlock), 0, s, b, full, out_by_T);
+    hipLaunchKernelGGL(k_fp64_observe_partial, dim3(kObsBlocks, (unsigned)b.G), dim3(kBlock), 0, s, b, full);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)b.G * b.R;
+    hipLaunchKernelGGL(k_fp64_observe_final, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, b,
+                       full, out_by_T);
     return hipGetLastError();
 }
 

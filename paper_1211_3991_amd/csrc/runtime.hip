@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -57,6 +58,8 @@ struct Plan {
     int max_n = 0, Qmax = 0;
     std::vector<int64_t> state_off;
     size_t item_cap = 0;
+    std::vector<Sell> sell;      // fix16 only
+    bool idx16 = false;
 };
 
 xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int max_records, Plan &p)
@@ -67,14 +70,32 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
     if (max_records < 0) return set_error(XY_EINVAL, "batch: max_records < 0");
     p.desc.assign(G, SampleDesc{});
     p.state_off.assign(G, 0);
-    size_t n_i32 = 0, n_u32 = 0, n_f64 = 0, state_elems = 0;
+    size_t n_i32 = 0, n_u32 = 0, n_f64 = 0, n_u16 = 0, n_u8 = 0, state_elems = 0;
+    const bool fix16 = precision == XY_FIX16;
+    int max_n = 0;
     for (int s = 0; s < G; ++s) {
         if (!g[s]) return set_error(XY_EINVAL, "batch: NULL graph");
+        max_n = std::max(max_n, g[s]->n);
+    }
+    p.idx16 = fix16 && max_n <= 65536;
+    if (fix16) p.sell.resize(G);
+    for (int s = 0; s < G; ++s) {
         const xy_graph &gr = *g[s];
         SampleDesc &d = p.desc[s];
         d.n = gr.n; d.Q = gr.Q; d.L = gr.L; d.max_deg = gr.max_deg;
-        d.row_ptr = (int64_t)n_i32; n_i32 += gr.n + 1;
-        d.col = (int64_t)n_i32;     n_i32 += 2 * (size_t)gr.m;
+        if (!fix16) {
+            d.row_ptr = (int64_t)n_i32; n_i32 += gr.n + 1;
+            d.col = (int64_t)n_i32;     n_i32 += 2 * (size_t)gr.m;
+        } else {
+            p.sell[s] = build_sell(gr);
+            const Sell &S = p.sell[s];
+            d.sell_ptr = (int64_t)n_i32; n_i32 += S.chunk_ptr.size();
+            d.sell_w = (int64_t)n_i32;   n_i32 += S.chunk_w.size();
+            if (p.idx16) { d.sell_col = (int64_t)n_u16; n_u16 += align_up(S.col.size(), 8); }
+            else         { d.sell_col = (int64_t)n_i32; n_i32 += S.col.size(); }
+            d.deg = (int64_t)n_u8;      n_u8 += align_up(gr.n, 16);
+            for (int c = 0; c <= kMaxColours; ++c) d.chunk_off[c] = S.chunk_off[std::min(c, gr.Q)];
+        }
         d.perm = (int64_t)n_i32;    n_i32 += gr.n;
         n_i32 = align_up(n_i32, 4);
         d.coord = (int64_t)n_u32;   n_u32 += align_up(gr.n, 4);
@@ -82,7 +103,7 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
         for (int c = 0; c <= kMaxColours; ++c) d.colour_off[c] = gr.colour_off[std::min(c, gr.Q)];
         d.state = (int64_t)state_elems;
         p.state_off[s] = d.state;
-        state_elems += (precision == XY_FP64) ? (size_t)gr.n * R : (size_t)((gr.n + 7) & ~7) * R;
+        state_elems += fix16 ? (size_t)((gr.n + 7) & ~7) * R : (size_t)gr.n * R;
         p.max_n = std::max(p.max_n, gr.n);
         p.Qmax = std::max(p.Qmax, gr.Q);
     }
@@ -93,11 +114,14 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
     gl.i32_pool = off;  off = align_up(off + 4 * n_i32, 256);
     gl.u32_pool = off;  off = align_up(off + 4 * n_u32, 256);
     gl.f64_pool = off;  off = align_up(off + 16 * n_f64, 256);
+    gl.u16_pool = off;  off = align_up(off + 2 * n_u16, 256);
+    gl.u8_pool = off;   off = align_up(off + n_u8, 256);
     gl.items = off;     off = align_up(off + 2 * sizeof(Item) * p.item_cap, 256);
     gl.tab32 = off;     off = align_up(off + 512 * 8, 256);
+    gl.tab2k = off;     off = align_up(off + 2048 * 8, 256);
     gl.tab64 = off;     off = align_up(off + 512 * 16, 256);
     gl.total = off;
-    gl.n_i32 = n_i32; gl.n_u32 = n_u32; gl.n_f64 = n_f64;
+    gl.n_i32 = n_i32; gl.n_u32 = n_u32; gl.n_f64 = n_f64; gl.n_u16 = n_u16; gl.n_u8 = n_u8;
     WorkLayout &wl = p.wl;
     const size_t GR = (size_t)G * R;
     off = 0;
@@ -109,6 +133,7 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
     wl.obs_slot = off;  off = align_up(off + 8 * XY_NOBS * GR, 256);
     wl.pt_acc = off;    off = align_up(off + 8 * GR, 256);
     wl.pt_try = off;    off = align_up(off + 8 * GR, 256);
+    wl.partial = off;   off = align_up(off + (fix16 ? 0 : 8 * 64 * 11 * GR), 256);
     wl.total = off;
     p.state_bytes = align_up(state_elems * (precision == XY_FP64 ? 16 : 2), 256);
     p.obs_bytes = align_up((size_t)max_records * GR * XY_NOBS * 8, 256);
@@ -196,7 +221,13 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
             const xy_graph &gr = *g[s_];
             for (int c = 0; c < gr.Q; ++c)
                 b->max_class[c] = std::max(b->max_class[c], gr.colour_off[c + 1] - gr.colour_off[c]);
-            b->perm[s_] = gr.perm;
+            if (precision == XY_FIX16) {
+                const Sell &S = p.sell[s_];
+                b->perm[s_].resize(gr.n);
+                for (int k = 0; k < gr.n; ++k) b->perm[s_][k] = gr.perm[S.order[k]];
+            } else {
+                b->perm[s_] = gr.perm;
+            }
             b->n[s_] = gr.n;
             p.desc[s_].seed_lo = (uint32_t)seeds[s_];
             p.desc[s_].seed_hi = (uint32_t)(seeds[s_] >> 32);
@@ -209,15 +240,29 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
         int32_t *i32 = reinterpret_cast<int32_t *>(gimg.data() + gl.i32_pool);
         uint32_t *u32 = reinterpret_cast<uint32_t *>(gimg.data() + gl.u32_pool);
         double *f64 = reinterpret_cast<double *>(gimg.data() + gl.f64_pool);
+        uint16_t *u16 = reinterpret_cast<uint16_t *>(gimg.data() + gl.u16_pool);
+        uint8_t *u8 = reinterpret_cast<uint8_t *>(gimg.data() + gl.u8_pool);
         const double two_pi = 6.283185307179586476925286766559;
         for (int s_ = 0; s_ < G; ++s_) {
             const xy_graph &gr = *g[s_];
             const SampleDesc &d = p.desc[s_];
-            std::copy(gr.row_ptr.begin(), gr.row_ptr.end(), i32 + d.row_ptr);
-            std::copy(gr.col.begin(), gr.col.end(), i32 + d.col);
-            std::copy(gr.perm.begin(), gr.perm.end(), i32 + d.perm);
+            if (precision == XY_FP64) {
+                std::copy(gr.row_ptr.begin(), gr.row_ptr.end(), i32 + d.row_ptr);
+                std::copy(gr.col.begin(), gr.col.end(), i32 + d.col);
+            } else {
+                const Sell &S = p.sell[s_];
+                std::copy(S.chunk_ptr.begin(), S.chunk_ptr.end(), i32 + d.sell_ptr);
+                std::copy(S.chunk_w.begin(), S.chunk_w.end(), i32 + d.sell_w);
+                if (p.idx16)
+                    for (size_t k = 0; k < S.col.size(); ++k) u16[d.sell_col + k] = (uint16_t)S.col[k];
+                else
+                    std::copy(S.col.begin(), S.col.end(), i32 + d.sell_col);
+                std::copy(S.deg.begin(), S.deg.end(), u8 + d.deg);
+            }
+            const std::vector<int32_t> &pm = b->perm[s_];   // device index -> lattice index
+            std::copy(pm.begin(), pm.end(), i32 + d.perm);
             for (int k = 0; k < gr.n; ++k) {
-                const int v = gr.perm[k];
+                const int v = pm[k];
                 u32[d.coord + k] = (uint32_t)gr.cx[v] | ((uint32_t)gr.cy[v] << 16);
             }
             for (int x = 0; x < gr.L; ++x) {
@@ -227,7 +272,13 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
         }
         const size_t off_tab32 = gl.tab32, off_tab64 = gl.tab64;
         float *t32 = reinterpret_cast<float *>(gimg.data() + off_tab32);
+        float *t2k = reinterpret_cast<float *>(gimg.data() + gl.tab2k);
         double *t64 = reinterpret_cast<double *>(gimg.data() + off_tab64);
+        for (int k = 0; k < 2048; ++k) {
+            const double a = two_pi * (32.0 * k) / 65536.0;
+            t2k[2 * k] = (float)std::cos(a);
+            t2k[2 * k + 1] = (float)std::sin(a);
+        }
         for (int k = 0; k < 256; ++k) {
             const double ahi = two_pi * (256.0 * k) / 65536.0, alo = two_pi * k / 65536.0;
             t64[2 * k] = std::cos(ahi);          t64[2 * k + 1] = std::sin(ahi);
@@ -237,6 +288,11 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
             t32[512 + 2 * k + 1] = (float)t64[512 + 2 * k + 1];
         }
         // fix16 items: LDS-resident where the replica fits, else global state
+        // (cos, sin) form of the fixed-point sweep: the hardware sine/cosine by
+        // default (fastest on gfx950); XY_FIX16_TRIG=0/1 selects a table form
+        int trig = 2;
+        if (const char *env = std::getenv("XY_FIX16_TRIG")) trig = std::atoi(env);
+        if (trig < 0 || trig > 2) trig = 2;
         if (precision == XY_FIX16) {
             int dev = 0, lds_limit = 0;
             (void)hipGetDevice(&dev);
@@ -246,9 +302,9 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
             size_t lds_max = 0, glob_max = 0;
             for (int s_ = 0; s_ < G; ++s_) {
                 const int n_pad = (p.desc[s_].n + 7) & ~7;
-                const size_t need = fix16_lds_bytes(n_pad, p.desc[s_].L);
+                const size_t need = fix16_lds_bytes(n_pad, trig);
                 if (need <= (size_t)lds_limit) { in_lds.push_back(s_); lds_max = std::max(lds_max, need); }
-                else { in_glob.push_back(s_); glob_max = std::max(glob_max, fix16_lds_bytes(0, p.desc[s_].L)); }
+                else { in_glob.push_back(s_); glob_max = std::max(glob_max, fix16_lds_bytes(0, trig)); }
             }
             const std::vector<Item> a = xcd_order(in_lds, p.desc, R), c = xcd_order(in_glob, p.desc, R);
             if (a.size() > p.item_cap || c.size() > p.item_cap) {
@@ -292,7 +348,10 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
         dv.i32 = reinterpret_cast<const int32_t *>(gbase + gl.i32_pool);
         dv.u32 = reinterpret_cast<const uint32_t *>(gbase + gl.u32_pool);
         dv.f64 = reinterpret_cast<const double2 *>(gbase + gl.f64_pool);
+        dv.u16 = reinterpret_cast<const uint16_t *>(gbase + gl.u16_pool);
+        dv.u8 = reinterpret_cast<const uint8_t *>(gbase + gl.u8_pool);
         dv.tab32 = reinterpret_cast<const float2 *>(gbase + off_tab32);
+        dv.tab2k = reinterpret_cast<const float2 *>(gbase + gl.tab2k);
         dv.tab64 = reinterpret_cast<const double2 *>(gbase + off_tab64);
         dv.state = d_state;
         dv.ctl = reinterpret_cast<Ctl *>(wbase + wl.ctl);
@@ -303,9 +362,12 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
         dv.obs_slot = reinterpret_cast<double *>(wbase + wl.obs_slot);
         dv.pt_acc = reinterpret_cast<unsigned long long *>(wbase + wl.pt_acc);
         dv.pt_try = reinterpret_cast<unsigned long long *>(wbase + wl.pt_try);
+        dv.partial = reinterpret_cast<double *>(wbase + wl.partial);
         dv.records = static_cast<double *>(d_obs);
         dv.G = G; dv.R = R; dv.max_records = max_records; dv.max_n = p.max_n;
         dv.log = nullptr; dv.log_sweeps = 0;
+        dv.idx16 = p.idx16 ? 1 : 0;
+        dv.trig = trig;
 
         e = (precision == XY_FP64) ? launch_fp64_init(dv, p.max_n, s) : launch_fix16_init(dv, p.max_n, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);   // host images must outlive the copies

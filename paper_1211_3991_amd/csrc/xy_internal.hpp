@@ -103,8 +103,13 @@ struct SampleDesc {
     int64_t coord;        // uint32 pool: x | y << 16, by colour-major index
     int64_t trig;         // double2 pool: (cos, sin)(2 pi x / L), x < L
     int64_t state;        // element offset into the state region (double2 or uint16)
+    int64_t sell_ptr;     // fix16: int32 pool, first column entry of each 64-site chunk (+1 end)
+    int64_t sell_w;       // fix16: int32 pool, per chunk: smallest degree | largest degree << 8
+    int64_t sell_col;     // fix16: u16 or int32 pool, columns chunk by chunk, [k][lane] inside a chunk
+    int64_t deg;          // fix16: u8 pool, degree by site
     uint32_t seed_lo, seed_hi;
     int32_t colour_off[kMaxColours + 1];
+    int32_t chunk_off[kMaxColours + 1];   // fix16: first chunk of each colour class
 };
 
 struct Ctl {
@@ -116,13 +121,28 @@ struct Ctl {
 
 // Work region layout (byte offsets computed by layout_work()).
 struct WorkLayout {
-    size_t ctl, beta, slot_of_T, T_of_slot, E_slot, obs_slot, pt_acc, pt_try, total;
+    size_t ctl, beta, slot_of_T, T_of_slot, E_slot, obs_slot, pt_acc, pt_try, partial, total;
 };
 
 struct GraphLayout {
-    size_t desc, i32_pool, u32_pool, f64_pool, items, tab32, tab64, total;
-    size_t n_i32, n_u32, n_f64;
+    size_t desc, i32_pool, u32_pool, f64_pool, u16_pool, u8_pool, items, tab32, tab2k, tab64, total;
+    size_t n_i32, n_u32, n_f64, n_u16, n_u8;
 };
+
+// Sliced-ELL form of a graph used by the fixed-point sweep.  Sites are
+// renumbered inside each colour class by decreasing degree (ties: colour-major
+// order), so the 64 sites of a chunk have nearly equal degree; chunk columns
+// are stored k-major ([k][lane]) so that the k-th neighbour loads of a wave are
+// contiguous.  Padding entries hold 0 and are skipped through the degree.
+struct Sell {
+    std::vector<int32_t> order;      // fix16 index -> colour-major index
+    std::vector<int32_t> chunk_ptr;  // n_chunks + 1
+    std::vector<int32_t> chunk_w;    // n_chunks: smallest degree | largest degree << 8
+    std::vector<int32_t> col;        // fix16 indices
+    std::vector<uint8_t> deg;
+    std::vector<int32_t> chunk_off;  // Q + 1
+};
+Sell build_sell(const xy_graph &g);
 
 // One fix16 work item: a (sample, slot) pair run by one workgroup.
 struct Item { int32_t sample, slot; };

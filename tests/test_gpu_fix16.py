@@ -90,9 +90,14 @@ def _tiny_exact(name, beta):
     return -np.sum(n * f ** (n - 1) * f1) / np.sum(f ** n)
 
 
+TRIG_FORMS = [0, 1, 2]   # (cos, sin) evaluation of the fixed-point sweep (XY_FIX16_TRIG)
+
+
+@pytest.mark.parametrize("trig", TRIG_FORMS)
 @pytest.mark.parametrize("name,n,edges", [("link", 2, [(0, 1)]), ("triangle", 3, [(0, 1), (1, 2), (2, 0)]),
                                           ("cycle4", 4, [(0, 1), (1, 2), (2, 3), (3, 0)])])
-def test_tiny_graphs_exact_energy(name, n, edges):
+def test_tiny_graphs_exact_energy(name, n, edges, trig, monkeypatch):
+    monkeypatch.setenv("XY_FIX16_TRIG", str(trig))
     T = np.array([0.8, 1.2, 1.6, 2.0])
     n_samples = 256
     g = xy.Graph.from_edges(n, edges)
@@ -107,8 +112,10 @@ def test_tiny_graphs_exact_energy(name, n, edges):
         assert abs(m - _tiny_exact(name, 1 / t)) < 4 * err, (name, t, m, _tiny_exact(name, 1 / t), err)
 
 
-def test_l16_observables_match_oracle():
+@pytest.mark.parametrize("trig", TRIG_FORMS)
+def test_l16_observables_match_oracle(trig, monkeypatch):
     """fix16 on 128 independent chains of the L=16 graph vs the FP64 oracle (1e4 sweeps)."""
+    monkeypatch.setenv("XY_FIX16_TRIG", str(trig))
     wl = workloads.plain_fp64_l16()
     s = wl.samples[0]
     e, _ = oracle.levy_graph(s.L, s.z, s.rho, s.seed)
