@@ -1,0 +1,120 @@
+"""Host analysis of measurement records (Sec. 3 observables, Sec. 4 method).
+
+Records come from ``Batch.records()``: float64 [n_rec, G, n_T, 8] with
+columns E, |m|^2, |m|^4, F_x, F_y, m_x, m_y, 0.  Thermal averages use the
+second half of the records (the last exponential time window, Sec. 4) and
+errors come from a jackknife over contiguous time bins (per sample) or over
+samples (disorder averages).
+
+Definitions (Sec. 3):
+  c    = (<H^2> - <H>^2) / (N T^2)                       Eq. (specificheat)
+  chi  = N <|m|^2>  (and N(<|m|^2> - |<m>|^2) with the m vector)   Eq. (chi)
+  U4   = <m^4> / <m^2>^2 - 1      (per sample; disorder: mean<m^4> / mean(<m^2>^2) - 1)
+  xi_2 = [chi(0)/chi(k_min) - 1]^(1/psi) / (2 sin(|k_min|/2)),  chi(k) = <F(k)>,
+         chi(0) = N <|m|^2>, |k_min| = 2 pi / L, psi = rho - 2 for rho < 3.75 else 2
+"""
+import numpy as np
+
+E, M2, M4, FX, FY, MX, MY = range(7)
+
+
+def psi_of(rho):
+    """Long-range exponent psi of the correlation length (rho - d in the
+    long-range regime, 2 in the short-range one; d = 2, boundary rho = 3.75)."""
+    return rho - 2.0 if rho < 3.75 else 2.0
+
+
+def bin_means(x, n_bins):
+    """Means of n_bins contiguous bins along axis 0 (trailing remainder dropped)."""
+    x = np.asarray(x, dtype=np.float64)
+    nb = x.shape[0] // n_bins
+    if nb < 1:
+        raise ValueError(f"need at least {n_bins} records, have {x.shape[0]}")
+    return x[: nb * n_bins].reshape((n_bins, nb) + x.shape[1:]).mean(axis=1)
+
+
+def jackknife(fn, blocks):
+    """Jackknife of fn over the first axis of each array in `blocks` (one entry
+    per bin or per sample).  Returns (bias-corrected estimate, error)."""
+    blocks = [np.asarray(b, dtype=np.float64) for b in blocks]
+    n = blocks[0].shape[0]
+    full = fn(*[b.mean(axis=0) for b in blocks])
+    tot = [b.sum(axis=0) for b in blocks]
+    loo = np.array([fn(*[(t - b[i]) / (n - 1) for t, b in zip(tot, blocks)]) for i in range(n)])
+    mean_loo = loo.mean(axis=0)
+    est = n * full - (n - 1) * mean_loo
+    err = np.sqrt((n - 1) / n * np.sum((loo - mean_loo) ** 2, axis=0))
+    return est, err
+
+
+def _observables(N, T, L, rho):
+    """Functions of the bin means (E, E^2, m2, m4, F) for one sample/temperature."""
+    beta = 1.0 / T
+    psi = psi_of(rho)
+    s = 2.0 * np.sin(np.pi / L)
+
+    def xi2(m2, f):
+        r = N * m2 / f - 1.0
+        return np.where(r > 0, np.abs(r) ** (1.0 / psi), np.nan) / s
+
+    return {
+        "e": lambda e, e2, m2, m4, f: e / N,
+        "c": lambda e, e2, m2, m4, f: beta * beta * (e2 - e * e) / N,
+        "chi": lambda e, e2, m2, m4, f: N * m2,
+        "U4": lambda e, e2, m2, m4, f: m4 / (m2 * m2) - 1.0,
+        "ratio": lambda e, e2, m2, m4, f: N * m2 / f,
+        "xi2": lambda e, e2, m2, m4, f: xi2(m2, f),
+    }
+
+
+def thermal(records, N, T, L, rho, n_bins=20, discard=0.5):
+    """Per-sample thermal averages with jackknife errors.
+
+    records: [n_rec, G, n_T, 8]; N, L, rho: per-sample sequences (or scalars);
+    T: [n_T] or [G, n_T].  Returns {name: (value[G, n_T], error[G, n_T])}."""
+    rec = np.asarray(records, dtype=np.float64)
+    rec = rec[int(rec.shape[0] * discard):]
+    n_rec, G, R, _ = rec.shape
+    N = np.broadcast_to(np.asarray(N, dtype=np.float64), (G,))
+    L = np.broadcast_to(np.asarray(L, dtype=np.float64), (G,))
+    rho = np.broadcast_to(np.asarray(rho, dtype=np.float64), (G,))
+    T = np.broadcast_to(np.asarray(T, dtype=np.float64), (G, R))
+    out = {}
+    for g in range(G):
+        for k in range(R):
+            x = rec[:, g, k]
+            f = 0.5 * (x[:, FX] + x[:, FY])
+            series = [x[:, E], x[:, E] ** 2, x[:, M2], x[:, M4], f]
+            blocks = [bin_means(sr, n_bins) for sr in series]
+            for name, fn in _observables(N[g], T[g, k], L[g], rho[g]).items():
+                v, e = jackknife(fn, blocks)
+                if name not in out:
+                    out[name] = (np.full((G, R), np.nan), np.full((G, R), np.nan))
+                out[name][0][g, k] = v
+                out[name][1][g, k] = e
+    return out
+
+
+def disorder(records, N, T, L, rho, discard=0.5):
+    """Disorder averages over the G samples (same N, L, rho) with a jackknife
+    over samples.  U4 is the ratio of disorder averages as printed in Sec. 3:
+    mean <m^4> / mean(<m^2>^2) - 1.  Returns {name: (value[n_T], error[n_T])}."""
+    rec = np.asarray(records, dtype=np.float64)
+    rec = rec[int(rec.shape[0] * discard):]
+    th = rec.mean(axis=0)                                  # [G, n_T, 8] thermal averages
+    e2 = (rec[:, :, :, E] ** 2).mean(axis=0)               # [G, n_T]
+    T = np.asarray(T, dtype=np.float64)
+    beta = 1.0 / T
+    psi = psi_of(rho)
+    s = 2.0 * np.sin(np.pi / L)
+    f = 0.5 * (th[:, :, FX] + th[:, :, FY])
+    var = e2 - th[:, :, E] ** 2                            # per-sample <H^2> - <H>^2
+    blocks = [th[:, :, E], var, th[:, :, M2], th[:, :, M4], th[:, :, M2] ** 2, f]
+    fns = {
+        "e": lambda e, v, m2, m4, m2sq, ff: e / N,
+        "c": lambda e, v, m2, m4, m2sq, ff: beta * beta * v / N,
+        "chi": lambda e, v, m2, m4, m2sq, ff: N * m2,
+        "U4": lambda e, v, m2, m4, m2sq, ff: m4 / m2sq - 1.0,
+        "xi2": lambda e, v, m2, m4, m2sq, ff: np.abs(N * m2 / ff - 1.0) ** (1.0 / psi) / s,
+    }
+    return {name: jackknife(fn, blocks) for name, fn in fns.items()}
