@@ -26,8 +26,6 @@
 namespace xy {
 namespace {
 
-constexpr int kSweepBlock = 1024;
-constexpr int kWaves = kSweepBlock / 64;
 constexpr int kGroup = 4;      // sites (chunks) per lane at a time
 constexpr int kUnroll = 8;     // neighbour indices loaded up front per site
 constexpr int kObsBlock = 256;
@@ -47,9 +45,9 @@ template <int kTrig> struct Trig;
 
 template <> struct Trig<0> {
     static constexpr size_t kBytes = 512 * 8;
-    static __device__ __forceinline__ void load(float2 *t, const DevBatch &b, int tid)
+    static __device__ __forceinline__ void load(float2 *t, const DevBatch &b, int tid, int stride)
     {
-        for (int k = tid; k < 512; k += kSweepBlock) t[k] = b.tab32[k];
+        for (int k = tid; k < 512; k += stride) t[k] = b.tab32[k];
     }
     static __device__ __forceinline__ float2 unit(uint32_t th, const float2 *t)
     {
@@ -60,9 +58,9 @@ template <> struct Trig<0> {
 
 template <> struct Trig<1> {
     static constexpr size_t kBytes = 2048 * 8;
-    static __device__ __forceinline__ void load(float2 *t, const DevBatch &b, int tid)
+    static __device__ __forceinline__ void load(float2 *t, const DevBatch &b, int tid, int stride)
     {
-        for (int k = tid; k < 2048; k += kSweepBlock) t[k] = b.tab2k[k];
+        for (int k = tid; k < 2048; k += stride) t[k] = b.tab2k[k];
     }
     static __device__ __forceinline__ float2 unit(uint32_t th, const float2 *t)
     {
@@ -75,7 +73,7 @@ template <> struct Trig<1> {
 
 template <> struct Trig<2> {
     static constexpr size_t kBytes = 0;
-    static __device__ __forceinline__ void load(float2 *, const DevBatch &, int) {}
+    static __device__ __forceinline__ void load(float2 *, const DevBatch &, int, int) {}
     static __device__ __forceinline__ float2 unit(uint32_t th, const float2 *)
     {
         // 1 + theta / 2^16 revolutions, built from the bits (exact); one whole
@@ -182,12 +180,41 @@ __device__ __forceinline__ void observe(const DevBatch &b, const SampleDesc &d, 
     dst[5] = mx; dst[6] = my; dst[7] = 0.0;
 }
 
+// Where a replica's spins live during a sweep, and how a site's FP32 unit
+// vector is obtained.  Angles (uint16, in LDS or global memory) evaluate
+// (cos, sin) at every use; kUnitLds keeps the unit vector of every site in LDS
+// (8 bytes per site, graphs of up to ~20k sites) next to the angles in global
+// memory, so a neighbour costs one LDS read.  The unit vectors are exactly
+// Trig<kTrig>::unit of the angles, so all three give identical trajectories.
+enum Mode { kAngLds = 0, kAngGlobal = 1, kUnitLds = 2 };
+
+template <int kMode, int kTrig> struct Spins {
+    uint16_t *ang;
+    const float2 *tab;
+    __device__ __forceinline__ float2 nbr(int j) const { return Trig<kTrig>::unit(ang[j], tab); }
+    __device__ __forceinline__ uint32_t angle(int i) const { return ang[i]; }
+    __device__ __forceinline__ float2 own(int, uint32_t th) const { return Trig<kTrig>::unit(th, tab); }
+    __device__ __forceinline__ float2 unit(uint32_t th) const { return Trig<kTrig>::unit(th, tab); }
+    __device__ __forceinline__ void set(int i, uint32_t th, float2) const { ang[i] = (uint16_t)th; }
+};
+
+template <int kTrig> struct Spins<kUnitLds, kTrig> {
+    uint16_t *ang;          // global memory
+    float2 *uv;             // LDS
+    const float2 *tab;
+    __device__ __forceinline__ float2 nbr(int j) const { return uv[j]; }
+    __device__ __forceinline__ uint32_t angle(int i) const { return ang[i]; }
+    __device__ __forceinline__ float2 own(int i, uint32_t) const { return uv[i]; }
+    __device__ __forceinline__ float2 unit(uint32_t th) const { return Trig<kTrig>::unit(th, tab); }
+    __device__ __forceinline__ void set(int i, uint32_t th, float2 u) const { ang[i] = (uint16_t)th; uv[i] = u; }
+};
+
 // One colour phase of one sub-sweep for this workgroup's replica: every site
 // of colour class [c0, c1) is updated once (Metropolis when sub == 0, else
 // over-relaxation).  Returns, when kLast, the energy of the links from the
 // updated sites to lower colours (their final values in the last sub-sweep).
-template <bool kLast, typename Idx, int kTrig>
-__device__ __forceinline__ double colour_phase(const SampleDesc &d, uint16_t *ang, const float2 *tab,
+template <bool kLast, int kWaves, typename Idx, typename Sp>
+__device__ __forceinline__ double colour_phase(const SampleDesc &d, const Sp &sp,
                                                const int32_t *cptr, const int32_t *cw, const Idx *col,
                                                const uint8_t *deg, int c0, int c1, int ch0, int nch, int wave,
                                                int lane, uint32_t sweep, int slot, int sub, float beta)
@@ -221,20 +248,20 @@ __device__ __forceinline__ double colour_phase(const SampleDesc &d, uint16_t *an
             for (int k = 0; k < kUnroll; ++k) {
                 if (k < wmin[r]) {
                     const int j = (int)jj[r][k];
-                    const float2 u = Trig<kTrig>::unit(ang[j], tab);
+                    const float2 u = sp.nbr(j);
                     hx[r] += u.x; hy[r] += u.y;
                     if (kLast && j < c0) { lx[r] += u.x; ly[r] += u.y; }
                 }
             }
             for (int k = kUnroll; k < wmin[r]; ++k) {                // wide chunks (uniform)
                 const int j = (int)col[base[r] + k * 64 + lane];
-                const float2 u = Trig<kTrig>::unit(ang[j], tab);
+                const float2 u = sp.nbr(j);
                 hx[r] += u.x; hy[r] += u.y;
                 if (kLast && j < c0) { lx[r] += u.x; ly[r] += u.y; }
             }
             for (int k = wmin[r]; k < dg[r]; ++k) {                   // lanes above the chunk minimum
                 const int j = (int)col[base[r] + k * 64 + lane];
-                const float2 u = Trig<kTrig>::unit(ang[j], tab);
+                const float2 u = sp.nbr(j);
                 hx[r] += u.x; hy[r] += u.y;
                 if (kLast && j < c0) { lx[r] += u.x; ly[r] += u.y; }
             }
@@ -248,15 +275,15 @@ __device__ __forceinline__ double colour_phase(const SampleDesc &d, uint16_t *an
 #pragma unroll
         for (int r = 0; r < kGroup; ++r) {
             if (site[r] >= c1 || g0 + r >= nch) continue;
-            const uint32_t th = ang[site[r]];
-            const float2 cur = Trig<kTrig>::unit(th, tab);
+            const uint32_t th = sp.angle(site[r]);
+            const float2 cur = sp.own(site[r], th);
             uint32_t th_new;
             if (sub == 0) {
                 th_new = words[r] & 0xFFFFu;                          // uniform proposal
             } else {
                 th_new = (field_axis2(hx[r], hy[r]) - th) & 0xFFFFu;   // reflection
             }
-            const float2 nu = Trig<kTrig>::unit(th_new, tab);
+            const float2 nu = sp.unit(th_new);
             const float dE = hx[r] * (cur.x - nu.x) + hy[r] * (cur.y - nu.y);
             bool accept = dE <= 0.f;
             if (!accept) {
@@ -277,7 +304,7 @@ __device__ __forceinline__ double colour_phase(const SampleDesc &d, uint16_t *an
                     }
                 }
             }
-            if (accept) ang[site[r]] = (uint16_t)th_new;
+            if (accept) sp.set(site[r], th_new, nu);
             if (kLast) {
                 const float2 f = accept ? nu : cur;
                 e_grp -= f.x * lx[r] + f.y * ly[r];
@@ -288,12 +315,14 @@ __device__ __forceinline__ double colour_phase(const SampleDesc &d, uint16_t *an
     return e_acc;
 }
 
-// LDS map: [double scratch kWaves*kNRed][trig table][uint16 angles n_pad (LDS variant)]
+// LDS map: [double scratch 16*kNRed][trig table][replica: uint16 angles
+// (kAngLds) or float2 unit vectors (kUnitLds), n_pad entries]
 constexpr size_t kOffTab = 1536;
 
-template <bool kLds, typename Idx, int kTrig>
-__global__ __launch_bounds__(kSweepBlock) void k_fix16_sweep(DevBatch b, const Item *items, int n_or, int measure)
+template <int kMode, int kTrig, int kBlock, typename Idx>
+__global__ __launch_bounds__(kBlock) void k_fix16_sweep(DevBatch b, const Item *items, int n_or, int measure)
 {
+    constexpr int kW = kBlock / 64;
     extern __shared__ __align__(16) unsigned char smem[];
     const Item it = items[blockIdx.x];
     if (it.sample < 0) return;
@@ -304,14 +333,22 @@ __global__ __launch_bounds__(kSweepBlock) void k_fix16_sweep(DevBatch b, const I
 
     double *scratch = reinterpret_cast<double *>(smem);
     float2 *tab = reinterpret_cast<float2 *>(smem + kOffTab);
+    unsigned char *rep = smem + kOffTab + Trig<kTrig>::kBytes;
     uint16_t *g_ang = static_cast<uint16_t *>(b.state) + d.state + (int64_t)slot * n_pad;
-    uint16_t *ang = kLds ? reinterpret_cast<uint16_t *>(smem + kOffTab + Trig<kTrig>::kBytes) : g_ang;
 
-    Trig<kTrig>::load(tab, b, tid);
-    if (kLds) {
+    Spins<kMode, kTrig> sp;
+    sp.tab = tab;
+    sp.ang = kMode == kAngLds ? reinterpret_cast<uint16_t *>(rep) : g_ang;
+    Trig<kTrig>::load(tab, b, tid, kBlock);
+    if constexpr (kMode == kAngLds) {
         const uint4 *src = reinterpret_cast<const uint4 *>(g_ang);
-        uint4 *dst = reinterpret_cast<uint4 *>(ang);
-        for (int k = tid; k < n_pad / 8; k += kSweepBlock) dst[k] = src[k];
+        uint4 *dst = reinterpret_cast<uint4 *>(rep);
+        for (int k = tid; k < n_pad / 8; k += kBlock) dst[k] = src[k];
+    }
+    if constexpr (kMode == kUnitLds) {
+        sp.uv = reinterpret_cast<float2 *>(rep);
+        __syncthreads();                                      // the table must be in place
+        for (int k = tid; k < n; k += kBlock) sp.uv[k] = Trig<kTrig>::unit(g_ang[k], tab);
     }
     __syncthreads();
 
@@ -329,11 +366,11 @@ __global__ __launch_bounds__(kSweepBlock) void k_fix16_sweep(DevBatch b, const I
             const int c0 = d.colour_off[c], c1 = d.colour_off[c + 1];
             const int ch0 = d.chunk_off[c], nch = d.chunk_off[c + 1] - ch0;
             if (last)
-                e_acc += colour_phase<true, Idx, kTrig>(d, ang, tab, cptr, cw, col, deg, c0, c1, ch0, nch, wave,
-                                                        lane, sweep, slot, sub, beta);
+                e_acc += colour_phase<true, kW, Idx>(d, sp, cptr, cw, col, deg, c0, c1, ch0, nch, wave, lane, sweep,
+                                                     slot, sub, beta);
             else
-                colour_phase<false, Idx, kTrig>(d, ang, tab, cptr, cw, col, deg, c0, c1, ch0, nch, wave, lane,
-                                                sweep, slot, sub, beta);
+                colour_phase<false, kW, Idx>(d, sp, cptr, cw, col, deg, c0, c1, ch0, nch, wave, lane, sweep, slot,
+                                             sub, beta);
             __syncthreads();
         }
     }
@@ -343,12 +380,12 @@ __global__ __launch_bounds__(kSweepBlock) void k_fix16_sweep(DevBatch b, const I
         block_sum<1>(v, scratch);
         if (tid == 0) b.E_slot[s * R + slot] = v[0];
     }
-    if (measure) observe<Idx>(b, d, ang, scratch, b.obs_slot + ((int64_t)s * R + slot) * XY_NOBS);
-    if (kLds) {
+    if (measure) observe<Idx>(b, d, sp.ang, scratch, b.obs_slot + ((int64_t)s * R + slot) * XY_NOBS);
+    if constexpr (kMode == kAngLds) {
         __syncthreads();
-        const uint4 *src = reinterpret_cast<const uint4 *>(ang);
+        const uint4 *src = reinterpret_cast<const uint4 *>(rep);
         uint4 *dst = reinterpret_cast<uint4 *>(g_ang);
-        for (int k = tid; k < n_pad / 8; k += kSweepBlock) dst[k] = src[k];
+        for (int k = tid; k < n_pad / 8; k += kBlock) dst[k] = src[k];
     }
 }
 
@@ -388,38 +425,47 @@ __global__ __launch_bounds__(kObsBlock) void k_fix16_observe(DevBatch b, double 
     b.E_slot[s * R + slot] = o[0];
 }
 
-template <bool kLds, typename Idx, int kTrig>
+template <int kMode, int kTrig, int kBlock, typename Idx>
 hipError_t launch_sweep_t(const DevBatch &b, const Item *items, int n_items, int n_or, int measure, size_t lds,
                           hipStream_t s)
 {
     static bool attr_set = false;
-    if (kLds && !attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fix16_sweep<kLds, Idx, kTrig>),
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fix16_sweep<kMode, kTrig, kBlock, Idx>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_fix16_sweep<kLds, Idx, kTrig>), dim3(n_items), dim3(kSweepBlock), lds, s, b, items,
+    hipLaunchKernelGGL((k_fix16_sweep<kMode, kTrig, kBlock, Idx>), dim3(n_items), dim3(kBlock), lds, s, b, items,
                        n_or, measure);
     return hipGetLastError();
 }
 
-template <bool kLds, typename Idx>
+template <int kMode, int kBlock, typename Idx>
 hipError_t launch_sweep_i(const DevBatch &b, const Item *items, int n_items, int n_or, int measure, size_t lds,
                           hipStream_t s)
 {
     switch (b.trig) {
-    case 0: return launch_sweep_t<kLds, Idx, 0>(b, items, n_items, n_or, measure, lds, s);
-    case 2: return launch_sweep_t<kLds, Idx, 2>(b, items, n_items, n_or, measure, lds, s);
-    default: return launch_sweep_t<kLds, Idx, 1>(b, items, n_items, n_or, measure, lds, s);
+    case 0: return launch_sweep_t<kMode, 0, kBlock, Idx>(b, items, n_items, n_or, measure, lds, s);
+    case 1: return launch_sweep_t<kMode, 1, kBlock, Idx>(b, items, n_items, n_or, measure, lds, s);
+    default: return launch_sweep_t<kMode, 2, kBlock, Idx>(b, items, n_items, n_or, measure, lds, s);
     }
+}
+
+template <int kMode, int kBlock>
+hipError_t launch_sweep_m(const DevBatch &b, const Item *items, int n_items, int n_or, int measure, size_t lds,
+                          hipStream_t s)
+{
+    return b.idx16 ? launch_sweep_i<kMode, kBlock, uint16_t>(b, items, n_items, n_or, measure, lds, s)
+                   : launch_sweep_i<kMode, kBlock, int32_t>(b, items, n_items, n_or, measure, lds, s);
 }
 
 }  // namespace
 
-size_t fix16_lds_bytes(int n_pad, int trig)
+size_t fix16_lds_bytes(int n_pad, int trig, int mode)
 {
-    const size_t tab = trig == 0 ? Trig<0>::kBytes : trig == 2 ? Trig<2>::kBytes : Trig<1>::kBytes;
-    return kOffTab + tab + 2 * (size_t)n_pad;
+    const size_t tab = trig == 0 ? Trig<0>::kBytes : trig == 1 ? Trig<1>::kBytes : Trig<2>::kBytes;
+    const size_t per_site = mode == kAngLds ? 2 : mode == kUnitLds ? 8 : 0;
+    return kOffTab + tab + per_site * (size_t)n_pad;
 }
 
 hipError_t launch_fix16_init(const DevBatch &b, int max_n, hipStream_t s)
@@ -430,16 +476,15 @@ hipError_t launch_fix16_init(const DevBatch &b, int max_n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_fix16_sweep(const DevBatch &b, const Item *items, int n_items, bool lds, int n_or,
+hipError_t launch_fix16_sweep(const DevBatch &b, const Item *items, int n_items, int mode, int block, int n_or,
                               int measure, size_t lds_bytes, hipStream_t s)
 {
     if (n_items == 0) return hipSuccess;
-    if (lds) {
-        return b.idx16 ? launch_sweep_i<true, uint16_t>(b, items, n_items, n_or, measure, lds_bytes, s)
-                       : launch_sweep_i<true, int32_t>(b, items, n_items, n_or, measure, lds_bytes, s);
-    }
-    return b.idx16 ? launch_sweep_i<false, uint16_t>(b, items, n_items, n_or, measure, lds_bytes, s)
-                   : launch_sweep_i<false, int32_t>(b, items, n_items, n_or, measure, lds_bytes, s);
+    if (mode == kUnitLds && block == 256)
+        return launch_sweep_m<kUnitLds, 256>(b, items, n_items, n_or, measure, lds_bytes, s);
+    if (mode == kUnitLds) return launch_sweep_m<kUnitLds, 1024>(b, items, n_items, n_or, measure, lds_bytes, s);
+    if (mode == kAngLds) return launch_sweep_m<kAngLds, 1024>(b, items, n_items, n_or, measure, lds_bytes, s);
+    return launch_sweep_m<kAngGlobal, 1024>(b, items, n_items, n_or, measure, lds_bytes, s);
 }
 
 hipError_t launch_fix16_observe(const DevBatch &b, double *out_by_T, hipStream_t s)

@@ -24,9 +24,9 @@ struct xy_batch {
     void *d_state = nullptr, *d_graph = nullptr, *d_work = nullptr, *d_obs = nullptr;
     DevBatch dev{};
     WorkLayout wl{};
-    Item *items_lds = nullptr, *items_glob = nullptr;
-    int n_items_lds = 0, n_items_glob = 0;
-    size_t lds_bytes_lds = 0, lds_bytes_glob = 0;
+    // fix16 launch groups: (storage mode, block size) with their work items
+    struct Group { int mode, block, n_items; size_t lds; Item *items; };
+    std::vector<Group> groups;
     uint32_t host_sweep = 0;
     // HIP graph replay of `chunk` sweeps of one shape
     int chunk = 0;
@@ -44,6 +44,12 @@ struct xy_batch {
 namespace {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+constexpr int kGroups = 4;   // fix16 launch groups
+// (storage mode, block size): unit vectors in LDS with 256 threads (graphs of
+// at most 4096 sites) or 1024, angles in LDS, angles in global memory
+constexpr int kGroupMode[kGroups] = {2, 2, 0, 1};
+constexpr int kGroupBlock[kGroups] = {256, 1024, 1024, 1024};
 
 xy_status hip_err(hipError_t e, const char *where)
 {
@@ -107,7 +113,7 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
         p.max_n = std::max(p.max_n, gr.n);
         p.Qmax = std::max(p.Qmax, gr.Q);
     }
-    p.item_cap = 8 * (size_t)G * R + 8;   // XCD interleave pads short queues
+    p.item_cap = 8 * (size_t)G * R + 8;   // XCD interleave pads short queues (per launch group)
     GraphLayout &gl = p.gl;
     size_t off = 0;
     gl.desc = off;      off = align_up(off + sizeof(SampleDesc) * G, 256);
@@ -116,7 +122,7 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
     gl.f64_pool = off;  off = align_up(off + 16 * n_f64, 256);
     gl.u16_pool = off;  off = align_up(off + 2 * n_u16, 256);
     gl.u8_pool = off;   off = align_up(off + n_u8, 256);
-    gl.items = off;     off = align_up(off + 2 * sizeof(Item) * p.item_cap, 256);
+    gl.items = off;     off = align_up(off + kGroups * sizeof(Item) * p.item_cap, 256);
     gl.tab32 = off;     off = align_up(off + 512 * 8, 256);
     gl.tab2k = off;     off = align_up(off + 2048 * 8, 256);
     gl.tab64 = off;     off = align_up(off + 512 * 16, 256);
@@ -298,28 +304,41 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
             (void)hipGetDevice(&dev);
             if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
                 lds_limit = 65536;
-            std::vector<int> in_lds, in_glob;
-            size_t lds_max = 0, glob_max = 0;
+            // XY_FIX16_GLOBAL=1 keeps every replica in global memory (the variant
+            // used for graphs too large for LDS); tests use it at small sizes
+            if (const char *env = std::getenv("XY_FIX16_GLOBAL"))
+                if (std::atoi(env) != 0) lds_limit = 0;
+            // XY_FIX16_NOUNIT=1 disables the unit-vector form (tests compare the forms)
+            bool allow_unit = true;
+            if (const char *env = std::getenv("XY_FIX16_NOUNIT"))
+                if (std::atoi(env) != 0) allow_unit = false;
+            std::vector<std::vector<int>> members(kGroups);
+            std::vector<size_t> lds_need(kGroups, 0);
             for (int s_ = 0; s_ < G; ++s_) {
                 const int n_pad = (p.desc[s_].n + 7) & ~7;
-                const size_t need = fix16_lds_bytes(n_pad, trig);
-                if (need <= (size_t)lds_limit) { in_lds.push_back(s_); lds_max = std::max(lds_max, need); }
-                else { in_glob.push_back(s_); glob_max = std::max(glob_max, fix16_lds_bytes(0, trig)); }
-            }
-            const std::vector<Item> a = xcd_order(in_lds, p.desc, R), c = xcd_order(in_glob, p.desc, R);
-            if (a.size() > p.item_cap || c.size() > p.item_cap) {
-                delete b;
-                return set_error(XY_EUNSUP, "xy_batch_init: work-item list exceeds its capacity");
+                int grp;
+                if (allow_unit && fix16_lds_bytes(n_pad, trig, 2) <= (size_t)lds_limit)
+                    grp = p.desc[s_].n <= 4096 ? 0 : 1;
+                else if (fix16_lds_bytes(n_pad, trig, 0) <= (size_t)lds_limit)
+                    grp = 2;
+                else
+                    grp = 3;
+                members[grp].push_back(s_);
+                lds_need[grp] = std::max(lds_need[grp], fix16_lds_bytes(grp == 3 ? 0 : n_pad, trig, kGroupMode[grp]));
             }
             Item *items = reinterpret_cast<Item *>(gimg.data() + gl.items);
-            std::copy(a.begin(), a.end(), items);
-            std::copy(c.begin(), c.end(), items + p.item_cap);
-            b->n_items_lds = (int)a.size();
-            b->n_items_glob = (int)c.size();
-            b->lds_bytes_lds = lds_max;
-            b->lds_bytes_glob = glob_max;
-            b->items_lds = reinterpret_cast<Item *>(static_cast<unsigned char *>(d_graph) + gl.items);
-            b->items_glob = b->items_lds + p.item_cap;
+            Item *d_items = reinterpret_cast<Item *>(static_cast<unsigned char *>(d_graph) + gl.items);
+            for (int k = 0; k < kGroups; ++k) {
+                const std::vector<Item> list = xcd_order(members[k], p.desc, R);
+                if (list.size() > p.item_cap) {
+                    delete b;
+                    return set_error(XY_EUNSUP, "xy_batch_init: work-item list exceeds its capacity");
+                }
+                std::copy(list.begin(), list.end(), items + k * p.item_cap);
+                if (!list.empty())
+                    b->groups.push_back({kGroupMode[k], kGroupBlock[k], (int)list.size(), lds_need[k],
+                                         d_items + k * p.item_cap});
+            }
         }
 
         // ---- work region image
@@ -416,9 +435,10 @@ hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream
         if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
         if (e == hipSuccess && (do_pt || do_rec)) e = launch_fp64_observe(b->dev, do_rec, nullptr, s);
     } else {
-        e = launch_fix16_sweep(b->dev, b->items_lds, b->n_items_lds, true, n_or, do_rec, b->lds_bytes_lds, s);
-        if (e == hipSuccess)
-            e = launch_fix16_sweep(b->dev, b->items_glob, b->n_items_glob, false, n_or, do_rec, b->lds_bytes_glob, s);
+        for (const auto &grp : b->groups) {
+            e = launch_fix16_sweep(b->dev, grp.items, grp.n_items, grp.mode, grp.block, n_or, do_rec, grp.lds, s);
+            if (e != hipSuccess) break;
+        }
         if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
     }
     if (e == hipSuccess) e = launch_end_sweep(b->dev, do_pt, do_rec, 1, s);

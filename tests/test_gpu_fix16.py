@@ -112,10 +112,19 @@ def test_tiny_graphs_exact_energy(name, n, edges, trig, monkeypatch):
         assert abs(m - _tiny_exact(name, 1 / t)) < 4 * err, (name, t, m, _tiny_exact(name, 1 / t), err)
 
 
-@pytest.mark.parametrize("trig", TRIG_FORMS)
-def test_l16_observables_match_oracle(trig, monkeypatch):
-    """fix16 on 128 independent chains of the L=16 graph vs the FP64 oracle (1e4 sweeps)."""
+def _set_form(monkeypatch, form):
+    """Storage form of the fixed-point sweep: unit vectors in LDS (default for
+    small graphs), angles in LDS, or angles in global memory."""
+    monkeypatch.setenv("XY_FIX16_NOUNIT", "0" if form == "unit" else "1")
+    monkeypatch.setenv("XY_FIX16_GLOBAL", "1" if form == "global" else "0")
+
+
+@pytest.mark.parametrize("trig,form", [(0, "lds"), (1, "lds"), (2, "lds"), (2, "global"), (2, "unit"), (0, "unit")])
+def test_l16_observables_match_oracle(trig, form, monkeypatch):
+    """fix16 on 128 independent chains of the L=16 graph vs the FP64 oracle (1e4 sweeps),
+    for each (cos, sin) form and spin storage form."""
     monkeypatch.setenv("XY_FIX16_TRIG", str(trig))
+    _set_form(monkeypatch, form)
     wl = workloads.plain_fp64_l16()
     s = wl.samples[0]
     e, _ = oracle.levy_graph(s.L, s.z, s.rho, s.seed)
@@ -162,6 +171,44 @@ def test_pt_batch_matches_fp64_gpu():
             zs.append(d.mean() / (d.std(ddof=1) / np.sqrt(len(d))))
     zs = np.array(zs)
     assert np.max(np.abs(zs)) < 4.0, zs
+
+
+@pytest.mark.parametrize("L", [32, 128])
+def test_storage_forms_give_identical_trajectories(L, monkeypatch):
+    """Unit vectors in LDS, angles in LDS and angles in global memory are the
+    same algorithm: identical spins and PT permutations on the same batch, and
+    records equal up to the order of the FP64 reductions."""
+    g = [xy.Graph.levy(L, 6, 2.5, s) for s in range(3)]
+    T = workloads.linear_ladder(1.0, 2.5, 5)
+    out = []
+    for form in ("unit", "lds", "global"):
+        _set_form(monkeypatch, form)
+        b = xy.Batch(g, T, precision="fix16", seeds=[7, 8, 9], max_records=10)
+        b.sweep(40, pt_every=1, meas_every=4)
+        out.append((b.get_state(), b.records().cpu().numpy()))
+    (sa, ra) = out[0]
+    for sb, rb in out[1:]:
+        assert all(np.array_equal(x, y) for x, y in zip(sa[0], sb[0]))
+        assert np.array_equal(sa[1], sb[1])
+        assert np.allclose(ra, rb, rtol=1e-12, atol=1e-12)
+
+
+def test_large_graph_uses_global_variant():
+    """L=512 replicas do not fit LDS; 3 sweeps with PT, then the measurement
+    kernel vs the oracle's measurement of the same state."""
+    g = xy.Graph.levy(512, 6, 2.5, 0)
+    T = np.array([1.5, 2.5, 3.5])
+    b = xy.Batch([g], T, precision="fix16", seeds=[0])
+    b.sweep(3, pt_every=1, meas_every=0)
+    o = b.measure().cpu().numpy()[0]
+    st, sot, sw = b.get_state()
+    assert sw == 3
+    e, _ = oracle.levy_graph(512, 6, 2.5, 0)
+    col, _ = oracle.slo_colour(512 * 512, e)
+    sim = oracle.Sim(512 * 512, e, col, 512, T, 0)
+    sim.set_state(_unit(st[0]), sot[0], sw)
+    ref = sim.measure()
+    assert np.allclose(o[:, :7], ref[:, :7], rtol=1e-10, atol=1e-9)
 
 
 def test_graph_replay_equals_direct_launches():
