@@ -11,7 +11,7 @@
 // load, and all indices of a site are in flight before the first is used.
 // Each lane updates four sites of one colour at a time (four chunks), which
 // overlaps their latencies and lets one Philox4x32-10 call supply the random
-// words of all four updates.  The workgroups of one sample are placed on one
+// words of four Metropolis updates or of eight over-relaxation updates.  The workgroups of one sample are placed on one
 // XCD by the item order the host builds, so they share its graph in that L2.
 //
 // Over-relaxation on the clock model: theta' = (q - theta) mod 2^16 with
@@ -220,7 +220,9 @@ __device__ __forceinline__ double colour_phase(const SampleDesc &d, const Sp &sp
                                                int lane, uint32_t sweep, int slot, int sub, float beta)
 {
     double e_acc = 0.0;
-    for (int g0 = wave * kGroup; g0 < nch; g0 += kWaves * kGroup) {
+    U4 w_or = {0u, 0u, 0u, 0u};
+    int it = 0;
+    for (int g0 = wave * kGroup; g0 < nch; g0 += kWaves * kGroup, ++it) {
         // chunk records are the same for the whole wave: scalar loads
         int site[kGroup], dg[kGroup], base[kGroup], wmin[kGroup];
         Idx jj[kGroup][kUnroll];
@@ -267,10 +269,22 @@ __device__ __forceinline__ double colour_phase(const SampleDesc &d, const Sp &sp
             }
         }
 
-        // one Philox call: word r drives the update of site r
-        const U4 w = philox4x32_10({(uint32_t)site[0], sweep, (uint32_t)slot,
-                                    tag(sub == 0 ? kMet : kOR, (uint32_t)sub)}, d.seed_lo, d.seed_hi);
-        const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+        // Random words: Metropolis takes one Philox call per group (word r =
+        // 16 proposal bits | 16 uniform bits for site r); over-relaxation
+        // needs 16 uniform bits per site, so one call serves this group and the
+        // wave's next one (low halves, then high halves).
+        uint32_t words[4];
+        if (sub == 0) {
+            const U4 w = philox4x32_10({(uint32_t)site[0], sweep, (uint32_t)slot, tag(kMet)}, d.seed_lo, d.seed_hi);
+            words[0] = w.x; words[1] = w.y; words[2] = w.z; words[3] = w.w;
+        } else {
+            if ((it & 1) == 0)
+                w_or = philox4x32_10({(uint32_t)site[0], sweep, (uint32_t)slot, tag(kOR, (uint32_t)sub)},
+                                     d.seed_lo, d.seed_hi);
+            const int sh = (it & 1) ? 16 : 0;
+            words[0] = (w_or.x >> sh) << 16; words[1] = (w_or.y >> sh) << 16;
+            words[2] = (w_or.z >> sh) << 16; words[3] = (w_or.w >> sh) << 16;
+        }
         float e_grp = 0.f;
 #pragma unroll
         for (int r = 0; r < kGroup; ++r) {
@@ -287,21 +301,17 @@ __device__ __forceinline__ double colour_phase(const SampleDesc &d, const Sp &sp
             const float dE = hx[r] * (cur.x - nu.x) + hy[r] * (cur.y - nu.y);
             bool accept = dE <= 0.f;
             if (!accept) {
+                // 16 uniform bits (the top half of the word), extended by 32
+                // more only on a tie: accept iff U < p exactly for p in FP32
                 const float p = __expf(-beta * dE);
-                if (sub != 0) {
-                    accept = (float)(words[r] >> 8) * 0x1.0p-24f < p;
+                const float p16 = p * 65536.0f;
+                const uint32_t u16 = words[r] >> 16, f = (uint32_t)p16;
+                if (u16 != f) {
+                    accept = u16 < f;
                 } else {
-                    // 16 uniform bits, extended by 32 more only on a tie:
-                    // accept iff U < p exactly for p in FP32
-                    const float p16 = p * 65536.0f;
-                    const uint32_t u16 = words[r] >> 16, f = (uint32_t)p16;
-                    if (u16 != f) {
-                        accept = u16 < f;
-                    } else {
-                        const U4 x = philox4x32_10({(uint32_t)site[r], sweep, (uint32_t)slot, tag(kMetAcc)},
-                                                   d.seed_lo, d.seed_hi);
-                        accept = (double)x.x < (double)(p16 - (float)f) * 4294967296.0;
-                    }
+                    const U4 x = philox4x32_10({(uint32_t)site[r], sweep, (uint32_t)slot, tag(kMetAcc, (uint32_t)sub)},
+                                               d.seed_lo, d.seed_hi);
+                    accept = (double)x.x < (double)(p16 - (float)f) * 4294967296.0;
                 }
             }
             if (accept) sp.set(site[r], th_new, nu);

@@ -84,3 +84,30 @@ def test_from_edges_and_errors():
         xy.Graph.levy(2, 3, 1.0, 0)           # z >= N - 1 with N = 4
     with pytest.raises(xy.XYError, match="EINVAL"):
         xy.Graph.from_edges(2, [(0, 1)], L=4, coords=[(0, 0), (4, 0)])   # coordinate outside [0, L)
+
+
+def test_batch_argument_errors_without_device():
+    """Argument checks of the batch entry points happen before any device call."""
+    import ctypes
+    g = xy.Graph.levy(8, 6, 3.5, 0)
+    garr = (ctypes.c_void_p * 1)(g._h.value)
+    sz = _lib.Sizes()
+    raw = _lib.raw()
+    assert raw.xy_batch_sizes(garr, 1, 0, 1, 0, ctypes.byref(sz)) == _lib.XY_EINVAL        # n_T = 0
+    assert raw.xy_batch_sizes(garr, 1, 257, 1, 0, ctypes.byref(sz)) == _lib.XY_EINVAL      # n_T > 256
+    assert raw.xy_batch_sizes(garr, 1, 4, 7, 0, ctypes.byref(sz)) == _lib.XY_EINVAL        # precision
+    assert raw.xy_batch_sizes(garr, 0, 4, 1, 0, ctypes.byref(sz)) == _lib.XY_EINVAL        # no graphs
+    assert raw.xy_batch_sizes(garr, 1, 4, 1, 5, ctypes.byref(sz)) == _lib.XY_OK
+    assert sz.state_bytes >= 64 * 4 * 2 and sz.obs_bytes >= 5 * 4 * 8 * 8
+    h = ctypes.c_void_p()
+    T = np.array([1.0, -1.0, 2.0, 3.0])
+    seeds = np.zeros(1, np.uint64)
+    st = raw.xy_batch_init(ctypes.byref(h), garr, 1, 4, T.ctypes.data_as(ctypes.c_void_p), 1,
+                           seeds.ctypes.data_as(ctypes.c_void_p), 0, None, None, None, None, None)
+    assert st == _lib.XY_EINVAL and b"temperatures" in raw.xy_last_error()
+    T = np.array([1.0, 1.5, 2.0, 3.0])
+    st = raw.xy_batch_init(ctypes.byref(h), garr, 1, 4, T.ctypes.data_as(ctypes.c_void_p), 1,
+                           seeds.ctypes.data_as(ctypes.c_void_p), 0, None, None, None, None, None)
+    assert st == _lib.XY_EINVAL and b"NULL device buffer" in raw.xy_last_error()
+    assert raw.xy_sweep(None, 1, 5, 1, 1, None) == _lib.XY_EINVAL
+    assert raw.xy_measure(None, None, None) == _lib.XY_EINVAL
