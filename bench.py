@@ -50,6 +50,7 @@ def time_gpu(wl, precision, steps, warmup, graphs, torch, xy):
     stream = torch.cuda.Stream()
     b = xy.Batch(graphs, wl.T, precision=precision, seeds=[s.seed for s in wl.samples],
                  max_records=max(1, (steps + warmup) // wl.meas_every + 1), stream=stream)
+    tune = b.autotune(n_or=wl.n_or, use_cache=False) if precision == "fix16" else None
     b.sweep(warmup, n_or=wl.n_or, pt_every=wl.pt_every, meas_every=wl.meas_every)
     b.synchronize()
     b.kernel_timing(True)
@@ -67,7 +68,7 @@ def time_gpu(wl, precision, steps, warmup, graphs, torch, xy):
     rec = b.records().cpu().numpy()
     b.close()
     return {"ms": ms, "kernel_ms": k_ms / max(k_n, 1), "kernel_n": k_n, "records": rec,
-            "pt_rate": float(acc.sum()) / max(float(tries.sum()), 1.0)}
+            "pt_rate": float(acc.sum()) / max(float(tries.sum()), 1.0), "autotune": tune}
 
 
 def cpu_baseline(wl, seconds):
@@ -149,7 +150,8 @@ def main():
             traffic = tr["bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_fix16_sweep<true>" if args.precision == "fix16" else "k_fp64_phase (all phases of a sweep)",
+                "kernel": ("k_fix16_sweep (one launch = one sweep of every (sample, slot))" if args.precision == "fix16"
+                           else "k_fp64_phase (all colour-phase launches of a sweep)"),
                 "kernel_ms": round(k_ms, 4), "alg_bytes_per_update": round(bpu, 3),
                 "updates_per_launch": upd_per_sweep}
 
@@ -179,6 +181,7 @@ def main():
         "fp64_plain": fp64,
         "cpu_baseline": cpu,
         "pt_acceptance": round(main_run["pt_rate"], 4),
+        "autotune": main_run["autotune"],
     }
     print(json.dumps(out), flush=True)
 

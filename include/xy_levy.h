@@ -188,6 +188,18 @@ xy_status xy_batch_use_graph(xy_batch *b, int chunk);
 xy_status xy_kernel_timing(xy_batch *b, int enable);
 xy_status xy_kernel_time(xy_batch *b, double *ms_total, int *n_timed);
 
+/* Fixed-point sweep configuration (fix16 batches; used by the autotuner).
+ *   trig        : (cos, sin) of a 16-bit angle: 0 two-level LDS table, 1 2048-entry
+ *                 LDS table with a small-angle rotation, 2 hardware sine/cosine
+ *   allow_unit  : keep FP32 unit vectors in LDS for graphs that fit (else angles)
+ *   force_global: keep every replica in global memory
+ * Each choice samples the clock model with its own FP32 (cos, sin); all are
+ * exact Metropolis samplers.  Synchronises `stream`, then uploads the new
+ * work-item lists.  Initial values: trig 2, allow_unit 1, force_global 0
+ * (the environment variables XY_FIX16_TRIG, XY_FIX16_NOUNIT and
+ * XY_FIX16_GLOBAL override them at xy_batch_init). */
+xy_status xy_batch_set_fix16_form(xy_batch *b, int trig, int allow_unit, int force_global, void *stream);
+
 const char *xy_last_error(void);
 void xy_batch_free(xy_batch *b);
 

@@ -131,6 +131,16 @@ class Batch:
     def use_graph(self, chunk):
         _lib.call("xy_batch_use_graph", self._h, int(chunk))
 
+    def set_fix16_form(self, trig=2, allow_unit=True, force_global=False):
+        """(cos, sin) form and spin storage of the fixed-point sweep (see xy_levy.h)."""
+        _lib.call("xy_batch_set_fix16_form", self._h, int(trig), int(bool(allow_unit)), int(bool(force_global)),
+                  self._s())
+
+    def autotune(self, sweeps=3, n_or=5, use_cache=True):
+        """Times the fixed-point configurations on this batch and keeps the fastest."""
+        from .autotune import autotune
+        return autotune(self, sweeps=sweeps, n_or=n_or, use_cache=use_cache)
+
     def kernel_timing(self, enable=True):
         _lib.call("xy_kernel_timing", self._h, int(bool(enable)))
 

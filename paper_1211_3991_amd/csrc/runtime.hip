@@ -27,6 +27,10 @@ struct xy_batch {
     // fix16 launch groups: (storage mode, block size) with their work items
     struct Group { int mode, block, n_items; size_t lds; Item *items; };
     std::vector<Group> groups;
+    std::vector<SampleDesc> desc_host;        // fix16: for regrouping
+    size_t item_cap = 0;
+    Item *d_items = nullptr;
+    int lds_limit = 0;
     uint32_t host_sweep = 0;
     // HIP graph replay of `chunk` sweeps of one shape
     int chunk = 0;
@@ -176,6 +180,41 @@ std::vector<Item> xcd_order(const std::vector<int> &samples, const std::vector<S
     return out;
 }
 
+// Splits the samples of a fix16 batch into launch groups by the storage form
+// that fits: unit vectors in LDS (block 256 up to 4096 sites, else 1024),
+// angles in LDS, angles in global memory; writes each group's XCD-ordered
+// items at items + k * item_cap.  Returns false if a list overflows.
+bool build_groups(xy_batch *b, int trig, bool allow_unit, bool force_global, Item *items)
+{
+    const int G = b->G, R = b->R;
+    const size_t limit = force_global ? 0 : (size_t)b->lds_limit;
+    std::vector<std::vector<int>> members(kGroups);
+    std::vector<size_t> lds_need(kGroups, 0);
+    for (int s_ = 0; s_ < G; ++s_) {
+        const int n_pad = (b->desc_host[s_].n + 7) & ~7;
+        int grp;
+        if (allow_unit && fix16_lds_bytes(n_pad, trig, 2) <= limit)
+            grp = b->desc_host[s_].n <= 4096 ? 0 : 1;
+        else if (fix16_lds_bytes(n_pad, trig, 0) <= limit)
+            grp = 2;
+        else
+            grp = 3;
+        members[grp].push_back(s_);
+        lds_need[grp] = std::max(lds_need[grp], fix16_lds_bytes(grp == 3 ? 0 : n_pad, trig, kGroupMode[grp]));
+    }
+    b->groups.clear();
+    for (int k = 0; k < kGroups; ++k) {
+        const std::vector<Item> list = xcd_order(members[k], b->desc_host, R);
+        if (list.size() > b->item_cap) return false;
+        std::copy(list.begin(), list.end(), items + k * b->item_cap);
+        if (!list.empty())
+            b->groups.push_back({kGroupMode[k], kGroupBlock[k], (int)list.size(), lds_need[k],
+                                 b->d_items + k * b->item_cap});
+    }
+    b->dev.trig = trig;
+    return true;
+}
+
 }  // namespace
 
 extern "C" xy_status xy_batch_sizes(const xy_graph *const *g, int n_graphs, int n_T, int precision,
@@ -306,38 +345,21 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
                 lds_limit = 65536;
             // XY_FIX16_GLOBAL=1 keeps every replica in global memory (the variant
             // used for graphs too large for LDS); tests use it at small sizes
+            bool force_global = false;
             if (const char *env = std::getenv("XY_FIX16_GLOBAL"))
-                if (std::atoi(env) != 0) lds_limit = 0;
+                if (std::atoi(env) != 0) force_global = true;
             // XY_FIX16_NOUNIT=1 disables the unit-vector form (tests compare the forms)
             bool allow_unit = true;
             if (const char *env = std::getenv("XY_FIX16_NOUNIT"))
                 if (std::atoi(env) != 0) allow_unit = false;
-            std::vector<std::vector<int>> members(kGroups);
-            std::vector<size_t> lds_need(kGroups, 0);
-            for (int s_ = 0; s_ < G; ++s_) {
-                const int n_pad = (p.desc[s_].n + 7) & ~7;
-                int grp;
-                if (allow_unit && fix16_lds_bytes(n_pad, trig, 2) <= (size_t)lds_limit)
-                    grp = p.desc[s_].n <= 4096 ? 0 : 1;
-                else if (fix16_lds_bytes(n_pad, trig, 0) <= (size_t)lds_limit)
-                    grp = 2;
-                else
-                    grp = 3;
-                members[grp].push_back(s_);
-                lds_need[grp] = std::max(lds_need[grp], fix16_lds_bytes(grp == 3 ? 0 : n_pad, trig, kGroupMode[grp]));
-            }
+            b->desc_host = p.desc;
+            b->item_cap = p.item_cap;
+            b->lds_limit = lds_limit;
+            b->d_items = reinterpret_cast<Item *>(static_cast<unsigned char *>(d_graph) + gl.items);
             Item *items = reinterpret_cast<Item *>(gimg.data() + gl.items);
-            Item *d_items = reinterpret_cast<Item *>(static_cast<unsigned char *>(d_graph) + gl.items);
-            for (int k = 0; k < kGroups; ++k) {
-                const std::vector<Item> list = xcd_order(members[k], p.desc, R);
-                if (list.size() > p.item_cap) {
-                    delete b;
-                    return set_error(XY_EUNSUP, "xy_batch_init: work-item list exceeds its capacity");
-                }
-                std::copy(list.begin(), list.end(), items + k * p.item_cap);
-                if (!list.empty())
-                    b->groups.push_back({kGroupMode[k], kGroupBlock[k], (int)list.size(), lds_need[k],
-                                         d_items + k * p.item_cap});
+            if (!build_groups(b, trig, allow_unit, force_global, items)) {
+                delete b;
+                return set_error(XY_EUNSUP, "xy_batch_init: work-item list exceeds its capacity");
             }
         }
 
@@ -690,6 +712,27 @@ extern "C" xy_status xy_kernel_time(xy_batch *b, double *ms_total, int *n_timed)
     }
     if (ms_total) *ms_total = total;
     if (n_timed) *n_timed = (int)b->events_used;
+    return XY_OK;
+}
+
+extern "C" xy_status xy_batch_set_fix16_form(xy_batch *b, int trig, int allow_unit, int force_global, void *stream)
+{
+    if (!b) return set_error(XY_EINVAL, "xy_batch_set_fix16_form: batch is NULL");
+    if (b->precision != XY_FIX16) return set_error(XY_EUNSUP, "xy_batch_set_fix16_form: fix16 batches only");
+    if (trig < 0 || trig > 2) return set_error(XY_EINVAL, "xy_batch_set_fix16_form: trig must be 0, 1 or 2");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    try {
+        std::vector<Item> items(kGroups * b->item_cap, Item{-1, -1});
+        if (!build_groups(b, trig, allow_unit != 0, force_global != 0, items.data())) return set_error(XY_EUNSUP, "xy_batch_set_fix16_form: work-item list exceeds its capacity");
+        hipError_t e = hipStreamSynchronize(s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_err(e, "xy_batch_set_fix16_form");
+    } catch (const std::bad_alloc &) {
+        return set_error(XY_ENOMEM, "xy_batch_set_fix16_form: out of memory");
+    }
+    if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
     return XY_OK;
 }
 

@@ -230,3 +230,20 @@ def test_graph_replay_equals_direct_launches():
     graph.sweep(3, pt_every=1, meas_every=4)      # a remainder that is not a whole chunk
     eager.sweep(3, pt_every=1, meas_every=4)
     assert all(np.array_equal(x, y) for x, y in zip(eager.get_state()[0], graph.get_state()[0]))
+
+
+def test_autotune_restores_state_and_applies_choice(tmp_path, monkeypatch):
+    monkeypatch.setenv("XY_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    g = [xy.Graph.levy(32, 6, 3.5, s) for s in range(8)] + [xy.Graph.levy(128, 6, 3.5, 9)]
+    b = xy.Batch(g, workloads.linear_ladder(1.0, 2.5, 4), precision="fix16", max_records=4)
+    b.sweep(5, pt_every=1, meas_every=0)
+    before = b.get_state()
+    rep = b.autotune(sweeps=2)
+    assert rep["tuned"] and not rep["cached"] and len(rep["ms_per_sweep"]) == 6
+    after = b.get_state()
+    assert after[2] == before[2] == 5 and np.array_equal(after[1], before[1])
+    assert all(np.array_equal(x, y) for x, y in zip(after[0], before[0]))
+    b.sweep(4, pt_every=1, meas_every=2)
+    assert b.counters()[0] == 2
+    rep2 = b.autotune()
+    assert rep2["cached"] and (rep2["trig"], rep2["allow_unit"]) == (rep["trig"], rep["allow_unit"])
