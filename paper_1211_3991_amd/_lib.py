@@ -37,6 +37,13 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                       "(the HIP library is required, there is no fallback)")
 
+# PyTorch ships its own HIP runtime (soname libamdhip64.so.7).  Loading torch
+# first makes the library's libamdhip64.so.7 dependency resolve to that same,
+# already loaded runtime, so device pointers and streams handed over by torch
+# belong to the runtime the library calls.  Loading the library first would
+# bring in a second HIP runtime from the system ROCm.
+import torch  # noqa: E402,F401
+
 _c = ctypes.CDLL(LIB_PATH)
 _vp, _i32, _u32, _u64, _dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
 _sigs = {

@@ -111,3 +111,10 @@ def test_batch_argument_errors_without_device():
     assert st == _lib.XY_EINVAL and b"NULL device buffer" in raw.xy_last_error()
     assert raw.xy_sweep(None, 1, 5, 1, 1, None) == _lib.XY_EINVAL
     assert raw.xy_measure(None, None, None) == _lib.XY_EINVAL
+
+
+def test_single_hip_runtime_in_process():
+    """The library shares PyTorch's HIP runtime (one libamdhip64 mapped)."""
+    maps = open("/proc/self/maps").read()
+    paths = {ln.split()[-1] for ln in maps.splitlines() if "libamdhip64" in ln}
+    assert len(paths) == 1, paths
