@@ -118,7 +118,7 @@ xy_status finish_graph(xy_graph &g)
     return XY_OK;
 }
 
-Sell build_sell(const xy_graph &g)
+Sell build_sell(const xy_graph &g, int window)
 {
     Sell S;
     const int n = g.n, Q = g.Q;
@@ -126,12 +126,18 @@ Sell build_sell(const xy_graph &g)
     S.deg.resize(n);
     S.chunk_off.assign(Q + 1, 0);
     std::vector<int32_t> inv(n);
+    // degree sort inside windows of `window` consecutive sites of a class: the
+    // chunks get nearly uniform degree, and a small window still covers a
+    // compact band of the lattice (neighbour gathers from global memory keep
+    // their locality)
+    if (window < 64) window = 64;
     for (int c = 0; c < Q; ++c) {
         const int c0 = g.colour_off[c], c1 = g.colour_off[c + 1];
         std::iota(S.order.begin() + c0, S.order.begin() + c1, c0);
-        std::stable_sort(S.order.begin() + c0, S.order.begin() + c1, [&](int a, int b) {
-            return g.row_ptr[a + 1] - g.row_ptr[a] > g.row_ptr[b + 1] - g.row_ptr[b];
-        });
+        for (int w0 = c0; w0 < c1; w0 += window)
+            std::stable_sort(S.order.begin() + w0, S.order.begin() + std::min(c1, w0 + window), [&](int a, int b) {
+                return g.row_ptr[a + 1] - g.row_ptr[a] > g.row_ptr[b + 1] - g.row_ptr[b];
+            });
         S.chunk_off[c + 1] = S.chunk_off[c] + (c1 - c0 + 63) / 64;
     }
     for (int k = 0; k < n; ++k) {

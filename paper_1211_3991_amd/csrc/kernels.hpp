@@ -44,7 +44,7 @@ hipError_t launch_end_sweep(const DevBatch &b, int do_pt, int do_record, int adv
 // fix16 path (kernels_fix16.hip).
 hipError_t launch_fix16_init(const DevBatch &b, int max_n, hipStream_t s);
 // mode: 0 angles in LDS, 1 angles in global memory, 2 unit vectors in LDS
-// (angles in global memory); block: 256 or 1024 threads (mode 2 only takes 256)
+// (angles in global memory); block: mode 2 takes 256 or 1024, mode 0 1024, mode 1 512
 hipError_t launch_fix16_sweep(const DevBatch &b, const Item *items, int n_items, int mode, int block,
                               int n_or, int measure, size_t lds_bytes, hipStream_t s);
 hipError_t launch_fix16_observe(const DevBatch &b, double *out_by_T, hipStream_t s);

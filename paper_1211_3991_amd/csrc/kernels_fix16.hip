@@ -11,7 +11,7 @@
 // load, and all indices of a site are in flight before the first is used.
 // Each lane updates four sites of one colour at a time (four chunks), which
 // overlaps their latencies and lets one Philox4x32-10 call supply the random
-// words of four Metropolis updates or of eight over-relaxation updates.  The workgroups of one sample are placed on one
+// words of all four updates.  The workgroups of one sample are placed on one
 // XCD by the item order the host builds, so they share its graph in that L2.
 //
 // Over-relaxation on the clock model: theta' = (q - theta) mod 2^16 with
@@ -26,7 +26,6 @@
 namespace xy {
 namespace {
 
-constexpr int kGroup = 4;      // sites (chunks) per lane at a time
 constexpr int kUnroll = 8;     // neighbour indices loaded up front per site
 constexpr int kObsBlock = 256;
 constexpr int kNRed = 11;      // E, m_x, m_y, 4 Fourier sums along x, 4 along y
@@ -213,16 +212,15 @@ template <int kTrig> struct Spins<kUnitLds, kTrig> {
 // of colour class [c0, c1) is updated once (Metropolis when sub == 0, else
 // over-relaxation).  Returns, when kLast, the energy of the links from the
 // updated sites to lower colours (their final values in the last sub-sweep).
-template <bool kLast, int kWaves, typename Idx, typename Sp>
+template <bool kLast, int kWaves, int kGroup, typename Idx, typename Sp>
 __device__ __forceinline__ double colour_phase(const SampleDesc &d, const Sp &sp,
                                                const int32_t *cptr, const int32_t *cw, const Idx *col,
                                                const uint8_t *deg, int c0, int c1, int ch0, int nch, int wave,
                                                int lane, uint32_t sweep, int slot, int sub, float beta)
 {
+    static_assert(kGroup == 1 || kGroup == 2 || kGroup == 4, "groups must tile the 4-chunk key groups");
     double e_acc = 0.0;
-    U4 w_or = {0u, 0u, 0u, 0u};
-    int it = 0;
-    for (int g0 = wave * kGroup; g0 < nch; g0 += kWaves * kGroup, ++it) {
+    for (int g0 = wave * kGroup; g0 < nch; g0 += kWaves * kGroup) {
         // chunk records are the same for the whole wave: scalar loads
         int site[kGroup], dg[kGroup], base[kGroup], wmin[kGroup];
         Idx jj[kGroup][kUnroll];
@@ -269,21 +267,20 @@ __device__ __forceinline__ double colour_phase(const SampleDesc &d, const Sp &sp
             }
         }
 
-        // Random words: Metropolis takes one Philox call per group (word r =
-        // 16 proposal bits | 16 uniform bits for site r); over-relaxation
-        // needs 16 uniform bits per site, so one call serves this group and the
-        // wave's next one (low halves, then high halves).
-        uint32_t words[4];
-        if (sub == 0) {
-            const U4 w = philox4x32_10({(uint32_t)site[0], sweep, (uint32_t)slot, tag(kMet)}, d.seed_lo, d.seed_hi);
-            words[0] = w.x; words[1] = w.y; words[2] = w.z; words[3] = w.w;
-        } else {
-            if ((it & 1) == 0)
-                w_or = philox4x32_10({(uint32_t)site[0], sweep, (uint32_t)slot, tag(kOR, (uint32_t)sub)},
-                                     d.seed_lo, d.seed_hi);
-            const int sh = (it & 1) ? 16 : 0;
-            words[0] = (w_or.x >> sh) << 16; words[1] = (w_or.y >> sh) << 16;
-            words[2] = (w_or.z >> sh) << 16; words[3] = (w_or.w >> sh) << 16;
+        // Random words: one Philox call per 4-chunk key group (chunks 4m..4m+3
+        // of the colour class), keyed by the first chunk's site of this lane;
+        // word (chunk mod 4) drives that chunk's site.  The keying depends on
+        // the site only, never on the launch shape, so every storage form and
+        // block size gives the same trajectory.  Metropolis: 16 proposal bits
+        // | 16 uniform bits; over-relaxation: the top 16 bits as the uniform.
+        uint32_t words[kGroup];
+        {
+            const int kg0 = g0 & ~3;
+            const U4 w = philox4x32_10({(uint32_t)(c0 + kg0 * 64 + lane), sweep, (uint32_t)slot,
+                                        tag(sub == 0 ? kMet : kOR, (uint32_t)sub)}, d.seed_lo, d.seed_hi);
+            const uint32_t all[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int r = 0; r < kGroup; ++r) words[r] = all[(g0 - kg0 + r) & 3];
         }
         float e_grp = 0.f;
 #pragma unroll
@@ -333,6 +330,9 @@ template <int kMode, int kTrig, int kBlock, typename Idx>
 __global__ __launch_bounds__(kBlock) void k_fix16_sweep(DevBatch b, const Item *items, int n_or, int measure)
 {
     constexpr int kW = kBlock / 64;
+    // sites per lane at a time: 4 where the replica is in LDS; 2 from global
+    // memory (fewer registers, so two workgroups share a CU to hide latency)
+    constexpr int kG = kMode == kAngGlobal ? 2 : 4;
     extern __shared__ __align__(16) unsigned char smem[];
     const Item it = items[blockIdx.x];
     if (it.sample < 0) return;
@@ -376,10 +376,10 @@ __global__ __launch_bounds__(kBlock) void k_fix16_sweep(DevBatch b, const Item *
             const int c0 = d.colour_off[c], c1 = d.colour_off[c + 1];
             const int ch0 = d.chunk_off[c], nch = d.chunk_off[c + 1] - ch0;
             if (last)
-                e_acc += colour_phase<true, kW, Idx>(d, sp, cptr, cw, col, deg, c0, c1, ch0, nch, wave, lane, sweep,
+                e_acc += colour_phase<true, kW, kG, Idx>(d, sp, cptr, cw, col, deg, c0, c1, ch0, nch, wave, lane, sweep,
                                                      slot, sub, beta);
             else
-                colour_phase<false, kW, Idx>(d, sp, cptr, cw, col, deg, c0, c1, ch0, nch, wave, lane, sweep, slot,
+                colour_phase<false, kW, kG, Idx>(d, sp, cptr, cw, col, deg, c0, c1, ch0, nch, wave, lane, sweep, slot,
                                              sub, beta);
             __syncthreads();
         }
@@ -494,7 +494,7 @@ hipError_t launch_fix16_sweep(const DevBatch &b, const Item *items, int n_items,
         return launch_sweep_m<kUnitLds, 256>(b, items, n_items, n_or, measure, lds_bytes, s);
     if (mode == kUnitLds) return launch_sweep_m<kUnitLds, 1024>(b, items, n_items, n_or, measure, lds_bytes, s);
     if (mode == kAngLds) return launch_sweep_m<kAngLds, 1024>(b, items, n_items, n_or, measure, lds_bytes, s);
-    return launch_sweep_m<kAngGlobal, 1024>(b, items, n_items, n_or, measure, lds_bytes, s);
+    return launch_sweep_m<kAngGlobal, 512>(b, items, n_items, n_or, measure, lds_bytes, s);
 }
 
 hipError_t launch_fix16_observe(const DevBatch &b, double *out_by_T, hipStream_t s)

@@ -51,9 +51,10 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 constexpr int kGroups = 4;   // fix16 launch groups
 // (storage mode, block size): unit vectors in LDS with 256 threads (graphs of
-// at most 4096 sites) or 1024, angles in LDS, angles in global memory
+// at most 4096 sites) or 1024, angles in LDS, angles in global memory with 512
+// threads (several workgroups per CU hide the latency of the gathers)
 constexpr int kGroupMode[kGroups] = {2, 2, 0, 1};
-constexpr int kGroupBlock[kGroups] = {256, 1024, 1024, 1024};
+constexpr int kGroupBlock[kGroups] = {256, 1024, 1024, 512};
 
 xy_status hip_err(hipError_t e, const char *where)
 {
@@ -97,7 +98,7 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
             d.row_ptr = (int64_t)n_i32; n_i32 += gr.n + 1;
             d.col = (int64_t)n_i32;     n_i32 += 2 * (size_t)gr.m;
         } else {
-            p.sell[s] = build_sell(gr);
+            p.sell[s] = build_sell(gr, sell_window(gr.n));
             const Sell &S = p.sell[s];
             d.sell_ptr = (int64_t)n_i32; n_i32 += S.chunk_ptr.size();
             d.sell_w = (int64_t)n_i32;   n_i32 += S.chunk_w.size();

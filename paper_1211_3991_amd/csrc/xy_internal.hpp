@@ -130,8 +130,9 @@ struct GraphLayout {
 };
 
 // Sliced-ELL form of a graph used by the fixed-point sweep.  Sites are
-// renumbered inside each colour class by decreasing degree (ties: colour-major
-// order), so the 64 sites of a chunk have nearly equal degree; chunk columns
+// renumbered inside each colour class by decreasing degree within windows of
+// consecutive sites (ties: colour-major order), so the 64 sites of a chunk
+// have nearly equal degree; chunk columns
 // are stored k-major ([k][lane]) so that the k-th neighbour loads of a wave are
 // contiguous.  Padding entries hold 0 and are skipped through the degree.
 struct Sell {
@@ -142,7 +143,13 @@ struct Sell {
     std::vector<uint8_t> deg;
     std::vector<int32_t> chunk_off;  // Q + 1
 };
-Sell build_sell(const xy_graph &g);
+// window: sites per degree-sorted window (the whole class when >= n).
+Sell build_sell(const xy_graph &g, int window);
+
+// Window for a graph of n sites: whole classes when a replica fits in LDS
+// (n <= 65536 on gfx950; neighbour locality is irrelevant there and uniform
+// chunks matter), 4096-site windows otherwise (gathers from global memory).
+inline int sell_window(int n) { return n <= 65536 ? n : 4096; }
 
 // One fix16 work item: a (sample, slot) pair run by one workgroup.
 struct Item { int32_t sample, slot; };

@@ -247,3 +247,35 @@ def test_autotune_restores_state_and_applies_choice(tmp_path, monkeypatch):
     assert b.counters()[0] == 2
     rep2 = b.autotune()
     assert rep2["cached"] and (rep2["trig"], rep2["allow_unit"]) == (rep["trig"], rep["allow_unit"])
+
+
+def test_full_headline_shape_sampled():
+    """64 x L=256 x 24 T, the benchmark's launch configuration (autotuned form):
+    after 6 sweeps with PT the fused record of the last sweep equals a
+    standalone measurement of the same state, samples 0 and 37 of it equal the
+    oracle's measurement of that state, and every PT pair was attempted on its
+    parity's sweeps."""
+    wl = workloads.headline_l256()
+    graphs = [xy.Graph.levy(s.L, s.z, s.rho, s.seed) for s in wl.samples]
+    b = xy.Batch(graphs, wl.T, precision="fix16", seeds=[s.seed for s in wl.samples], max_records=4)
+    b.autotune(sweeps=1, use_cache=False)
+    b.sweep(6, pt_every=1, meas_every=3)
+    nrec, acc, tries = b.counters()
+    assert nrec == 2
+    rec = b.records().cpu().numpy()
+    o = b.measure().cpu().numpy()
+    assert np.allclose(rec[-1], o, rtol=1e-12, atol=1e-9)
+    st, sot, sw = b.get_state()
+    assert sw == 6
+    for k in (0, 37):
+        s = wl.samples[k]
+        e, _ = oracle.levy_graph(s.L, s.z, s.rho, s.seed)
+        col, _ = oracle.slo_colour(s.L * s.L, e)
+        sim = oracle.Sim(s.L * s.L, e, col, s.L, wl.T, s.seed)
+        sim.set_state(_unit(st[k]), sot[k], sw)
+        ref = sim.measure()
+        assert np.allclose(o[k, :, :7], ref[:, :7], rtol=1e-10, atol=1e-8), k
+    # pairs (k, k+1) with k even are tried on even sweeps (0, 2, 4), odd k on odd sweeps
+    R = wl.n_T
+    expect = np.array([3 if k % 2 == 0 else 3 for k in range(R - 1)] + [0])
+    assert np.array_equal(tries[0].astype(int), expect)
