@@ -50,4 +50,14 @@ hipError_t launch_fix16_sweep(const DevBatch &b, const Item *items, int n_items,
 hipError_t launch_fix16_observe(const DevBatch &b, double *out_by_T, hipStream_t s);
 size_t fix16_lds_bytes(int n_pad, int trig, int mode);
 
+// fix16 phase form (site-major state, one launch per colour phase) for the
+// samples listed in phase_samples[n_phase]; sites_per_block(R) sites per block.
+int fix16_phase_sites_per_block(int R);
+hipError_t launch_fix16_phase(const DevBatch &b, const int32_t *phase_samples, int n_phase, int colour, int sub,
+                              int max_blocks, hipStream_t s);
+// Energies (and, when full, observables) of the phase-form samples: two
+// deterministic stages through b.partial.
+hipError_t launch_fix16_observe_sm(const DevBatch &b, const int32_t *phase_samples, int n_phase, int full,
+                                   hipStream_t s);
+
 }  // namespace xy

@@ -133,7 +133,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *scratch)
 // E = -sum_links cos(theta_i - theta_j) (each link once, at its higher
 // endpoint), m = (1/N) sum S_j, F_a = |sum_j S_j e^{i 2pi a_j/L}|^2/N.
 template <typename Idx>
-__device__ __forceinline__ void observe(const DevBatch &b, const SampleDesc &d, const uint16_t *ang,
+__device__ __forceinline__ void observe(const DevBatch &b, const SampleDesc &d, const uint16_t *ang, int stride,
                                         double *scratch, double *dst)
 {
     const int32_t *cptr = b.i32 + d.sell_ptr;
@@ -149,13 +149,13 @@ __device__ __forceinline__ void observe(const DevBatch &b, const SampleDesc &d, 
         for (int ch = wave; ch < d.chunk_off[c + 1] - ch0; ch += nw) {
             const int i = c0 + ch * 64 + lane;
             if (i >= c1) continue;
-            const double2 si = unit64(ang[i], t64);
+            const double2 si = unit64(ang[(int64_t)i * stride], t64);
             const int base = cptr[ch0 + ch], dg = deg[i];
             double e = 0.0;
             for (int k = 0; k < dg; ++k) {
                 const int j = (int)col[base + k * 64 + lane];
                 if (j < i) {
-                    const double2 sj = unit64(ang[j], t64);
+                    const double2 sj = unit64(ang[(int64_t)j * stride], t64);
                     e += si.x * sj.x + si.y * sj.y;
                 }
             }
@@ -177,6 +177,22 @@ __device__ __forceinline__ void observe(const DevBatch &b, const SampleDesc &d, 
     dst[3] = (v[3] * v[3] + v[4] * v[4] + v[5] * v[5] + v[6] * v[6]) / N;
     dst[4] = (v[7] * v[7] + v[8] * v[8] + v[9] * v[9] + v[10] * v[10]) / N;
     dst[5] = mx; dst[6] = my; dst[7] = 0.0;
+}
+
+// Metropolis acceptance with probability min(1, exp(-beta dE)) for the FP32
+// exp.  The uniform is the top 16 bits of `word`; on a tie with the 16-bit
+// threshold (probability 2^-16) 32 more bits are drawn from the counter
+// (site, sweep, slot, purpose 4 | sub), so the test is exact: U < p.
+__device__ __forceinline__ bool accept_move(float dE, float beta, uint32_t word, uint32_t site, uint32_t sweep,
+                                            uint32_t slot, uint32_t sub, const SampleDesc &d)
+{
+    if (dE <= 0.f) return true;
+    const float p = __expf(-beta * dE);
+    const float p16 = p * 65536.0f;
+    const uint32_t u16 = word >> 16, f = (uint32_t)p16;
+    if (u16 != f) return u16 < f;
+    const U4 x = philox4x32_10({site, sweep, slot, tag(kMetAcc, sub)}, d.seed_lo, d.seed_hi);
+    return (double)x.x < (double)(p16 - (float)f) * 4294967296.0;
 }
 
 // Where a replica's spins live during a sweep, and how a site's FP32 unit
@@ -296,21 +312,8 @@ __device__ __forceinline__ double colour_phase(const SampleDesc &d, const Sp &sp
             }
             const float2 nu = sp.unit(th_new);
             const float dE = hx[r] * (cur.x - nu.x) + hy[r] * (cur.y - nu.y);
-            bool accept = dE <= 0.f;
-            if (!accept) {
-                // 16 uniform bits (the top half of the word), extended by 32
-                // more only on a tie: accept iff U < p exactly for p in FP32
-                const float p = __expf(-beta * dE);
-                const float p16 = p * 65536.0f;
-                const uint32_t u16 = words[r] >> 16, f = (uint32_t)p16;
-                if (u16 != f) {
-                    accept = u16 < f;
-                } else {
-                    const U4 x = philox4x32_10({(uint32_t)site[r], sweep, (uint32_t)slot, tag(kMetAcc, (uint32_t)sub)},
-                                               d.seed_lo, d.seed_hi);
-                    accept = (double)x.x < (double)(p16 - (float)f) * 4294967296.0;
-                }
-            }
+            const bool accept = accept_move(dE, beta, words[r], (uint32_t)site[r], sweep, (uint32_t)slot,
+                                            (uint32_t)sub, d);
             if (accept) sp.set(site[r], th_new, nu);
             if (kLast) {
                 const float2 f = accept ? nu : cur;
@@ -390,7 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_fix16_sweep(DevBatch b, const Item *
         block_sum<1>(v, scratch);
         if (tid == 0) b.E_slot[s * R + slot] = v[0];
     }
-    if (measure) observe<Idx>(b, d, sp.ang, scratch, b.obs_slot + ((int64_t)s * R + slot) * XY_NOBS);
+    if (measure) observe<Idx>(b, d, sp.ang, 1, scratch, b.obs_slot + ((int64_t)s * R + slot) * XY_NOBS);
     if constexpr (kMode == kAngLds) {
         __syncthreads();
         const uint4 *src = reinterpret_cast<const uint4 *>(rep);
@@ -407,7 +410,10 @@ __global__ __launch_bounds__(256) void k_fix16_init(DevBatch b)
     const int n_pad = (d.n + 7) & ~7;
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= (int64_t)n_pad * b.R) return;
-    const int slot = (int)(t / n_pad), site = (int)(t % n_pad);
+    // element t of the sample's block: slot-major [slot][site_pad] or
+    // site-major [site][slot]; the value depends on (site, slot) only
+    const int slot = d.layout ? (int)(t % b.R) : (int)(t / n_pad);
+    const int site = d.layout ? (int)(t / b.R) : (int)(t % n_pad);
     uint16_t *S = static_cast<uint16_t *>(b.state) + d.state;
     uint16_t v = 0;
     if (site < d.n) {
@@ -425,14 +431,161 @@ __global__ __launch_bounds__(kObsBlock) void k_fix16_observe(DevBatch b, double 
     const int slot = blockIdx.x, s = blockIdx.y, R = b.R;
     const SampleDesc &d = b.desc[s];
     const int n_pad = (d.n + 7) & ~7;
-    const uint16_t *ang = static_cast<const uint16_t *>(b.state) + d.state + (int64_t)slot * n_pad;
+    const uint16_t *ang = static_cast<const uint16_t *>(b.state) + d.state +
+                          (d.layout ? (int64_t)slot : (int64_t)slot * n_pad);
     double o[XY_NOBS];
-    observe<Idx>(b, d, ang, scratch, o);
+    observe<Idx>(b, d, ang, d.layout ? R : 1, scratch, o);
     if (threadIdx.x != 0) return;
     double *dst = out_by_T ? out_by_T + ((int64_t)s * R + b.T_of_slot[s * R + slot]) * XY_NOBS
                            : b.obs_slot + ((int64_t)s * R + slot) * XY_NOBS;
     for (int q = 0; q < XY_NOBS; ++q) dst[q] = o[q];
     b.E_slot[s * R + slot] = o[0];
+}
+
+// Phase form (graphs too large for LDS): the state of a sample is site-major,
+// [site][slot], and one launch updates one colour class of all phase-form
+// samples.  Thread (site, q) updates slots 4q..4q+3 of one site: the
+// neighbour index is read once for the four slots and their four angles are
+// one 8-byte load, so graph and gather traffic are shared by four replicas.
+// Random words: one Philox call per (site, sweep, slot 4q), word r for slot
+// 4q + r.  (cos, sin) is the hardware form.
+constexpr int kPhaseBlock = 256;
+
+template <typename Idx>
+__global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const int32_t *phase_samples, int colour,
+                                                            int sub)
+{
+    const int R = b.R, Lq = R >> 2, S = kPhaseBlock / Lq;
+    const int t = threadIdx.x, q = t % Lq, sl = t / Lq;
+    if (sl >= S) return;
+    const int s = phase_samples[blockIdx.y];
+    const SampleDesc &d = b.desc[s];
+    if (colour >= d.Q) return;
+    const int c0 = d.colour_off[colour], c1 = d.colour_off[colour + 1];
+    const int i = c0 + blockIdx.x * S + sl;
+    if (i >= c1) return;
+    const int rel = i - c0, ln = rel & 63;
+    const int base = b.i32[d.sell_ptr + d.chunk_off[colour] + (rel >> 6)];
+    const Idx *col = reinterpret_cast<const Idx *>(sizeof(Idx) == 2 ? (const void *)b.u16 : (const void *)b.i32) + d.sell_col;
+    const int dg = b.u8[d.deg + i];
+    uint2 *A = reinterpret_cast<uint2 *>(static_cast<uint16_t *>(b.state) + d.state);   // [site][Lq] x 4 angles
+
+    float hx[4] = {0.f, 0.f, 0.f, 0.f}, hy[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < dg; ++k) {
+        const int j = (int)col[base + k * 64 + ln];
+        const uint2 v = A[(int64_t)j * Lq + q];
+        const uint32_t th[4] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float2 u = Trig<2>::unit(th[r], nullptr);
+            hx[r] += u.x; hy[r] += u.y;
+        }
+    }
+    const uint32_t sweep = b.ctl->sweep;
+    const U4 w = philox4x32_10({(uint32_t)i, sweep, (uint32_t)(4 * q), tag(sub == 0 ? kMet : kOR, (uint32_t)sub)},
+                               d.seed_lo, d.seed_hi);
+    const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+    const uint2 me = A[(int64_t)i * Lq + q];
+    const uint32_t cur_th[4] = {me.x & 0xFFFFu, me.x >> 16, me.y & 0xFFFFu, me.y >> 16};
+    uint32_t out[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int slot = 4 * q + r;
+        const float beta = (float)b.beta[s * R + b.T_of_slot[s * R + slot]];
+        const uint32_t th = cur_th[r];
+        const uint32_t th_new = sub == 0 ? (words[r] & 0xFFFFu) : ((field_axis2(hx[r], hy[r]) - th) & 0xFFFFu);
+        const float2 cur = Trig<2>::unit(th, nullptr), nu = Trig<2>::unit(th_new, nullptr);
+        const float dE = hx[r] * (cur.x - nu.x) + hy[r] * (cur.y - nu.y);
+        out[r] = accept_move(dE, beta, words[r], (uint32_t)i, sweep, (uint32_t)slot, (uint32_t)sub, d) ? th_new : th;
+    }
+    A[(int64_t)i * Lq + q] = make_uint2(out[0] | (out[1] << 16), out[2] | (out[3] << 16));
+}
+
+// Energies (and observables when full) of the phase-form samples, stage 1:
+// block b of a sample covers a contiguous site range for all slots; thread t
+// takes slot t % R of sites t / R, t / R + nsl, ... (whole [site][slot] rows
+// per warp); FP64 unit vectors of the 16-bit angles.  Each link is counted
+// once, at its higher endpoint.  Stage 2 adds the kObsBlocks partials in
+// block order.
+constexpr int kObsBlocks = 64;
+
+template <typename Idx>
+__global__ __launch_bounds__(kObsBlock) void k_fix16_observe_sm_partial(DevBatch b, const int32_t *phase_samples,
+                                                                       int full)
+{
+    __shared__ double red[kObsBlock * kNRed];
+    const int s = phase_samples[blockIdx.y], R = b.R;
+    const SampleDesc &d = b.desc[s];
+    const int nsl = kObsBlock / R, t = threadIdx.x, slot = t % R, sl = t / R;
+    const int per = (d.n + kObsBlocks - 1) / kObsBlocks;
+    const int i0 = blockIdx.x * per, i1 = min(d.n, i0 + per);
+    double v[kNRed] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (sl < nsl) {
+        const uint16_t *A = static_cast<const uint16_t *>(b.state) + d.state;
+        const int32_t *cptr = b.i32 + d.sell_ptr;
+        const Idx *col = reinterpret_cast<const Idx *>(sizeof(Idx) == 2 ? (const void *)b.u16 : (const void *)b.i32) + d.sell_col;
+        const uint8_t *deg = b.u8 + d.deg;
+        const uint32_t *xy = b.u32 + d.coord;
+        const double2 *trig = b.f64 + d.trig;
+        const double2 *t64 = b.tab64;
+        int c = 0;
+        for (int i = i0 + sl; i < i1; i += nsl) {
+            while (i >= d.colour_off[c + 1]) ++c;
+            const int rel = i - d.colour_off[c];
+            const int base = cptr[d.chunk_off[c] + (rel >> 6)], ln = rel & 63;
+            const double2 si = unit64(A[(int64_t)i * R + slot], t64);
+            double e = 0.0;
+            for (int k = 0; k < deg[i]; ++k) {
+                const int j = (int)col[base + k * 64 + ln];
+                if (j < i) {
+                    const double2 sj = unit64(A[(int64_t)j * R + slot], t64);
+                    e += si.x * sj.x + si.y * sj.y;
+                }
+            }
+            v[0] -= e;
+            if (full) {
+                const uint32_t p = xy[i];
+                const double2 ex = trig[p & 0xFFFFu], ey = trig[p >> 16];
+                v[1] += si.x; v[2] += si.y;
+                v[3] += si.x * ex.x; v[4] += si.x * ex.y; v[5] += si.y * ex.x; v[6] += si.y * ex.y;
+                v[7] += si.x * ey.x; v[8] += si.x * ey.y; v[9] += si.y * ey.x; v[10] += si.y * ey.y;
+            }
+        }
+    }
+    for (int qq = 0; qq < kNRed; ++qq) red[t * kNRed + qq] = v[qq];
+    __syncthreads();
+    if (t < R) {
+        for (int qq = 0; qq < kNRed; ++qq) {
+            double acc = 0.0;
+            for (int k = 0; k < nsl; ++k) acc += red[(k * R + t) * kNRed + qq];
+            b.partial[(((int64_t)blockIdx.y * kObsBlocks + blockIdx.x) * R + t) * kNRed + qq] = acc;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kObsBlock) void k_fix16_observe_sm_final(DevBatch b, const int32_t *phase_samples,
+                                                                     int n_phase, int full)
+{
+    const int R = b.R;
+    const int64_t t = (int64_t)blockIdx.x * kObsBlock + threadIdx.x;
+    if (t >= (int64_t)n_phase * R) return;
+    const int k = (int)(t / R), slot = (int)(t % R), s = phase_samples[k];
+    const SampleDesc &d = b.desc[s];
+    double v[kNRed];
+    for (int qq = 0; qq < kNRed; ++qq) v[qq] = 0.0;
+    for (int blk = 0; blk < kObsBlocks; ++blk)
+        for (int qq = 0; qq < kNRed; ++qq) v[qq] += b.partial[(((int64_t)k * kObsBlocks + blk) * R + slot) * kNRed + qq];
+    b.E_slot[s * R + slot] = v[0];
+    if (!full) return;
+    const double N = (double)d.n;
+    const double mx = v[1] / N, my = v[2] / N, m2 = mx * mx + my * my;
+    double *dst = b.obs_slot + ((int64_t)s * R + slot) * XY_NOBS;
+    dst[0] = v[0];
+    dst[1] = m2;
+    dst[2] = m2 * m2;
+    dst[3] = (v[3] * v[3] + v[4] * v[4] + v[5] * v[5] + v[6] * v[6]) / N;
+    dst[4] = (v[7] * v[7] + v[8] * v[8] + v[9] * v[9] + v[10] * v[10]) / N;
+    dst[5] = mx; dst[6] = my; dst[7] = 0.0;
 }
 
 template <int kMode, int kTrig, int kBlock, typename Idx>
@@ -495,6 +648,37 @@ hipError_t launch_fix16_sweep(const DevBatch &b, const Item *items, int n_items,
     if (mode == kUnitLds) return launch_sweep_m<kUnitLds, 1024>(b, items, n_items, n_or, measure, lds_bytes, s);
     if (mode == kAngLds) return launch_sweep_m<kAngLds, 1024>(b, items, n_items, n_or, measure, lds_bytes, s);
     return launch_sweep_m<kAngGlobal, 512>(b, items, n_items, n_or, measure, lds_bytes, s);
+}
+
+int fix16_phase_sites_per_block(int R) { return kPhaseBlock / (R / 4); }
+
+hipError_t launch_fix16_phase(const DevBatch &b, const int32_t *phase_samples, int n_phase, int colour, int sub,
+                              int max_blocks, hipStream_t s)
+{
+    if (n_phase == 0 || max_blocks == 0) return hipSuccess;
+    dim3 grid((unsigned)max_blocks, (unsigned)n_phase);
+    if (b.idx16)
+        hipLaunchKernelGGL(k_fix16_phase<uint16_t>, grid, dim3(kPhaseBlock), 0, s, b, phase_samples, colour, sub);
+    else
+        hipLaunchKernelGGL(k_fix16_phase<int32_t>, grid, dim3(kPhaseBlock), 0, s, b, phase_samples, colour, sub);
+    return hipGetLastError();
+}
+
+hipError_t launch_fix16_observe_sm(const DevBatch &b, const int32_t *phase_samples, int n_phase, int full,
+                                   hipStream_t s)
+{
+    if (n_phase == 0) return hipSuccess;
+    dim3 grid(kObsBlocks, (unsigned)n_phase);
+    if (b.idx16)
+        hipLaunchKernelGGL(k_fix16_observe_sm_partial<uint16_t>, grid, dim3(kObsBlock), 0, s, b, phase_samples, full);
+    else
+        hipLaunchKernelGGL(k_fix16_observe_sm_partial<int32_t>, grid, dim3(kObsBlock), 0, s, b, phase_samples, full);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)n_phase * b.R;
+    hipLaunchKernelGGL(k_fix16_observe_sm_final, dim3((unsigned)((n + kObsBlock - 1) / kObsBlock)), dim3(kObsBlock),
+                       0, s, b, phase_samples, n_phase, full);
+    return hipGetLastError();
 }
 
 hipError_t launch_fix16_observe(const DevBatch &b, double *out_by_T, hipStream_t s)

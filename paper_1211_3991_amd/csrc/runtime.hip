@@ -28,6 +28,10 @@ struct xy_batch {
     struct Group { int mode, block, n_items; size_t lds; Item *items; };
     std::vector<Group> groups;
     std::vector<SampleDesc> desc_host;        // fix16: for regrouping
+    // fix16 phase form (site-major samples, one launch per colour phase)
+    int n_phase = 0;
+    int32_t *d_phase = nullptr;
+    std::vector<int> phase_max_blocks;        // per colour
     size_t item_cap = 0;
     Item *d_items = nullptr;
     int lds_limit = 0;
@@ -90,6 +94,12 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
     }
     p.idx16 = fix16 && max_n <= 65536;
     if (fix16) p.sell.resize(G);
+    // phase form for graphs too large for LDS (site-major state); needs the
+    // slots in groups of four.  XY_FIX16_PHASE=1 puts every sample in it (tests).
+    bool force_phase = false;
+    if (const char *env = std::getenv("XY_FIX16_PHASE"))
+        if (std::atoi(env) != 0) force_phase = true;
+    int n_phase = 0;
     for (int s = 0; s < G; ++s) {
         const xy_graph &gr = *g[s];
         SampleDesc &d = p.desc[s];
@@ -112,6 +122,8 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
         d.coord = (int64_t)n_u32;   n_u32 += align_up(gr.n, 4);
         d.trig = (int64_t)n_f64;    n_f64 += gr.L;
         for (int c = 0; c <= kMaxColours; ++c) d.colour_off[c] = gr.colour_off[std::min(c, gr.Q)];
+        d.layout = (fix16 && R % 4 == 0 && (force_phase || gr.n > 65536)) ? 1 : 0;
+        n_phase += d.layout;
         d.state = (int64_t)state_elems;
         p.state_off[s] = d.state;
         state_elems += fix16 ? (size_t)((gr.n + 7) & ~7) * R : (size_t)gr.n * R;
@@ -128,6 +140,7 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
     gl.u16_pool = off;  off = align_up(off + 2 * n_u16, 256);
     gl.u8_pool = off;   off = align_up(off + n_u8, 256);
     gl.items = off;     off = align_up(off + kGroups * sizeof(Item) * p.item_cap, 256);
+    gl.phase = off;     off = align_up(off + 4 * (size_t)G, 256);
     gl.tab32 = off;     off = align_up(off + 512 * 8, 256);
     gl.tab2k = off;     off = align_up(off + 2048 * 8, 256);
     gl.tab64 = off;     off = align_up(off + 512 * 16, 256);
@@ -144,7 +157,7 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
     wl.obs_slot = off;  off = align_up(off + 8 * XY_NOBS * GR, 256);
     wl.pt_acc = off;    off = align_up(off + 8 * GR, 256);
     wl.pt_try = off;    off = align_up(off + 8 * GR, 256);
-    wl.partial = off;   off = align_up(off + (fix16 ? 0 : 8 * 64 * 11 * GR), 256);
+    wl.partial = off;   off = align_up(off + ((fix16 && n_phase == 0) ? 0 : 8 * 64 * 11 * GR), 256);
     wl.total = off;
     p.state_bytes = align_up(state_elems * (precision == XY_FP64 ? 16 : 2), 256);
     p.obs_bytes = align_up((size_t)max_records * GR * XY_NOBS * 8, 256);
@@ -192,6 +205,7 @@ bool build_groups(xy_batch *b, int trig, bool allow_unit, bool force_global, Ite
     std::vector<std::vector<int>> members(kGroups);
     std::vector<size_t> lds_need(kGroups, 0);
     for (int s_ = 0; s_ < G; ++s_) {
+        if (b->desc_host[s_].layout) continue;          // phase form
         const int n_pad = (b->desc_host[s_].n + 7) & ~7;
         int grp;
         if (allow_unit && fix16_lds_bytes(n_pad, trig, 2) <= limit)
@@ -357,6 +371,22 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
             b->item_cap = p.item_cap;
             b->lds_limit = lds_limit;
             b->d_items = reinterpret_cast<Item *>(static_cast<unsigned char *>(d_graph) + gl.items);
+            std::vector<int32_t> phase;
+            b->phase_max_blocks.assign(p.Qmax, 0);
+            const int spb = R % 4 == 0 ? fix16_phase_sites_per_block(R) : 1;
+            for (int s_ = 0; s_ < G; ++s_) {
+                if (!p.desc[s_].layout) continue;
+                const int k = (int)phase.size();
+                phase.push_back(s_);
+                for (int c = 0; c < p.desc[s_].Q; ++c) {
+                    const int size_c = p.desc[s_].colour_off[c + 1] - p.desc[s_].colour_off[c];
+                    b->phase_max_blocks[c] = std::max(b->phase_max_blocks[c], (size_c + spb - 1) / spb);
+                }
+                (void)k;
+            }
+            std::copy(phase.begin(), phase.end(), reinterpret_cast<int32_t *>(gimg.data() + gl.phase));
+            b->n_phase = (int)phase.size();
+            b->d_phase = reinterpret_cast<int32_t *>(static_cast<unsigned char *>(d_graph) + gl.phase);
             Item *items = reinterpret_cast<Item *>(gimg.data() + gl.items);
             if (!build_groups(b, trig, allow_unit, force_global, items)) {
                 delete b;
@@ -461,6 +491,13 @@ hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream
         for (const auto &grp : b->groups) {
             e = launch_fix16_sweep(b->dev, grp.items, grp.n_items, grp.mode, grp.block, n_or, do_rec, grp.lds, s);
             if (e != hipSuccess) break;
+        }
+        if (e == hipSuccess && b->n_phase > 0) {
+            for (int sub = 0; sub <= n_or && e == hipSuccess; ++sub)
+                for (int c = 0; c < (int)b->phase_max_blocks.size() && e == hipSuccess; ++c)
+                    e = launch_fix16_phase(b->dev, b->d_phase, b->n_phase, c, sub, b->phase_max_blocks[c], s);
+            if (e == hipSuccess && (do_pt || do_rec))
+                e = launch_fix16_observe_sm(b->dev, b->d_phase, b->n_phase, do_rec, s);
         }
         if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
     }
@@ -578,10 +615,12 @@ extern "C" xy_status xy_get_state(xy_batch *b, void *h_state, int32_t *h_slot_of
                     out_off += 2 * (size_t)R * n;
                 } else {
                     const int n_pad = (n + 7) & ~7;
+                    const bool site_major = b->desc_host[g].layout != 0;
                     const uint16_t *src = reinterpret_cast<const uint16_t *>(raw.data()) + b->state_off[g];
                     uint16_t *dst = static_cast<uint16_t *>(h_state) + out_off;
                     for (int r = 0; r < R; ++r)
-                        for (int k = 0; k < n; ++k) dst[(size_t)r * n + pm[k]] = src[(size_t)r * n_pad + k];
+                        for (int k = 0; k < n; ++k)
+                            dst[(size_t)r * n + pm[k]] = site_major ? src[(size_t)k * R + r] : src[(size_t)r * n_pad + k];
                     out_off += (size_t)R * n;
                 }
             }
@@ -630,10 +669,12 @@ extern "C" xy_status xy_set_state(xy_batch *b, const void *h_state, const int32_
                     in_off += 2 * (size_t)R * n;
                 } else {
                     const int n_pad = (n + 7) & ~7;
+                    const bool site_major = b->desc_host[g].layout != 0;
                     uint16_t *dst = reinterpret_cast<uint16_t *>(raw.data()) + b->state_off[g];
                     const uint16_t *src = static_cast<const uint16_t *>(h_state) + in_off;
                     for (int r = 0; r < R; ++r)
-                        for (int k = 0; k < n; ++k) dst[(size_t)r * n_pad + k] = src[(size_t)r * n + pm[k]];
+                        for (int k = 0; k < n; ++k)
+                            (site_major ? dst[(size_t)k * R + r] : dst[(size_t)r * n_pad + k]) = src[(size_t)r * n + pm[k]];
                     in_off += (size_t)R * n;
                 }
             }

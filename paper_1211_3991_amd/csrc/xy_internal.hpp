@@ -108,6 +108,8 @@ struct SampleDesc {
     int64_t sell_col;     // fix16: u16 or int32 pool, columns chunk by chunk, [k][lane] inside a chunk
     int64_t deg;          // fix16: u8 pool, degree by site
     uint32_t seed_lo, seed_hi;
+    int32_t layout;       // fix16 state: 0 slot-major [slot][site_pad], 1 site-major [site][slot]
+    int32_t pad_;
     int32_t colour_off[kMaxColours + 1];
     int32_t chunk_off[kMaxColours + 1];   // fix16: first chunk of each colour class
 };
@@ -125,7 +127,7 @@ struct WorkLayout {
 };
 
 struct GraphLayout {
-    size_t desc, i32_pool, u32_pool, f64_pool, u16_pool, u8_pool, items, tab32, tab2k, tab64, total;
+    size_t desc, i32_pool, u32_pool, f64_pool, u16_pool, u8_pool, items, phase, tab32, tab2k, tab64, total;
     size_t n_i32, n_u32, n_f64, n_u16, n_u8;
 };
 

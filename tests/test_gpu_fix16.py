@@ -114,12 +114,15 @@ def test_tiny_graphs_exact_energy(name, n, edges, trig, monkeypatch):
 
 def _set_form(monkeypatch, form):
     """Storage form of the fixed-point sweep: unit vectors in LDS (default for
-    small graphs), angles in LDS, or angles in global memory."""
+    small graphs), angles in LDS, angles in global memory, or the phase form
+    (site-major state, one launch per colour phase; default for large graphs)."""
     monkeypatch.setenv("XY_FIX16_NOUNIT", "0" if form == "unit" else "1")
     monkeypatch.setenv("XY_FIX16_GLOBAL", "1" if form == "global" else "0")
+    monkeypatch.setenv("XY_FIX16_PHASE", "1" if form == "phase" else "0")
 
 
-@pytest.mark.parametrize("trig,form", [(0, "lds"), (1, "lds"), (2, "lds"), (2, "global"), (2, "unit"), (0, "unit")])
+@pytest.mark.parametrize("trig,form", [(0, "lds"), (1, "lds"), (2, "lds"), (2, "global"), (2, "unit"), (0, "unit"),
+                                       (2, "phase")])
 def test_l16_observables_match_oracle(trig, form, monkeypatch):
     """fix16 on 128 independent chains of the L=16 graph vs the FP64 oracle (1e4 sweeps),
     for each (cos, sin) form and spin storage form."""
@@ -193,11 +196,13 @@ def test_storage_forms_give_identical_trajectories(L, monkeypatch):
         assert np.allclose(ra, rb, rtol=1e-12, atol=1e-12)
 
 
-def test_large_graph_uses_global_variant():
-    """L=512 replicas do not fit LDS; 3 sweeps with PT, then the measurement
+@pytest.mark.parametrize("T", [[1.5, 2.5, 3.5], [1.5, 2.0, 2.5, 3.5]])
+def test_large_graph_not_in_lds(T):
+    """L=512 replicas do not fit LDS: with 4 temperatures the phase form runs,
+    with 3 the slot-major global form.  3 sweeps with PT, then the measurement
     kernel vs the oracle's measurement of the same state."""
     g = xy.Graph.levy(512, 6, 2.5, 0)
-    T = np.array([1.5, 2.5, 3.5])
+    T = np.array(T)
     b = xy.Batch([g], T, precision="fix16", seeds=[0])
     b.sweep(3, pt_every=1, meas_every=0)
     o = b.measure().cpu().numpy()[0]
@@ -279,3 +284,46 @@ def test_full_headline_shape_sampled():
     R = wl.n_T
     expect = np.array([3 if k % 2 == 0 else 3 for k in range(R - 1)] + [0])
     assert np.array_equal(tries[0].astype(int), expect)
+
+
+def test_phase_form_pt_batch_matches_fp64_gpu(monkeypatch):
+    """Phase form on 64 samples of L=32 with PT vs the FP64 GPU path, paired by sample."""
+    monkeypatch.setenv("XY_FIX16_PHASE", "1")
+    T = workloads.linear_ladder(1.0, 2.5, 8)
+    graphs = [xy.Graph.levy(32, 6, 3.5, s) for s in range(64)]
+    res = {}
+    for prec in ("fp64", "fix16"):
+        b = xy.Batch(graphs, T, precision=prec, seeds=np.arange(64), max_records=200)
+        b.sweep(400, pt_every=1, meas_every=0)
+        b.sweep(1600, pt_every=1, meas_every=8)
+        res[prec] = b.records().cpu().numpy().mean(axis=0)
+    zs = []
+    for q in (0, 1, 3):
+        for k in range(len(T)):
+            d = res["fix16"][:, k, q] - res["fp64"][:, k, q]
+            zs.append(d.mean() / (d.std(ddof=1) / np.sqrt(len(d))))
+    assert np.max(np.abs(np.array(zs))) < 4.0, zs
+
+
+def test_phase_form_state_roundtrip_and_resume(monkeypatch):
+    monkeypatch.setenv("XY_FIX16_PHASE", "1")
+    graphs = [xy.Graph.levy(16, 6, 3.5, 1), xy.Graph.levy(32, 6, 2.5, 2)]
+    T = workloads.linear_ladder(0.8, 2.0, 8)
+    full = xy.Batch(graphs, T, precision="fix16", seeds=[1, 2])
+    full.sweep(20, pt_every=1, meas_every=0)
+    ref = full.get_state()
+    first = xy.Batch(graphs, T, precision="fix16", seeds=[1, 2])
+    first.sweep(9, pt_every=1, meas_every=0)
+    mid = first.get_state()
+    resumed = xy.Batch(graphs, T, precision="fix16", seeds=[1, 2])
+    resumed.set_state(*mid)
+    resumed.sweep(11, pt_every=1, meas_every=0)
+    got = resumed.get_state()
+    assert got[2] == 20 and np.array_equal(got[1], ref[1])
+    assert all(np.array_equal(x, y) for x, y in zip(got[0], ref[0]))
+    o = resumed.measure().cpu().numpy()
+    e, _ = oracle.levy_graph(32, 6, 2.5, 2)
+    col, _ = oracle.slo_colour(1024, e)
+    sim = oracle.Sim(1024, e, col, 32, T, 2)
+    sim.set_state(_unit(got[0][1]), got[1][1], got[2])
+    assert np.allclose(o[1, :, :7], sim.measure()[:, :7], rtol=1e-11, atol=1e-11)
