@@ -180,8 +180,9 @@ xy_status xy_decision_log(xy_batch *b, uint8_t *d_log, int max_sweeps);
 xy_status xy_batch_use_graph(xy_batch *b, int chunk);
 
 /* Kernel timing for roofline reports: while enabled, every xy_sweep records a
- * HIP event pair on its stream around the dominant kernel of each sweep (the
- * fix16 sweep kernel, or the colour-phase kernels of an FP64 sweep); HIP graph
+ * HIP event pair on its stream around the dominant kernels of each sweep (the
+ * fix16 sweep kernels and the fix16 phase-form colour-phase kernels, or the
+ * colour-phase kernels of an FP64 sweep); HIP graph
  * replay is bypassed meanwhile.  xy_kernel_time synchronises the stream of the
  * last sweep, returns the summed elapsed milliseconds and the number of timed
  * sweeps since timing was enabled, and keeps timing on. */
@@ -194,7 +195,9 @@ xy_status xy_kernel_time(xy_batch *b, double *ms_total, int *n_timed);
  *   allow_unit  : keep FP32 unit vectors in LDS for graphs that fit (else angles)
  *   force_global: keep every replica in global memory
  * Each choice samples the clock model with its own FP32 (cos, sin); all are
- * exact Metropolis samplers.  Synchronises `stream`, then uploads the new
+ * exact Metropolis samplers.  Samples in the phase form (graphs too large for
+ * LDS, state stored site-major; chosen at xy_batch_init) always use the
+ * hardware form and are not affected by this call.  Synchronises `stream`, then uploads the new
  * work-item lists.  Initial values: trig 2, allow_unit 1, force_global 0
  * (the environment variables XY_FIX16_TRIG, XY_FIX16_NOUNIT and
  * XY_FIX16_GLOBAL override them at xy_batch_init). */

