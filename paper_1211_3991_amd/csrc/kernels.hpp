@@ -25,7 +25,8 @@ struct DevBatch {
     int32_t *T_of_slot;       // [G][R]
     double *E_slot;           // [G][R]
     double *obs_slot;         // [G][R][XY_NOBS]
-    double *partial;          // fp64: [G][64][R][11] block partial sums of the observables
+    double *partial;          // [G][64][R][11] block partial sums of the observables (fp64, fix16 phase form)
+    double *epart;            // fix16 phase form: [n_phase][31][max_blocks][R] energy partials
     unsigned long long *pt_acc, *pt_try;  // [G][R]
     double *records;          // [max_records][G][R][XY_NOBS]
     int G, R, max_records, max_n;
@@ -53,8 +54,12 @@ size_t fix16_lds_bytes(int n_pad, int trig, int mode);
 // fix16 phase form (site-major state, one launch per colour phase) for the
 // samples listed in phase_samples[n_phase]; sites_per_block(R) sites per block.
 int fix16_phase_sites_per_block(int R);
+// blocks: grid width for this colour; max_blocks: stride of the energy
+// partials (the largest block count of any colour); last: fuse the energy.
 hipError_t launch_fix16_phase(const DevBatch &b, const int32_t *phase_samples, int n_phase, int colour, int sub,
-                              int max_blocks, hipStream_t s);
+                              int last, int blocks, int max_blocks, hipStream_t s);
+hipError_t launch_fix16_phase_energy(const DevBatch &b, const int32_t *phase_samples, int n_phase, int max_blocks,
+                                     hipStream_t s);
 // Energies (and, when full, observables) of the phase-form samples: two
 // deterministic stages through b.partial.
 hipError_t launch_fix16_observe_sm(const DevBatch &b, const int32_t *phase_samples, int n_phase, int full,

@@ -453,52 +453,131 @@ constexpr int kPhaseBlock = 256;
 
 template <typename Idx>
 __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const int32_t *phase_samples, int colour,
-                                                            int sub)
+                                                            int sub, int last, int max_blocks)
 {
+    __shared__ float esum[kPhaseBlock * 4];
     const int R = b.R, Lq = R >> 2, S = kPhaseBlock / Lq;
     const int t = threadIdx.x, q = t % Lq, sl = t / Lq;
-    if (sl >= S) return;
-    const int s = phase_samples[blockIdx.y];
+    const int k_ph = blockIdx.y;
+    const int s = phase_samples[k_ph];
     const SampleDesc &d = b.desc[s];
-    if (colour >= d.Q) return;
+    if (colour >= d.Q) return;                                   // uniform over the block
     const int c0 = d.colour_off[colour], c1 = d.colour_off[colour + 1];
+    if (c0 + (int)blockIdx.x * S >= c1) return;                  // uniform: block past the class
     const int i = c0 + blockIdx.x * S + sl;
-    if (i >= c1) return;
-    const int rel = i - c0, ln = rel & 63;
-    const int base = b.i32[d.sell_ptr + d.chunk_off[colour] + (rel >> 6)];
-    const Idx *col = reinterpret_cast<const Idx *>(sizeof(Idx) == 2 ? (const void *)b.u16 : (const void *)b.i32) + d.sell_col;
-    const int dg = b.u8[d.deg + i];
-    uint2 *A = reinterpret_cast<uint2 *>(static_cast<uint16_t *>(b.state) + d.state);   // [site][Lq] x 4 angles
+    const bool active = sl < S && i < c1;
+    float e_q[4] = {0.f, 0.f, 0.f, 0.f};                          // last sub-sweep: energy of links to lower colours
+    if (active) {
+        const int rel = i - c0, ln = rel & 63;
+        const int base = b.i32[d.sell_ptr + d.chunk_off[colour] + (rel >> 6)];
+        const Idx *col = reinterpret_cast<const Idx *>(sizeof(Idx) == 2 ? (const void *)b.u16 : (const void *)b.i32) + d.sell_col;
+        const int dg = b.u8[d.deg + i];
+        uint2 *A = reinterpret_cast<uint2 *>(static_cast<uint16_t *>(b.state) + d.state);   // [site][Lq] x 4 angles
 
-    float hx[4] = {0.f, 0.f, 0.f, 0.f}, hy[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int k = 0; k < dg; ++k) {
-        const int j = (int)col[base + k * 64 + ln];
-        const uint2 v = A[(int64_t)j * Lq + q];
-        const uint32_t th[4] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16};
+        // up to 8 neighbour indices and their 4-slot angle words in flight
+        int jj[8];
+        uint2 vv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) jj[k] = k < dg ? (int)col[base + k * 64 + ln] : i;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) vv[k] = A[(int64_t)jj[k] * Lq + q];
+        float hx[4] = {0.f, 0.f, 0.f, 0.f}, hy[4] = {0.f, 0.f, 0.f, 0.f};
+        float lx[4] = {0.f, 0.f, 0.f, 0.f}, ly[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k < dg) {
+                const uint32_t th[4] = {vv[k].x & 0xFFFFu, vv[k].x >> 16, vv[k].y & 0xFFFFu, vv[k].y >> 16};
+                const bool low = last && jj[k] < c0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float2 u = Trig<2>::unit(th[r], nullptr);
+                    hx[r] += u.x; hy[r] += u.y;
+                    if (low) { lx[r] += u.x; ly[r] += u.y; }
+                }
+            }
+        }
+        for (int k = 8; k < dg; ++k) {
+            const int j = (int)col[base + k * 64 + ln];
+            const uint2 v = A[(int64_t)j * Lq + q];
+            const uint32_t th[4] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16};
+            const bool low = last && j < c0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float2 u = Trig<2>::unit(th[r], nullptr);
+                hx[r] += u.x; hy[r] += u.y;
+                if (low) { lx[r] += u.x; ly[r] += u.y; }
+            }
+        }
+        const uint32_t sweep = b.ctl->sweep;
+        const U4 w = philox4x32_10({(uint32_t)i, sweep, (uint32_t)(4 * q), tag(sub == 0 ? kMet : kOR, (uint32_t)sub)},
+                                   d.seed_lo, d.seed_hi);
+        const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+        const uint2 me = A[(int64_t)i * Lq + q];
+        const uint32_t cur_th[4] = {me.x & 0xFFFFu, me.x >> 16, me.y & 0xFFFFu, me.y >> 16};
+        uint32_t out[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const float2 u = Trig<2>::unit(th[r], nullptr);
-            hx[r] += u.x; hy[r] += u.y;
+            const int slot = 4 * q + r;
+            const float beta = (float)b.beta[s * R + b.T_of_slot[s * R + slot]];
+            const uint32_t th = cur_th[r];
+            const uint32_t th_new = sub == 0 ? (words[r] & 0xFFFFu) : ((field_axis2(hx[r], hy[r]) - th) & 0xFFFFu);
+            const float2 cur = Trig<2>::unit(th, nullptr), nu = Trig<2>::unit(th_new, nullptr);
+            const float dE = hx[r] * (cur.x - nu.x) + hy[r] * (cur.y - nu.y);
+            const bool acc = accept_move(dE, beta, words[r], (uint32_t)i, sweep, (uint32_t)slot, (uint32_t)sub, d);
+            out[r] = acc ? th_new : th;
+            const float2 f = acc ? nu : cur;
+            e_q[r] = -(f.x * lx[r] + f.y * ly[r]);
+        }
+        A[(int64_t)i * Lq + q] = make_uint2(out[0] | (out[1] << 16), out[2] | (out[3] << 16));
+    }
+    if (!last) return;                                            // uniform over the block
+    // per-slot energy of this block, summed in a fixed order, to
+    // epart[k_ph][colour][block][slot]; a final pass adds the blocks in order
+#pragma unroll
+    for (int r = 0; r < 4; ++r) esum[t * 4 + r] = e_q[r];
+    __syncthreads();
+    if (t < R) {
+        const int qq = t >> 2, r = t & 3;
+        double acc = 0.0;
+        for (int k = 0; k < S; ++k) acc += (double)esum[(k * Lq + qq) * 4 + r];
+        b.epart[(((int64_t)k_ph * kMaxColours + colour) * max_blocks + blockIdx.x) * R + t] = acc;
+    }
+}
+
+// Energies of the phase-form samples from the per-block sums of the last
+// sub-sweep.  One block per sample; thread (part, slot) adds every P-th block
+// partial of each colour in order, then part 0 adds the P sums in order.
+constexpr int kPhaseEnergyBlock = 1024;
+
+__global__ __launch_bounds__(kPhaseEnergyBlock) void k_fix16_phase_energy(DevBatch b, const int32_t *phase_samples,
+                                                                          int max_blocks)
+{
+    __shared__ double red[kPhaseEnergyBlock];
+    const int R = b.R, S = kPhaseBlock / (R >> 2), P = kPhaseEnergyBlock / R;   // R <= 256, so P >= 4
+    const int k = blockIdx.x, s = phase_samples[k];
+    const SampleDesc &d = b.desc[s];
+    const int t = threadIdx.x, part = t / R, slot = t % R;
+    double e = 0.0;
+    if (part < P) {
+        for (int c = 0; c < d.Q; ++c) {
+            const int nb = (d.colour_off[c + 1] - d.colour_off[c] + S - 1) / S;
+            const double *src = b.epart + ((int64_t)k * kMaxColours + c) * max_blocks * R + slot;
+            int blk = part;
+            for (; blk + 3 * P < nb; blk += 4 * P) {
+                const double a0 = src[(int64_t)blk * R], a1 = src[(int64_t)(blk + P) * R];
+                const double a2 = src[(int64_t)(blk + 2 * P) * R], a3 = src[(int64_t)(blk + 3 * P) * R];
+                e += a0; e += a1; e += a2; e += a3;
+            }
+            for (; blk < nb; blk += P) e += src[(int64_t)blk * R];
         }
     }
-    const uint32_t sweep = b.ctl->sweep;
-    const U4 w = philox4x32_10({(uint32_t)i, sweep, (uint32_t)(4 * q), tag(sub == 0 ? kMet : kOR, (uint32_t)sub)},
-                               d.seed_lo, d.seed_hi);
-    const uint32_t words[4] = {w.x, w.y, w.z, w.w};
-    const uint2 me = A[(int64_t)i * Lq + q];
-    const uint32_t cur_th[4] = {me.x & 0xFFFFu, me.x >> 16, me.y & 0xFFFFu, me.y >> 16};
-    uint32_t out[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int slot = 4 * q + r;
-        const float beta = (float)b.beta[s * R + b.T_of_slot[s * R + slot]];
-        const uint32_t th = cur_th[r];
-        const uint32_t th_new = sub == 0 ? (words[r] & 0xFFFFu) : ((field_axis2(hx[r], hy[r]) - th) & 0xFFFFu);
-        const float2 cur = Trig<2>::unit(th, nullptr), nu = Trig<2>::unit(th_new, nullptr);
-        const float dE = hx[r] * (cur.x - nu.x) + hy[r] * (cur.y - nu.y);
-        out[r] = accept_move(dE, beta, words[r], (uint32_t)i, sweep, (uint32_t)slot, (uint32_t)sub, d) ? th_new : th;
+    red[t] = e;
+    __syncthreads();
+    if (t < R) {
+        double acc = 0.0;
+        for (int q = 0; q < P; ++q) acc += red[q * R + t];
+        b.E_slot[s * R + t] = acc;
     }
-    A[(int64_t)i * Lq + q] = make_uint2(out[0] | (out[1] << 16), out[2] | (out[3] << 16));
 }
 
 // Energies (and observables when full) of the phase-form samples, stage 1:
@@ -653,14 +732,25 @@ hipError_t launch_fix16_sweep(const DevBatch &b, const Item *items, int n_items,
 int fix16_phase_sites_per_block(int R) { return kPhaseBlock / (R / 4); }
 
 hipError_t launch_fix16_phase(const DevBatch &b, const int32_t *phase_samples, int n_phase, int colour, int sub,
-                              int max_blocks, hipStream_t s)
+                              int last, int blocks, int max_blocks, hipStream_t s)
 {
-    if (n_phase == 0 || max_blocks == 0) return hipSuccess;
-    dim3 grid((unsigned)max_blocks, (unsigned)n_phase);
+    if (n_phase == 0 || blocks == 0) return hipSuccess;
+    dim3 grid((unsigned)blocks, (unsigned)n_phase);
     if (b.idx16)
-        hipLaunchKernelGGL(k_fix16_phase<uint16_t>, grid, dim3(kPhaseBlock), 0, s, b, phase_samples, colour, sub);
+        hipLaunchKernelGGL(k_fix16_phase<uint16_t>, grid, dim3(kPhaseBlock), 0, s, b, phase_samples, colour, sub, last,
+                           max_blocks);
     else
-        hipLaunchKernelGGL(k_fix16_phase<int32_t>, grid, dim3(kPhaseBlock), 0, s, b, phase_samples, colour, sub);
+        hipLaunchKernelGGL(k_fix16_phase<int32_t>, grid, dim3(kPhaseBlock), 0, s, b, phase_samples, colour, sub, last,
+                           max_blocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_fix16_phase_energy(const DevBatch &b, const int32_t *phase_samples, int n_phase, int max_blocks,
+                                     hipStream_t s)
+{
+    if (n_phase == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fix16_phase_energy, dim3((unsigned)n_phase), dim3(kPhaseEnergyBlock), 0, s, b, phase_samples,
+                       max_blocks);
     return hipGetLastError();
 }
 

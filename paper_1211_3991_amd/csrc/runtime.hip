@@ -32,6 +32,7 @@ struct xy_batch {
     int n_phase = 0;
     int32_t *d_phase = nullptr;
     std::vector<int> phase_max_blocks;        // per colour
+    int phase_stride = 0;                     // largest of them (energy partial stride)
     size_t item_cap = 0;
     Item *d_items = nullptr;
     int lds_limit = 0;
@@ -75,6 +76,7 @@ struct Plan {
     size_t item_cap = 0;
     std::vector<Sell> sell;      // fix16 only
     bool idx16 = false;
+    int phase_blocks = 0;        // largest phase-form block count of any colour
 };
 
 xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int max_records, Plan &p)
@@ -99,7 +101,7 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
     bool force_phase = false;
     if (const char *env = std::getenv("XY_FIX16_PHASE"))
         if (std::atoi(env) != 0) force_phase = true;
-    int n_phase = 0;
+    int n_phase = 0, phase_blocks = 0;
     for (int s = 0; s < G; ++s) {
         const xy_graph &gr = *g[s];
         SampleDesc &d = p.desc[s];
@@ -124,6 +126,11 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
         for (int c = 0; c <= kMaxColours; ++c) d.colour_off[c] = gr.colour_off[std::min(c, gr.Q)];
         d.layout = (fix16 && R % 4 == 0 && (force_phase || gr.n > 65536)) ? 1 : 0;
         n_phase += d.layout;
+        if (d.layout) {
+            const int spb = fix16_phase_sites_per_block(R);
+            for (int c = 0; c < gr.Q; ++c)
+                phase_blocks = std::max(phase_blocks, (gr.colour_off[c + 1] - gr.colour_off[c] + spb - 1) / spb);
+        }
         d.state = (int64_t)state_elems;
         p.state_off[s] = d.state;
         state_elems += fix16 ? (size_t)((gr.n + 7) & ~7) * R : (size_t)gr.n * R;
@@ -158,6 +165,8 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
     wl.pt_acc = off;    off = align_up(off + 8 * GR, 256);
     wl.pt_try = off;    off = align_up(off + 8 * GR, 256);
     wl.partial = off;   off = align_up(off + ((fix16 && n_phase == 0) ? 0 : 8 * 64 * 11 * GR), 256);
+    wl.epart = off;     off = align_up(off + 8 * (size_t)n_phase * kMaxColours * phase_blocks * R, 256);
+    p.phase_blocks = phase_blocks;
     wl.total = off;
     p.state_bytes = align_up(state_elems * (precision == XY_FP64 ? 16 : 2), 256);
     p.obs_bytes = align_up((size_t)max_records * GR * XY_NOBS * 8, 256);
@@ -386,6 +395,7 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
             }
             std::copy(phase.begin(), phase.end(), reinterpret_cast<int32_t *>(gimg.data() + gl.phase));
             b->n_phase = (int)phase.size();
+            b->phase_stride = p.phase_blocks;
             b->d_phase = reinterpret_cast<int32_t *>(static_cast<unsigned char *>(d_graph) + gl.phase);
             Item *items = reinterpret_cast<Item *>(gimg.data() + gl.items);
             if (!build_groups(b, trig, allow_unit, force_global, items)) {
@@ -435,6 +445,7 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
         dv.pt_acc = reinterpret_cast<unsigned long long *>(wbase + wl.pt_acc);
         dv.pt_try = reinterpret_cast<unsigned long long *>(wbase + wl.pt_try);
         dv.partial = reinterpret_cast<double *>(wbase + wl.partial);
+        dv.epart = reinterpret_cast<double *>(wbase + wl.epart);
         dv.records = static_cast<double *>(d_obs);
         dv.G = G; dv.R = R; dv.max_records = max_records; dv.max_n = p.max_n;
         dv.log = nullptr; dv.log_sweeps = 0;
@@ -494,12 +505,16 @@ hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream
         }
         for (int sub = 0; sub <= n_or && e == hipSuccess && b->n_phase > 0; ++sub)
             for (int c = 0; c < (int)b->phase_max_blocks.size() && e == hipSuccess; ++c)
-                e = launch_fix16_phase(b->dev, b->d_phase, b->n_phase, c, sub, b->phase_max_blocks[c], s);
+                e = launch_fix16_phase(b->dev, b->d_phase, b->n_phase, c, sub, sub == n_or, b->phase_max_blocks[c],
+                                       b->phase_stride, s);
         // the timed part: the sweep kernels (with their fused energies) and the
         // colour-phase kernels of the phase form
         if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
-        if (e == hipSuccess && b->n_phase > 0 && (do_pt || do_rec))
-            e = launch_fix16_observe_sm(b->dev, b->d_phase, b->n_phase, do_rec, s);
+        if (e == hipSuccess && b->n_phase > 0) {
+            if (do_rec) e = launch_fix16_observe_sm(b->dev, b->d_phase, b->n_phase, 1, s);
+            // E_slot for tempering: the FP32-form energies fused in the last sub-sweep
+            if (e == hipSuccess && do_pt) e = launch_fix16_phase_energy(b->dev, b->d_phase, b->n_phase, b->phase_stride, s);
+        }
     }
     if (e == hipSuccess) e = launch_end_sweep(b->dev, do_pt, do_rec, 1, s);
     return e;
