@@ -14,6 +14,7 @@ oracle (sequential FP64 C) on a bounded slice on the host cores.
 Prints one JSON line (rank 0; one GPU only).
 """
 import argparse
+import csv
 import hashlib
 import json
 import os
@@ -28,7 +29,21 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fix16_sweep_L256.json")
+
+
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+
+
+def uses_phase_form(wl):
+    """The library's rule for the fix16 site-major phase form (does any sample
+    use it): graphs of at least XY_FIX16_PHASE_MIN (16384) sites with the
+    temperature count a multiple of 4; XY_FIX16_PHASE=1 / 0 forces it on / off."""
+    mode = os.environ.get("XY_FIX16_PHASE", "")
+    n_min = int(os.environ.get("XY_FIX16_PHASE_MIN", "") or 16384)
+    if wl.n_T % 4 or mode == "0":
+        return False
+    return mode not in ("",) or any(s.L * s.L >= n_min for s in wl.samples)
 
 
 def alg_bytes_per_update(b_s, z, R):
@@ -46,19 +61,27 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def time_gpu(wl, precision, steps, warmup, graphs, torch, xy):
+def time_gpu(wl, precision, steps, warmup, graphs, torch, xy, n_or=None, form=None):
+    """Times `steps` sweeps.  fix16: autotunes first, or takes `form` =
+    (trig, allow_unit) from an earlier tuning."""
+    n_or = wl.n_or if n_or is None else n_or
     stream = torch.cuda.Stream()
     b = xy.Batch(graphs, wl.T, precision=precision, seeds=[s.seed for s in wl.samples],
                  max_records=max(1, (steps + warmup) // wl.meas_every + 1), stream=stream)
-    tune = b.autotune(n_or=wl.n_or, use_cache=False) if precision == "fix16" else None
-    b.sweep(warmup, n_or=wl.n_or, pt_every=wl.pt_every, meas_every=wl.meas_every)
+    tune = None
+    if precision == "fix16":
+        if form is None:
+            tune = b.autotune(n_or=n_or, use_cache=False)
+        else:
+            b.set_fix16_form(trig=form[0], allow_unit=form[1])
+    b.sweep(warmup, n_or=n_or, pt_every=wl.pt_every, meas_every=wl.meas_every)
     b.synchronize()
     b.kernel_timing(True)
     with torch.cuda.stream(stream):
         t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t0.record(stream)
-        b.sweep(steps, n_or=wl.n_or, pt_every=wl.pt_every, meas_every=wl.meas_every)
+        b.sweep(steps, n_or=n_or, pt_every=wl.pt_every, meas_every=wl.meas_every)
         t1.record(stream)
         torch.cuda.synchronize()
     ms = t0.elapsed_time(t1)
@@ -69,6 +92,58 @@ def time_gpu(wl, precision, steps, warmup, graphs, torch, xy):
     b.close()
     return {"ms": ms, "kernel_ms": k_ms / max(k_n, 1), "kernel_n": k_n, "records": rec,
             "pt_rate": float(acc.sum()) / max(float(tries.sum()), 1.0), "autotune": tune}
+
+
+def _pmc_rows(path):
+    with open(path, newline="") as fh:
+        rows = list(csv.DictReader(fh))
+    return sorted(rows, key=lambda r: int(r["Dispatch_Id"]))
+
+
+def write_traffic(wl, paths, argv):
+    """HBM bytes per sweep of the dominant fix16 kernel from rocprofv3 counter
+    CSVs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by what the
+    same counter reads for a plain 512 MiB device copy."""
+    fetch, write, cal_f, cal_w = (_pmc_rows(p) for p in paths)
+    pat = "k_fix16_phase" if uses_phase_form(wl) else "k_fix16_sweep"
+
+    def per_dispatch(rows, counter):
+        # the most frequent instantiation of the kernel is the tuned form the
+        # timed sweeps ran; count its dispatches per sweep (k_end_sweep ends one)
+        names = [r["Kernel_Name"] for r in rows if pat in r["Kernel_Name"] and r["Counter_Name"] == counter]
+        name = max(set(names), key=names.count)
+        vals, sweeps, seen = [], 0, False
+        for r in rows:
+            if r["Counter_Name"] != counter:
+                continue
+            if r["Kernel_Name"] == name:
+                vals.append(float(r["Counter_Value"]))
+                seen = True
+            elif "k_end_sweep" in r["Kernel_Name"]:
+                sweeps += seen
+                seen = False
+        return name, sum(vals) / len(vals), len(vals) / max(sweeps, 1)
+
+    def copy_kib(rows, counter):
+        v = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == counter]
+        return sum(v) / len(v)
+
+    copy_bytes = 512 << 20
+    f_scale = copy_bytes / (copy_kib(cal_f, "FETCH_SIZE") * 1024)
+    w_scale = copy_bytes / (copy_kib(cal_w, "WRITE_SIZE") * 1024)
+    name, f_kib, per_sweep = per_dispatch(fetch, "FETCH_SIZE")
+    _, w_kib, _ = per_dispatch(write, "WRITE_SIZE")
+    per_sweep = round(per_sweep)
+    bytes_sweep = (f_kib * f_scale + w_kib * w_scale) * 1024 * per_sweep
+    upd = wl.updates_per_sweep()
+    out = {"workload": wl.name, "kernel": name, "kernel_digest": kernel_source_digest(),
+           "dispatches_per_sweep": per_sweep, "fetch_kib_per_dispatch": round(f_kib, 1),
+           "write_kib_per_dispatch": round(w_kib, 1), "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+           "bytes_per_sweep": int(bytes_sweep), "bytes_per_update": round(bytes_sweep / upd, 4),
+           "updates_per_sweep": upd, "command": f"python bench.py {argv}"}
+    with open(traffic_file(wl.name), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
 
 
 def cpu_baseline(wl, seconds):
@@ -102,9 +177,17 @@ def main():
     ap.add_argument("--precision", default="fix16", choices=["fix16", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=8, help="sweeps of the FP64 plain comparison (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle time budget (0 = skip)")
+    ap.add_argument("--split-steps", type=int, default=8,
+                    help="sweeps of the Metropolis-only run that splits the rate into Met and OR (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (HBM counter calibration)")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH_CSV", "CAL_WRITE_CSV"),
+                    help="no GPU work: turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter CSVs of this workload "
+                         "and of --calibrate-copy 512 into profiles/traffic_<workload>.json")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(workloads.ALL[args.workload](), args.traffic_from, " ".join(sys.argv[1:]))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the samples are independent and a multi-GPU "
               "run would shard them with no communication; use --gpus 1", file=sys.stderr)
@@ -141,17 +224,22 @@ def main():
     b_s = 2 if args.precision == "fix16" else 16
     bpu = alg_bytes_per_update(b_s, z, wl.n_T)
     k_ms = main_run["kernel_ms"]
-    achieved = bpu * upd_per_sweep / (k_ms * 1e6)   # GB/s, one sweep kernel launch = one sweep
+    achieved = bpu * upd_per_sweep / (k_ms * 1e6)   # GB/s over the sweep's launches of the dominant kernel
     traffic = None
-    if args.precision == "fix16" and os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as fh:
+    if args.precision == "fix16" and os.path.exists(traffic_file(wl.name)):
+        with open(traffic_file(wl.name)) as fh:
             tr = json.load(fh)
         if tr.get("kernel_digest") == kernel_source_digest() and tr.get("workload") == wl.name:
-            traffic = tr["bytes_per_launch"]
+            traffic = tr["bytes_per_sweep"]
+    if args.precision == "fp64":
+        kname = "k_fp64_phase (the 6·Q colour-phase launches of one sweep)"
+    elif uses_phase_form(wl):
+        kname = "k_fix16_phase (the 6·Q colour-phase launches of one sweep, all samples per launch)"
+    else:
+        kname = "k_fix16_sweep (one launch = one sweep of every (sample, slot))"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": ("k_fix16_sweep (one launch = one sweep of every (sample, slot))" if args.precision == "fix16"
-                           else "k_fp64_phase (all colour-phase launches of a sweep)"),
+                "kernel": kname,
                 "kernel_ms": round(k_ms, 4), "alg_bytes_per_update": round(bpu, 3),
                 "updates_per_launch": upd_per_sweep}
 
@@ -163,6 +251,22 @@ def main():
                 "state": "FP64 unit vectors", "speedup_fix16_over_fp64": round(value / v64, 2)}
         print(f"# fp64 plain: {r['ms'] / args.fp64_steps:.3f} ms/sweep, {v64:.2f} updates/ns",
               file=sys.stderr, flush=True)
+
+    split = None
+    if args.split_steps > 0 and wl.n_or > 0:
+        # Metropolis-only sweeps on the same batch shape and form; the OR rate
+        # follows from the difference of the kernel times (PT and measurement
+        # are outside the kernel time)
+        tuned = main_run["autotune"]
+        form = (tuned["trig"], tuned["allow_unit"]) if tuned and "trig" in tuned else None
+        met = time_gpu(wl, args.precision, args.split_steps, 2, graphs, torch, xy, n_or=0, form=form)
+        n_upd = upd_per_sweep // (1 + wl.n_or)
+        or_ms = k_ms - met["kernel_ms"]
+        split = {"met_only": round(n_upd / (met["kernel_ms"] * 1e6), 2),
+                 "or_only": round(wl.n_or * n_upd / (or_ms * 1e6), 2) if or_ms > 0 else None,
+                 "unit": "spin updates/ns (kernel time)", "met_kernel_ms": round(met["kernel_ms"], 4),
+                 "note": "Metropolis-only sweeps (n_or=0) timed separately; OR from the difference"}
+        print(f"# split: Met {split['met_only']} / OR {split['or_only']} updates/ns", file=sys.stderr, flush=True)
 
     cpu = cpu_baseline(wl, args.cpu_seconds) if args.cpu_seconds > 0 else None
     s0 = wl.samples[0]
@@ -179,6 +283,7 @@ def main():
                    else "FP64 unit vectors", "parallelism": "samples x temperatures on one GPU"},
         "roofline": roofline,
         "fp64_plain": fp64,
+        "sub_sweep_rates": split,
         "cpu_baseline": cpu,
         "pt_acceptance": round(main_run["pt_rate"], 4),
         "autotune": main_run["autotune"],

@@ -125,7 +125,14 @@ xy_status xy_batch_sizes(const xy_graph *const *g, int n_graphs, int n_T, int pr
  * Philox purpose 2) on `stream`.
  *   T     : double[n_graphs * n_T] temperature ladders (T > 0), slot k starts at T[k]
  *   seeds : uint64[n_graphs] Philox keys of the samples' dynamics
- * The graphs may be freed after this call returns. */
+ * The graphs may be freed after this call returns.
+ * fix16 storage per sample: graphs of at least 16384 sites, when n_T is a
+ * multiple of 4, are stored site-major and swept one colour phase of all such
+ * samples per launch (the phase form); smaller graphs, or any n_T, get one
+ * workgroup per replica with the replica in LDS when it fits (else in global
+ * memory).  The environment variables XY_FIX16_PHASE_MIN (the site threshold)
+ * and XY_FIX16_PHASE (1: every sample, 0: none) override the rule; they are
+ * read here and by xy_batch_sizes, which must see the same values. */
 xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int n_graphs, int n_T,
                         const double *T, int precision, const uint64_t *seeds, int max_records,
                         void *d_state, void *d_graph, void *d_work, void *d_obs, void *stream);

@@ -32,6 +32,7 @@ class Graph:
     """A host graph handle (xy_graph)."""
 
     def __init__(self, handle):
+        self._free = _lib.raw().xy_graph_free
         self._h = ctypes.c_void_p(handle)
         n, m, q, md = (ctypes.c_int() for _ in range(4))
         att = ctypes.c_int64()
@@ -70,9 +71,11 @@ class Graph:
         return {"edges": e, "colour": colour, "perm": perm, "colour_off": off, "row_ptr": rp, "col": col}
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            _lib.raw().xy_graph_free(h)
+        # the free function is bound at creation: module globals may already
+        # be gone when the interpreter shuts down
+        h, free = getattr(self, "_h", None), getattr(self, "_free", None)
+        if h is not None and h.value and free is not None:
+            free(h)
             self._h = None
 
 
@@ -119,6 +122,7 @@ class Batch:
                   ctypes.c_void_p(self.d_graph.data_ptr()), ctypes.c_void_p(self.d_work.data_ptr()),
                   ctypes.c_void_p(self.d_obs.data_ptr()), self._s())
         self._h = h
+        self._free = _lib.raw().xy_batch_free
         self._log = None
 
     def _s(self):
@@ -214,9 +218,9 @@ class Batch:
         return self._log
 
     def close(self):
-        h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            _lib.raw().xy_batch_free(h)
+        h, free = getattr(self, "_h", None), getattr(self, "_free", None)
+        if h is not None and h.value and free is not None:
+            free(h)
             self._h = None
 
     def __del__(self):

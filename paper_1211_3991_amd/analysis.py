@@ -118,3 +118,75 @@ def disorder(records, N, T, L, rho, discard=0.5):
         "xi2": lambda e, v, m2, m4, m2sq, ff: np.abs(N * m2 / ff - 1.0) ** (1.0 / psi) / s,
     }
     return {name: jackknife(fn, blocks) for name, fn in fns.items()}
+
+
+def crossing(T, ya, yb):
+    """Temperature where the curves ya(T) and yb(T) cross: the first sign change
+    of ya - yb along the ladder T (ascending), linearly interpolated.  None if
+    they do not cross."""
+    T = np.asarray(T, dtype=np.float64)
+    d = np.asarray(ya, dtype=np.float64) - np.asarray(yb, dtype=np.float64)
+    for k in range(len(T) - 1):
+        if d[k] == 0.0:
+            return float(T[k])
+        if d[k] * d[k + 1] < 0.0:
+            return float(T[k] - d[k] * (T[k + 1] - T[k]) / (d[k + 1] - d[k]))
+    return float(T[-1]) if d[-1] == 0.0 else None
+
+
+def u4_samples(records, discard=0.5):
+    """Per-sample thermal <m^4> and <m^2>^2 ([G, n_T] each) of records
+    [n_rec, G, n_T, 8], after discarding the first part (Sec. 4)."""
+    rec = np.asarray(records, dtype=np.float64)
+    rec = rec[int(rec.shape[0] * discard):]
+    th = rec.mean(axis=0)
+    return th[:, :, M4], th[:, :, M2] ** 2
+
+
+def u4_crossing(T, rec_small, rec_large, discard=0.5):
+    """Crossing temperature of the disorder-averaged U4 (Sec. 3, ratio of
+    disorder averages) of two sizes, with a jackknife error over the samples
+    of both sizes (independent sets: the leave-one-out variances add).
+    Sec. 5 estimates T_c from the crossing of U4(T, N) with U4(T, N/4)."""
+    a4, a2 = u4_samples(rec_small, discard)
+    b4, b2 = u4_samples(rec_large, discard)
+
+    def cross(a4m, a2m, b4m, b2m):
+        return crossing(T, a4m / a2m - 1.0, b4m / b2m - 1.0)
+
+    est = cross(a4.mean(0), a2.mean(0), b4.mean(0), b2.mean(0))
+    if est is None:
+        return None, None
+    var = 0.0
+    for x4, x2, other, first in ((a4, a2, (b4.mean(0), b2.mean(0)), True), (b4, b2, (a4.mean(0), a2.mean(0)), False)):
+        n = x4.shape[0]
+        s4, s2 = x4.sum(0), x2.sum(0)
+        loo = []
+        for i in range(n):
+            m4, m2 = (s4 - x4[i]) / (n - 1), (s2 - x2[i]) / (n - 1)
+            c = cross(m4, m2, *other) if first else cross(*other, m4, m2)
+            if c is not None:
+                loo.append(c)
+        loo = np.asarray(loo)
+        if loo.size > 1:
+            var += (n - 1) / n * np.sum((loo - loo.mean()) ** 2)
+    return est, float(np.sqrt(var))
+
+
+def fss_tc(N, T_cross, nu_bar):
+    """T_c from crossing temperatures T(N) under T(N) = C N^(-1/nu_bar) + T_c
+    (Sec. 5): least squares in (N^(-1/nu_bar), T).  Returns (T_c, C)."""
+    x = np.asarray(N, dtype=np.float64) ** (-1.0 / nu_bar)
+    A = np.stack([np.ones_like(x), x], axis=1)
+    (tc, c), *_ = np.linalg.lstsq(A, np.asarray(T_cross, dtype=np.float64), rcond=None)
+    return float(tc), float(c)
+
+
+def bethe_tc(excess_degree):
+    """Critical temperature of the XY model on a locally tree-like random
+    graph in the Bethe approximation: I1(beta)/I0(beta) = 1 / excess degree
+    (the excess degree <k^2>/<k> - 1 is z for a Poisson degree of mean z)."""
+    from scipy.optimize import brentq
+    from scipy.special import i0e, i1e
+    f = lambda b: i1e(b) / i0e(b) - 1.0 / excess_degree
+    return 1.0 / brentq(f, 1e-9, 50.0)

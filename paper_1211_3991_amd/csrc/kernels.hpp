@@ -54,10 +54,11 @@ size_t fix16_lds_bytes(int n_pad, int trig, int mode);
 // fix16 phase form (site-major state, one launch per colour phase) for the
 // samples listed in phase_samples[n_phase]; sites_per_block(R) sites per block.
 int fix16_phase_sites_per_block(int R);
-// blocks: grid width for this colour; max_blocks: stride of the energy
-// partials (the largest block count of any colour); last: fuse the energy.
-hipError_t launch_fix16_phase(const DevBatch &b, const int32_t *phase_samples, int n_phase, int colour, int sub,
-                              int last, int blocks, int max_blocks, hipStream_t s);
+// units: the n_units (sample, phase-sample index, block, 0) work units of this colour;
+// max_blocks: stride of the energy partials (the largest block count of any
+// colour); last: fuse the energy.
+hipError_t launch_fix16_phase(const DevBatch &b, const int4 *units, int colour, int sub,
+                              int last, int n_units, int max_blocks, hipStream_t s);
 hipError_t launch_fix16_phase_energy(const DevBatch &b, const int32_t *phase_samples, int n_phase, int max_blocks,
                                      hipStream_t s);
 // Energies (and, when full, observables) of the phase-form samples: two

@@ -31,8 +31,10 @@ struct xy_batch {
     // fix16 phase form (site-major samples, one launch per colour phase)
     int n_phase = 0;
     int32_t *d_phase = nullptr;
-    std::vector<int> phase_max_blocks;        // per colour
-    int phase_stride = 0;                     // largest of them (energy partial stride)
+    std::vector<int> phase_units;             // per colour: work units of its launch
+    std::vector<size_t> phase_unit_off;       // per colour: first unit in d_units
+    int4 *d_units = nullptr;                  // (sample, phase-sample index, block of its class, 0)
+    int phase_stride = 0;                     // largest block count (energy partial stride)
     size_t item_cap = 0;
     Item *d_items = nullptr;
     int lds_limit = 0;
@@ -77,6 +79,7 @@ struct Plan {
     std::vector<Sell> sell;      // fix16 only
     bool idx16 = false;
     int phase_blocks = 0;        // largest phase-form block count of any colour
+    size_t phase_units = 0;      // phase-form blocks over all colours and samples
 };
 
 xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int max_records, Plan &p)
@@ -96,11 +99,17 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
     }
     p.idx16 = fix16 && max_n <= 65536;
     if (fix16) p.sell.resize(G);
-    // phase form for graphs too large for LDS (site-major state); needs the
-    // slots in groups of four.  XY_FIX16_PHASE=1 puts every sample in it (tests).
-    bool force_phase = false;
+    // fix16 storage of a sample: the site-major phase form (one launch per
+    // colour phase for all such samples, four slots per thread) for graphs of
+    // at least XY_FIX16_PHASE_MIN sites (default 16384) when n_T is a multiple
+    // of 4; below that a workgroup per replica with the replica in LDS wins.
+    // XY_FIX16_PHASE=1 / 0 puts every sample in / out of it.
+    int phase_mode = -1;
     if (const char *env = std::getenv("XY_FIX16_PHASE"))
-        if (std::atoi(env) != 0) force_phase = true;
+        if (*env) phase_mode = std::atoi(env) != 0 ? 1 : 0;
+    int phase_min = 16384;
+    if (const char *env = std::getenv("XY_FIX16_PHASE_MIN"))
+        if (*env) phase_min = std::atoi(env);
     int n_phase = 0, phase_blocks = 0;
     for (int s = 0; s < G; ++s) {
         const xy_graph &gr = *g[s];
@@ -124,12 +133,15 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
         d.coord = (int64_t)n_u32;   n_u32 += align_up(gr.n, 4);
         d.trig = (int64_t)n_f64;    n_f64 += gr.L;
         for (int c = 0; c <= kMaxColours; ++c) d.colour_off[c] = gr.colour_off[std::min(c, gr.Q)];
-        d.layout = (fix16 && R % 4 == 0 && (force_phase || gr.n > 65536)) ? 1 : 0;
+        d.layout = (fix16 && R % 4 == 0 && (phase_mode == 1 || (phase_mode < 0 && gr.n >= phase_min))) ? 1 : 0;
         n_phase += d.layout;
         if (d.layout) {
             const int spb = fix16_phase_sites_per_block(R);
-            for (int c = 0; c < gr.Q; ++c)
-                phase_blocks = std::max(phase_blocks, (gr.colour_off[c + 1] - gr.colour_off[c] + spb - 1) / spb);
+            for (int c = 0; c < gr.Q; ++c) {
+                const int nb = (gr.colour_off[c + 1] - gr.colour_off[c] + spb - 1) / spb;
+                phase_blocks = std::max(phase_blocks, nb);
+                p.phase_units += nb;
+            }
         }
         d.state = (int64_t)state_elems;
         p.state_off[s] = d.state;
@@ -147,7 +159,8 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
     gl.u16_pool = off;  off = align_up(off + 2 * n_u16, 256);
     gl.u8_pool = off;   off = align_up(off + n_u8, 256);
     gl.items = off;     off = align_up(off + kGroups * sizeof(Item) * p.item_cap, 256);
-    gl.phase = off;     off = align_up(off + 4 * (size_t)G, 256);
+    // phase-form sample list, then per colour the (sample, block) work units
+    gl.phase = off;     off = align_up(off + align_up(4 * (size_t)G, 16) + 16 * p.phase_units, 256);
     gl.tab32 = off;     off = align_up(off + 512 * 8, 256);
     gl.tab2k = off;     off = align_up(off + 2048 * 8, 256);
     gl.tab64 = off;     off = align_up(off + 512 * 16, 256);
@@ -380,23 +393,38 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
             b->item_cap = p.item_cap;
             b->lds_limit = lds_limit;
             b->d_items = reinterpret_cast<Item *>(static_cast<unsigned char *>(d_graph) + gl.items);
+            // phase form: the samples, and for each colour the launch's work
+            // units in sample order (each a block of sites of that sample's
+            // colour class), so every workgroup of a launch has work
             std::vector<int32_t> phase;
-            b->phase_max_blocks.assign(p.Qmax, 0);
+            for (int s_ = 0; s_ < G; ++s_)
+                if (p.desc[s_].layout) phase.push_back(s_);
+            std::vector<int4> units;
+            b->phase_units.assign(p.Qmax, 0);
+            b->phase_unit_off.assign(p.Qmax, 0);
             const int spb = R % 4 == 0 ? fix16_phase_sites_per_block(R) : 1;
-            for (int s_ = 0; s_ < G; ++s_) {
-                if (!p.desc[s_].layout) continue;
-                const int k = (int)phase.size();
-                phase.push_back(s_);
-                for (int c = 0; c < p.desc[s_].Q; ++c) {
-                    const int size_c = p.desc[s_].colour_off[c + 1] - p.desc[s_].colour_off[c];
-                    b->phase_max_blocks[c] = std::max(b->phase_max_blocks[c], (size_c + spb - 1) / spb);
+            for (int c = 0; c < p.Qmax; ++c) {
+                b->phase_unit_off[c] = units.size();
+                for (int k = 0; k < (int)phase.size(); ++k) {
+                    const SampleDesc &d = p.desc[phase[k]];
+                    if (c >= d.Q) continue;
+                    const int nb = (d.colour_off[c + 1] - d.colour_off[c] + spb - 1) / spb;
+                    for (int bx = 0; bx < nb; ++bx) units.push_back(make_int4(phase[k], k, bx, 0));
                 }
-                (void)k;
+                b->phase_units[c] = (int)(units.size() - b->phase_unit_off[c]);
             }
-            std::copy(phase.begin(), phase.end(), reinterpret_cast<int32_t *>(gimg.data() + gl.phase));
+            if (units.size() != p.phase_units) {
+                delete b;
+                return set_error(XY_EUNSUP, "xy_batch_init: phase-form work units do not match the plan");
+            }
+            unsigned char *ph = gimg.data() + gl.phase;
+            std::copy(phase.begin(), phase.end(), reinterpret_cast<int32_t *>(ph));
+            std::copy(units.begin(), units.end(), reinterpret_cast<int4 *>(ph + align_up(4 * (size_t)G, 16)));
             b->n_phase = (int)phase.size();
             b->phase_stride = p.phase_blocks;
             b->d_phase = reinterpret_cast<int32_t *>(static_cast<unsigned char *>(d_graph) + gl.phase);
+            b->d_units = reinterpret_cast<int4 *>(static_cast<unsigned char *>(d_graph) + gl.phase +
+                                                  align_up(4 * (size_t)G, 16));
             Item *items = reinterpret_cast<Item *>(gimg.data() + gl.items);
             if (!build_groups(b, trig, allow_unit, force_global, items)) {
                 delete b;
@@ -504,9 +532,9 @@ hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream
             if (e != hipSuccess) break;
         }
         for (int sub = 0; sub <= n_or && e == hipSuccess && b->n_phase > 0; ++sub)
-            for (int c = 0; c < (int)b->phase_max_blocks.size() && e == hipSuccess; ++c)
-                e = launch_fix16_phase(b->dev, b->d_phase, b->n_phase, c, sub, sub == n_or, b->phase_max_blocks[c],
-                                       b->phase_stride, s);
+            for (int c = 0; c < (int)b->phase_units.size() && e == hipSuccess; ++c)
+                e = launch_fix16_phase(b->dev, b->d_units + b->phase_unit_off[c], c, sub, sub == n_or,
+                                       b->phase_units[c], b->phase_stride, s);
         // the timed part: the sweep kernels (with their fused energies) and the
         // colour-phase kernels of the phase form
         if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);

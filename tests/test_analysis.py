@@ -47,3 +47,48 @@ def test_infinite_temperature_cumulants():
 
 def test_psi():
     assert analysis.psi_of(2.5) == 0.5 and analysis.psi_of(3.5) == 1.5 and analysis.psi_of(4.5) == 2.0
+
+
+def test_crossing_of_two_lines():
+    T = np.linspace(1.0, 3.0, 9)
+    assert abs(analysis.crossing(T, 0.5 + 0.1 * (T - 2.13), 0.5 + 0.4 * (T - 2.13)) - 2.13) < 1e-12
+    assert analysis.crossing(T, T, T + 1.0) is None
+
+
+def _u4_records(T, slope, G, n_rec=8, noise=None):
+    """Records whose thermal U4 is 0.5 + slope (T - 2.05) in every sample
+    (|m|^2 = 1, |m|^4 = 1 + U4), optionally with per-sample noise."""
+    u = 0.5 + slope * (np.asarray(T) - 2.05)
+    rec = np.zeros((n_rec, G, len(T), 8))
+    rec[:, :, :, 1] = 1.0
+    rec[:, :, :, 2] = 1.0 + u
+    if noise is not None:
+        rec[:, :, :, 2] += noise[None, :, None]
+    return rec
+
+
+def test_u4_crossing_exact_and_jackknife():
+    T = np.linspace(1.6, 2.4, 11)
+    est, err = analysis.u4_crossing(T, _u4_records(T, -0.2, 6), _u4_records(T, -0.6, 5))
+    assert abs(est - 2.05) < 1e-12 and err < 1e-12
+    # sample-to-sample scatter of the large size only: the crossing moves with
+    # the mean shift and the jackknife error is the shift's standard error
+    # divided by the slope difference (linear curves)
+    noise = np.random.default_rng(2).normal(scale=0.01, size=40)
+    est, err = analysis.u4_crossing(T, _u4_records(T, -0.2, 6), _u4_records(T, -0.6, 40, noise=noise))
+    assert abs(est - (2.05 + noise.mean() / 0.4)) < 1e-9
+    assert abs(err - noise.std(ddof=1) / np.sqrt(40) / 0.4) < 1e-9
+
+
+def test_fss_tc_recovers_the_law():
+    N = np.array([256.0, 1024.0, 4096.0])
+    tc, c = analysis.fss_tc(N, 1.93 + 3.0 * N ** -0.5, 2.0)
+    assert abs(tc - 1.93) < 1e-12 and abs(c - 3.0) < 1e-10
+
+
+def test_bethe_tc():
+    # I1/I0 at beta = 1 and 0.1 (tabulated Bessel ratios) give T = 1 and 10
+    assert abs(analysis.bethe_tc(1.0 / 0.446389965896535) - 1.0) < 1e-10
+    assert abs(analysis.bethe_tc(1.0 / 0.049937603987939) - 10.0) < 1e-8
+    # the analytic value for the Erdos-Renyi graph of mean degree 4 (Sec. 5)
+    assert abs(analysis.bethe_tc(4.0) - 1.9361) < 1e-4
