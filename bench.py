@@ -102,27 +102,29 @@ def _pmc_rows(path):
 
 def write_traffic(wl, paths, argv):
     """HBM bytes per sweep of the dominant fix16 kernel from rocprofv3 counter
-    CSVs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by what the
-    same counter reads for a plain 512 MiB device copy."""
+    CSVs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch, summed over a sweep's
+    dispatches), each scaled by what the same counter reads for a plain 512 MiB
+    device copy."""
     fetch, write, cal_f, cal_w = (_pmc_rows(p) for p in paths)
     pat = "k_fix16_phase" if uses_phase_form(wl) else "k_fix16_sweep"
 
-    def per_dispatch(rows, counter):
-        # the most frequent instantiation of the kernel is the tuned form the
-        # timed sweeps ran; count its dispatches per sweep (k_end_sweep ends one)
-        names = [r["Kernel_Name"] for r in rows if pat in r["Kernel_Name"] and r["Counter_Name"] == counter]
-        name = max(set(names), key=names.count)
-        vals, sweeps, seen = [], 0, False
+    def per_sweep(rows, counter, n_last=4):
+        # counter summed over the dominant kernel's dispatches of each sweep
+        # (k_end_sweep ends one); the mean of the last n_last sweeps, which
+        # all ran the tuned form
+        sums, cur, names, n_disp = [], 0.0, set(), 0
         for r in rows:
             if r["Counter_Name"] != counter:
                 continue
-            if r["Kernel_Name"] == name:
-                vals.append(float(r["Counter_Value"]))
-                seen = True
+            if pat in r["Kernel_Name"]:
+                cur += float(r["Counter_Value"])
+                names.add(r["Kernel_Name"])
+                n_disp += 1
             elif "k_end_sweep" in r["Kernel_Name"]:
-                sweeps += seen
-                seen = False
-        return name, sum(vals) / len(vals), len(vals) / max(sweeps, 1)
+                sums.append(cur)
+                cur = 0.0
+        last = sums[-n_last:]
+        return sorted(names), sum(last) / len(last), n_disp / max(len(sums), 1)
 
     def copy_kib(rows, counter):
         v = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == counter]
@@ -131,14 +133,13 @@ def write_traffic(wl, paths, argv):
     copy_bytes = 512 << 20
     f_scale = copy_bytes / (copy_kib(cal_f, "FETCH_SIZE") * 1024)
     w_scale = copy_bytes / (copy_kib(cal_w, "WRITE_SIZE") * 1024)
-    name, f_kib, per_sweep = per_dispatch(fetch, "FETCH_SIZE")
-    _, w_kib, _ = per_dispatch(write, "WRITE_SIZE")
-    per_sweep = round(per_sweep)
-    bytes_sweep = (f_kib * f_scale + w_kib * w_scale) * 1024 * per_sweep
+    names, f_kib, n_per_sweep = per_sweep(fetch, "FETCH_SIZE")
+    _, w_kib, _ = per_sweep(write, "WRITE_SIZE")
+    bytes_sweep = (f_kib * f_scale + w_kib * w_scale) * 1024
     upd = wl.updates_per_sweep()
-    out = {"workload": wl.name, "kernel": name, "kernel_digest": kernel_source_digest(),
-           "dispatches_per_sweep": per_sweep, "fetch_kib_per_dispatch": round(f_kib, 1),
-           "write_kib_per_dispatch": round(w_kib, 1), "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+    out = {"workload": wl.name, "kernels": names, "kernel_digest": kernel_source_digest(),
+           "dispatches_per_sweep": round(n_per_sweep, 2), "fetch_kib_per_sweep": round(f_kib, 1),
+           "write_kib_per_sweep": round(w_kib, 1), "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
            "bytes_per_sweep": int(bytes_sweep), "bytes_per_update": round(bytes_sweep / upd, 4),
            "updates_per_sweep": upd, "command": f"python bench.py {argv}"}
     with open(traffic_file(wl.name), "w") as fh:

@@ -210,6 +210,11 @@ xy_status xy_kernel_time(xy_batch *b, double *ms_total, int *n_timed);
  * XY_FIX16_GLOBAL override them at xy_batch_init). */
 xy_status xy_batch_set_fix16_form(xy_batch *b, int trig, int allow_unit, int force_global, void *stream);
 
+/* Storage form of each sample, as chosen at xy_batch_init: out[s] = 1 for
+ * the site-major phase form, 0 for a workgroup per replica (FP64 batches: 0
+ * for every sample).  out: host int32[n_graphs], caller-owned. */
+xy_status xy_batch_forms(const xy_batch *b, int32_t *out);
+
 const char *xy_last_error(void);
 void xy_batch_free(xy_batch *b);
 

@@ -140,6 +140,12 @@ class Batch:
         _lib.call("xy_batch_set_fix16_form", self._h, int(trig), int(bool(allow_unit)), int(bool(force_global)),
                   self._s())
 
+    def forms(self):
+        """Storage form per sample: 1 site-major phase form, 0 workgroup per replica."""
+        out = np.zeros(self.G, np.int32)
+        _lib.call("xy_batch_forms", self._h, ctypes.c_void_p(out.ctypes.data))
+        return out
+
     def autotune(self, sweeps=3, n_or=5, use_cache=True):
         """Times the fixed-point configurations on this batch and keeps the fastest."""
         from .autotune import autotune

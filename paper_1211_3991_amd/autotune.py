@@ -42,6 +42,8 @@ def autotune(batch, sweeps=3, n_or=5, use_cache=True):
     """Picks and applies the fastest (trig, allow_unit); returns a report dict."""
     if batch.precision != "fix16":
         return {"tuned": False, "reason": "fp64 batch"}
+    if batch.forms().all():
+        return {"tuned": False, "reason": "every sample is in the phase form, which these choices do not affect"}
     key = signature(batch)
     path = cache_path()
     cache = _load(path) if use_cache else {}

@@ -800,6 +800,14 @@ extern "C" xy_status xy_kernel_time(xy_batch *b, double *ms_total, int *n_timed)
     return XY_OK;
 }
 
+extern "C" xy_status xy_batch_forms(const xy_batch *b, int32_t *out)
+{
+    if (!b || !out) return set_error(XY_EINVAL, "xy_batch_forms: bad arguments");
+    for (int s = 0; s < b->G; ++s)
+        out[s] = (b->precision == XY_FIX16 && s < (int)b->desc_host.size()) ? b->desc_host[s].layout : 0;
+    return XY_OK;
+}
+
 extern "C" xy_status xy_batch_set_fix16_form(xy_batch *b, int trig, int allow_unit, int force_global, void *stream)
 {
     if (!b) return set_error(XY_EINVAL, "xy_batch_set_fix16_form: batch is NULL");

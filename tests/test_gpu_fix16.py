@@ -241,6 +241,8 @@ def test_autotune_restores_state_and_applies_choice(tmp_path, monkeypatch):
     monkeypatch.setenv("XY_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
     g = [xy.Graph.levy(32, 6, 3.5, s) for s in range(8)] + [xy.Graph.levy(128, 6, 3.5, 9)]
     b = xy.Batch(g, workloads.linear_ladder(1.0, 2.5, 4), precision="fix16", max_records=4)
+    # graphs from 16384 sites take the phase form (n_T a multiple of 4)
+    assert list(b.forms()) == [0] * 8 + [1]
     b.sweep(5, pt_every=1, meas_every=0)
     before = b.get_state()
     rep = b.autotune(sweeps=2)
