@@ -55,7 +55,7 @@ def alg_bytes_per_update(b_s, z, R):
 
 def kernel_source_digest():
     h = hashlib.sha256()
-    for f in ("kernels_fix16.hip", "kernels.hpp", "xy_internal.hpp"):
+    for f in ("kernels_phase.hip", "fix16_common.hpp", "kernels.hpp", "xy_internal.hpp"):
         with open(os.path.join(ROOT, "paper_1211_3991_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -21,6 +21,7 @@ HIP_COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 HIP_SOURCES = {
     "kernels_fp64.hip": ["-ffp-contract=off"],
     "kernels_fix16.hip": [],
+    "kernels_phase.hip": [],
     "runtime.hip": ["-ffp-contract=off"],
 }
 CXX_SOURCES = {"graph.cpp": ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wextra"]}

@@ -1,0 +1,117 @@
+// Device helpers shared by the fixed-point kernels: (cos, sin) of a 16-bit
+// angle, the over-relaxation axis, the FP64 unit vector of a measurement and
+// the exact Metropolis acceptance.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace xy {
+namespace {
+
+constexpr float kTwoPhiScale = 20860.756700940907f;   // 2^16 / pi: 2*phi in angle units
+constexpr float kAngle = 9.587379924285257e-05f;      // 2 pi / 2^16
+
+// (cos, sin) of a 16-bit angle in FP32.  The three forms are different
+// deterministic functions of the angle (each within a few ulp of the exact
+// value); whichever is compiled in defines the energy the sweep samples.
+//   0: two-level table, (cos, sin)(256 a) rotated by (cos, sin)(b), 2 x 256 entries
+//   1: 2048-entry table of (cos, sin)(32 a), rotated by the small angle of the
+//      low 5 bits, delta <= 3.1e-3, with cos = 1 - delta^2/2 and sin = delta
+//      (truncation errors 4e-12 and 5e-9)
+//   2: the hardware sine/cosine of theta / 2^16 revolutions (no table)
+template <int kTrig> struct Trig;
+
+template <> struct Trig<0> {
+    static constexpr size_t kBytes = 512 * 8;
+    static __device__ __forceinline__ void load(float2 *t, const DevBatch &b, int tid, int stride)
+    {
+        for (int k = tid; k < 512; k += stride) t[k] = b.tab32[k];
+    }
+    static __device__ __forceinline__ float2 unit(uint32_t th, const float2 *t)
+    {
+        const float2 a = t[th >> 8], c = t[256 + (th & 255u)];
+        return make_float2(a.x * c.x - a.y * c.y, a.y * c.x + a.x * c.y);
+    }
+};
+
+template <> struct Trig<1> {
+    static constexpr size_t kBytes = 2048 * 8;
+    static __device__ __forceinline__ void load(float2 *t, const DevBatch &b, int tid, int stride)
+    {
+        for (int k = tid; k < 2048; k += stride) t[k] = b.tab2k[k];
+    }
+    static __device__ __forceinline__ float2 unit(uint32_t th, const float2 *t)
+    {
+        const float2 a = t[th >> 5];
+        const float d = (float)(th & 31u) * kAngle;
+        const float c = 1.0f - 0.5f * d * d;
+        return make_float2(a.x * c - a.y * d, a.y * c + a.x * d);
+    }
+};
+
+template <> struct Trig<2> {
+    static constexpr size_t kBytes = 0;
+    static __device__ __forceinline__ void load(float2 *, const DevBatch &, int, int) {}
+    static __device__ __forceinline__ float2 unit(uint32_t th, const float2 *)
+    {
+        // 1 + theta / 2^16 revolutions, built from the bits (exact); one whole
+        // turn more than theta, which sine and cosine do not see
+        const float r = __uint_as_float(0x3F800000u | (th << 7));
+        return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
+    }
+};
+
+// 2 phi in units of 2pi/2^16, rounded, for phi = atan2(hy, hx): the axis of
+// the over-relaxation reflection.  atan on [0, 1] by an odd polynomial of
+// degree 11, least-squares fitted on 4000 Chebyshev nodes (|error| < 2e-6
+// rad in FP32), then the octant is restored.
+// The accuracy only affects the acceptance rate of the reflection, not the
+// detailed balance (the reflection is accepted by a Metropolis test).
+__device__ __forceinline__ uint32_t field_axis2(float hx, float hy)
+{
+    const float ax = fabsf(hx), ay = fabsf(hy);
+    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+    const float t = mx > 0.f ? mn * __builtin_amdgcn_rcpf(mx) : 0.f;
+    const float t2 = t * t;
+    float p = -0.011770499870181084f;
+    p = fmaf(p, t2, 0.05282348766922951f);
+    p = fmaf(p, t2, -0.11665111780166626f);
+    p = fmaf(p, t2, 0.19367031753063202f);
+    p = fmaf(p, t2, -0.33265548944473267f);
+    p = fmaf(p, t2, 0.9999798536300659f);
+    float a = p * t;                                   // atan(t), t in [0, 1]
+    a = ay > ax ? 1.5707963267948966f - a : a;
+    a = hx < 0.f ? 3.141592653589793f - a : a;
+    a = hy < 0.f ? -a : a;
+    return (uint32_t)__float2int_rn(a * kTwoPhiScale);
+}
+
+__device__ __forceinline__ double2 unit64(uint32_t th, const double2 *t64)
+{
+    const double2 a = t64[th >> 8], c = t64[256 + (th & 255u)];
+    return make_double2(a.x * c.x - a.y * c.y, a.y * c.x + a.x * c.y);
+}
+
+// Metropolis acceptance with probability min(1, exp(-beta dE)) for the FP32
+// exp.  The uniform is the top 16 bits of `word`; on a tie with the 16-bit
+// threshold (probability 2^-16) 32 more bits are drawn from the counter
+// (site, sweep, slot, purpose 4 | sub), so the test is exact: U < p.
+__device__ __forceinline__ bool accept_move(float dE, float beta, uint32_t word, uint32_t site, uint32_t sweep,
+                                            uint32_t slot, uint32_t sub, const SampleDesc &d)
+{
+    if (dE <= 0.f) return true;
+    const float p = __expf(-beta * dE);
+    const float p16 = p * 65536.0f;
+    const uint32_t u16 = word >> 16, f = (uint32_t)p16;
+    if (u16 != f) return u16 < f;
+    const U4 x = philox4x32_10({site, sweep, slot, tag(kMetAcc, sub)}, d.seed_lo, d.seed_hi);
+    return (double)x.x < (double)(p16 - (float)f) * 4294967296.0;
+}
+
+// Phase form: threads per workgroup of the colour-phase kernel
+constexpr int kPhaseBlock = 256;
+
+}  // namespace
+}  // namespace xy

@@ -21,6 +21,7 @@
 // is tiny (the axis is quantised to 2pi/2^17) and almost every move is taken.
 #include <hip/hip_runtime.h>
 
+#include "fix16_common.hpp"
 #include "kernels.hpp"
 
 namespace xy {
@@ -29,89 +30,7 @@ namespace {
 constexpr int kUnroll = 8;     // neighbour indices loaded up front per site
 constexpr int kObsBlock = 256;
 constexpr int kNRed = 11;      // E, m_x, m_y, 4 Fourier sums along x, 4 along y
-constexpr float kTwoPhiScale = 20860.756700940907f;   // 2^16 / pi: 2*phi in angle units
-constexpr float kAngle = 9.587379924285257e-05f;      // 2 pi / 2^16
 
-// (cos, sin) of a 16-bit angle in FP32.  The three forms are different
-// deterministic functions of the angle (each within a few ulp of the exact
-// value); whichever is compiled in defines the energy the sweep samples.
-//   0: two-level table, (cos, sin)(256 a) rotated by (cos, sin)(b), 2 x 256 entries
-//   1: 2048-entry table of (cos, sin)(32 a), rotated by the small angle of the
-//      low 5 bits, delta <= 3.1e-3, with cos = 1 - delta^2/2 and sin = delta
-//      (truncation errors 4e-12 and 5e-9)
-//   2: the hardware sine/cosine of theta / 2^16 revolutions (no table)
-template <int kTrig> struct Trig;
-
-template <> struct Trig<0> {
-    static constexpr size_t kBytes = 512 * 8;
-    static __device__ __forceinline__ void load(float2 *t, const DevBatch &b, int tid, int stride)
-    {
-        for (int k = tid; k < 512; k += stride) t[k] = b.tab32[k];
-    }
-    static __device__ __forceinline__ float2 unit(uint32_t th, const float2 *t)
-    {
-        const float2 a = t[th >> 8], c = t[256 + (th & 255u)];
-        return make_float2(a.x * c.x - a.y * c.y, a.y * c.x + a.x * c.y);
-    }
-};
-
-template <> struct Trig<1> {
-    static constexpr size_t kBytes = 2048 * 8;
-    static __device__ __forceinline__ void load(float2 *t, const DevBatch &b, int tid, int stride)
-    {
-        for (int k = tid; k < 2048; k += stride) t[k] = b.tab2k[k];
-    }
-    static __device__ __forceinline__ float2 unit(uint32_t th, const float2 *t)
-    {
-        const float2 a = t[th >> 5];
-        const float d = (float)(th & 31u) * kAngle;
-        const float c = 1.0f - 0.5f * d * d;
-        return make_float2(a.x * c - a.y * d, a.y * c + a.x * d);
-    }
-};
-
-template <> struct Trig<2> {
-    static constexpr size_t kBytes = 0;
-    static __device__ __forceinline__ void load(float2 *, const DevBatch &, int, int) {}
-    static __device__ __forceinline__ float2 unit(uint32_t th, const float2 *)
-    {
-        // 1 + theta / 2^16 revolutions, built from the bits (exact); one whole
-        // turn more than theta, which sine and cosine do not see
-        const float r = __uint_as_float(0x3F800000u | (th << 7));
-        return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
-    }
-};
-
-// 2 phi in units of 2pi/2^16, rounded, for phi = atan2(hy, hx): the axis of
-// the over-relaxation reflection.  atan on [0, 1] by an odd polynomial of
-// degree 11, least-squares fitted on 4000 Chebyshev nodes (|error| < 2e-6
-// rad in FP32), then the octant is restored.
-// The accuracy only affects the acceptance rate of the reflection, not the
-// detailed balance (the reflection is accepted by a Metropolis test).
-__device__ __forceinline__ uint32_t field_axis2(float hx, float hy)
-{
-    const float ax = fabsf(hx), ay = fabsf(hy);
-    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
-    const float t = mx > 0.f ? mn * __builtin_amdgcn_rcpf(mx) : 0.f;
-    const float t2 = t * t;
-    float p = -0.011770499870181084f;
-    p = fmaf(p, t2, 0.05282348766922951f);
-    p = fmaf(p, t2, -0.11665111780166626f);
-    p = fmaf(p, t2, 0.19367031753063202f);
-    p = fmaf(p, t2, -0.33265548944473267f);
-    p = fmaf(p, t2, 0.9999798536300659f);
-    float a = p * t;                                   // atan(t), t in [0, 1]
-    a = ay > ax ? 1.5707963267948966f - a : a;
-    a = hx < 0.f ? 3.141592653589793f - a : a;
-    a = hy < 0.f ? -a : a;
-    return (uint32_t)__float2int_rn(a * kTwoPhiScale);
-}
-
-__device__ __forceinline__ double2 unit64(uint32_t th, const double2 *t64)
-{
-    const double2 a = t64[th >> 8], c = t64[256 + (th & 255u)];
-    return make_double2(a.x * c.x - a.y * c.y, a.y * c.x + a.x * c.y);
-}
 
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double *scratch)
@@ -179,21 +98,6 @@ __device__ __forceinline__ void observe(const DevBatch &b, const SampleDesc &d, 
     dst[5] = mx; dst[6] = my; dst[7] = 0.0;
 }
 
-// Metropolis acceptance with probability min(1, exp(-beta dE)) for the FP32
-// exp.  The uniform is the top 16 bits of `word`; on a tie with the 16-bit
-// threshold (probability 2^-16) 32 more bits are drawn from the counter
-// (site, sweep, slot, purpose 4 | sub), so the test is exact: U < p.
-__device__ __forceinline__ bool accept_move(float dE, float beta, uint32_t word, uint32_t site, uint32_t sweep,
-                                            uint32_t slot, uint32_t sub, const SampleDesc &d)
-{
-    if (dE <= 0.f) return true;
-    const float p = __expf(-beta * dE);
-    const float p16 = p * 65536.0f;
-    const uint32_t u16 = word >> 16, f = (uint32_t)p16;
-    if (u16 != f) return u16 < f;
-    const U4 x = philox4x32_10({site, sweep, slot, tag(kMetAcc, sub)}, d.seed_lo, d.seed_hi);
-    return (double)x.x < (double)(p16 - (float)f) * 4294967296.0;
-}
 
 // Where a replica's spins live during a sweep, and how a site's FP32 unit
 // vector is obtained.  Angles (uint16, in LDS or global memory) evaluate
@@ -442,137 +346,7 @@ __global__ __launch_bounds__(kObsBlock) void k_fix16_observe(DevBatch b, double 
     b.E_slot[s * R + slot] = o[0];
 }
 
-// Phase form (graphs too large for LDS): the state of a sample is site-major,
-// [site][slot], and one launch updates one colour class of all phase-form
-// samples.  Thread (site, q) updates slots 4q..4q+3 of one site: the
-// neighbour index is read once for the four slots and their four angles are
-// one 8-byte load, so graph and gather traffic are shared by four replicas.
-// Random words: one Philox call per (site, sweep, slot 4q), word r for slot
-// 4q + r.  (cos, sin) is the hardware form.
-constexpr int kPhaseBlock = 256;
 
-// The hardware deals the workgroups of a launch to the 8 XCDs in turn
-// (workgroup w to XCD w mod 8).  Work unit of workgroup `lin` out of `n`:
-// each XCD takes one contiguous run of units, so the neighbouring blocks of a
-// sample, whose gathers overlap, meet in the same L2.  A bijection on [0, n).
-__device__ __forceinline__ int xcd_contiguous(int lin, int n)
-{
-    const int x = lin & 7, k = lin >> 3, per = n >> 3, rem = n & 7;
-    return x * per + min(x, rem) + k;
-}
-
-template <typename Idx, bool kLast>
-__global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const int4 *units, int colour, int sub,
-                                                            int max_blocks)
-{
-    __shared__ float esum[kLast ? kPhaseBlock * 4 : 1];
-    const int R = b.R, Lq = R >> 2, S = kPhaseBlock / Lq;
-    const int t = threadIdx.x, q = t % Lq, sl = t / Lq;
-    // work unit: (sample, its phase-sample index, block of its colour class)
-    const int4 u = units[xcd_contiguous(blockIdx.x, gridDim.x)];
-    const int s = u.x, k_ph = u.y, bx = u.z;
-    const SampleDesc &d = b.desc[s];
-    if (colour >= d.Q) return;                                   // uniform over the block
-    const int c0 = d.colour_off[colour], c1 = d.colour_off[colour + 1];
-    const int r0 = bx * S;                                        // first site of the block, relative to c0
-    if (c0 + r0 >= c1) return;                                   // uniform: block past the class
-    // neighbour-count bounds of the block from its chunks' (wmin, wmax):
-    // rows below kmin are real for every site, rows from kmax on for none
-    int kmin = 255, kmax = 0;
-    {
-        const int32_t *cw = b.i32 + d.sell_w + d.chunk_off[colour];
-        const int ch1 = (min(r0 + S, c1 - c0) - 1) >> 6;
-        for (int ch = r0 >> 6; ch <= ch1; ++ch) {
-            const int w = cw[ch];
-            kmin = min(kmin, w & 255);
-            kmax = max(kmax, w >> 8);
-        }
-    }
-    const int i = c0 + r0 + sl;
-    const bool active = sl < S && i < c1;
-    float e_q[4] = {0.f, 0.f, 0.f, 0.f};                          // last sub-sweep: energy of links to lower colours
-    if (active) {
-        const int rel = i - c0, ln = rel & 63;
-        const int base = b.i32[d.sell_ptr + d.chunk_off[colour] + (rel >> 6)];
-        const Idx *col = reinterpret_cast<const Idx *>(sizeof(Idx) == 2 ? (const void *)b.u16 : (const void *)b.i32) + d.sell_col;
-        const int dg = b.u8[d.deg + i];
-        uint2 *A = reinterpret_cast<uint2 *>(static_cast<uint16_t *>(b.state) + d.state);   // [site][Lq] x 4 angles
-        float beta[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) beta[r] = (float)b.beta[s * R + b.T_of_slot[s * R + 4 * q + r]];
-
-        // 8 rows of neighbour indices (a row past a chunk's width holds a
-        // valid site: the next chunk's or the padding), then the 4-slot angle
-        // words of all 8, in flight before the first use (unconditional
-        // loads keep the wait counts exact); rows past a lane's degree read
-        // its own word (cached, not used)
-        int jj[8];
-        uint2 vv[8];
-        const Idx *cl = col + (uint32_t)(base + ln);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) jj[k] = (int)cl[k * 64];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            jj[k] = k < dg ? jj[k] : i;
-            vv[k] = A[(uint32_t)jj[k] * (uint32_t)Lq + (uint32_t)q];
-        }
-        float hx[4] = {0.f, 0.f, 0.f, 0.f}, hy[4] = {0.f, 0.f, 0.f, 0.f};
-        float lx[4] = {0.f, 0.f, 0.f, 0.f}, ly[4] = {0.f, 0.f, 0.f, 0.f};
-        auto add = [&](uint2 v, int j) {
-            const uint32_t th[4] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16};
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float2 u = Trig<2>::unit(th[r], nullptr);
-                hx[r] += u.x; hy[r] += u.y;
-                if (kLast && j < c0) { lx[r] += u.x; ly[r] += u.y; }
-            }
-        };
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (k < kmin) add(vv[k], jj[k]);                     // uniform, unmasked
-            else if (k < kmax && k < dg) add(vv[k], jj[k]);
-        }
-        for (int k = 8; k < dg; ++k) {
-            const int j = (int)col[base + k * 64 + ln];
-            add(A[(uint32_t)j * (uint32_t)Lq + (uint32_t)q], j);
-        }
-        const uint32_t sweep = b.ctl->sweep;
-        const U4 w = philox4x32_10({(uint32_t)i, sweep, (uint32_t)(4 * q), tag(sub == 0 ? kMet : kOR, (uint32_t)sub)},
-                                   d.seed_lo, d.seed_hi);
-        const uint32_t words[4] = {w.x, w.y, w.z, w.w};
-        const uint2 me = A[(uint32_t)i * (uint32_t)Lq + (uint32_t)q];
-        const uint32_t cur_th[4] = {me.x & 0xFFFFu, me.x >> 16, me.y & 0xFFFFu, me.y >> 16};
-        uint32_t out[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int slot = 4 * q + r;
-            const uint32_t th = cur_th[r];
-            const uint32_t th_new = sub == 0 ? (words[r] & 0xFFFFu) : ((field_axis2(hx[r], hy[r]) - th) & 0xFFFFu);
-            const float2 cur = Trig<2>::unit(th, nullptr), nu = Trig<2>::unit(th_new, nullptr);
-            const float dE = hx[r] * (cur.x - nu.x) + hy[r] * (cur.y - nu.y);
-            const bool acc = accept_move(dE, beta[r], words[r], (uint32_t)i, sweep, (uint32_t)slot, (uint32_t)sub, d);
-            out[r] = acc ? th_new : th;
-            if (kLast) {
-                const float2 f = acc ? nu : cur;
-                e_q[r] = -(f.x * lx[r] + f.y * ly[r]);
-            }
-        }
-        A[(uint32_t)i * (uint32_t)Lq + (uint32_t)q] = make_uint2(out[0] | (out[1] << 16), out[2] | (out[3] << 16));
-    }
-    if constexpr (kLast) {
-        // per-slot energy of this block, summed in a fixed order, to
-        // epart[k_ph][colour][block][slot]; a final pass adds the blocks in order
-#pragma unroll
-        for (int r = 0; r < 4; ++r) esum[t * 4 + r] = e_q[r];
-        __syncthreads();
-        if (t < R) {
-            const int qq = t >> 2, r = t & 3;
-            double acc = 0.0;
-            for (int k = 0; k < S; ++k) acc += (double)esum[(k * Lq + qq) * 4 + r];
-            b.epart[(((int64_t)k_ph * kMaxColours + colour) * max_blocks + bx) * R + t] = acc;
-        }
-    }
-}
 
 // Energies of the phase-form samples from the per-block sums of the last
 // sub-sweep.  One block per sample; thread (part, slot) adds every P-th block
@@ -611,9 +385,8 @@ __global__ __launch_bounds__(kPhaseEnergyBlock) void k_fix16_phase_energy(DevBat
 }
 
 // Energies (and observables when full) of the phase-form samples, stage 1:
-// block b of a sample covers a contiguous site range for all slots; thread t
-// takes slot t % R of sites t / R, t / R + nsl, ... (whole [site][slot] rows
-// per warp); FP64 unit vectors of the 16-bit angles.  Each link is counted
+// block b of a sample covers a contiguous site range for all slots, S sites
+// at a time; FP64 unit vectors of the 16-bit angles.  Each link is counted
 // once, at its higher endpoint.  Stage 2 adds the kObsBlocks partials in
 // block order.
 constexpr int kObsBlocks = 64;
@@ -622,53 +395,96 @@ template <typename Idx>
 __global__ __launch_bounds__(kObsBlock) void k_fix16_observe_sm_partial(DevBatch b, const int32_t *phase_samples,
                                                                        int full)
 {
-    __shared__ double red[kObsBlock * kNRed];
-    const int s = phase_samples[blockIdx.y], R = b.R;
+    __shared__ double red[kObsBlock * 4];
+    __shared__ double2 t64[512];          // the FP64 two-level (cos, sin) table
+    const int s = phase_samples[blockIdx.y], R = b.R, Lq = R >> 2;
     const SampleDesc &d = b.desc[s];
-    const int nsl = kObsBlock / R, t = threadIdx.x, slot = t % R, sl = t / R;
+    for (int k = threadIdx.x; k < 512; k += kObsBlock) t64[k] = b.tab64[k];
+    __syncthreads();
+    // thread (site, q) handles slots 4q..4q+3 of one site at a time, the
+    // block's S sites in parallel: one 8-byte gather per neighbour for four
+    // slots, eight in flight
+    const int S = kObsBlock / Lq, t = threadIdx.x, q = t % Lq, sl = t / Lq;
     const int per = (d.n + kObsBlocks - 1) / kObsBlocks;
     const int i0 = blockIdx.x * per, i1 = min(d.n, i0 + per);
-    double v[kNRed] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (sl < nsl) {
-        const uint16_t *A = static_cast<const uint16_t *>(b.state) + d.state;
+    double v[kNRed][4];
+#pragma unroll
+    for (int qq = 0; qq < kNRed; ++qq)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[qq][r] = 0.0;
+    if (sl < S) {
+        const uint2 *A = reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(b.state) + d.state);
         const int32_t *cptr = b.i32 + d.sell_ptr;
         const Idx *col = reinterpret_cast<const Idx *>(sizeof(Idx) == 2 ? (const void *)b.u16 : (const void *)b.i32) + d.sell_col;
         const uint8_t *deg = b.u8 + d.deg;
         const uint32_t *xy = b.u32 + d.coord;
         const double2 *trig = b.f64 + d.trig;
-        const double2 *t64 = b.tab64;
         int c = 0;
-        for (int i = i0 + sl; i < i1; i += nsl) {
+        for (int i = i0 + sl; i < i1; i += S) {
             while (i >= d.colour_off[c + 1]) ++c;
             const int rel = i - d.colour_off[c];
             const int base = cptr[d.chunk_off[c] + (rel >> 6)], ln = rel & 63;
-            const double2 si = unit64(A[(int64_t)i * R + slot], t64);
-            double e = 0.0;
-            for (int k = 0; k < deg[i]; ++k) {
-                const int j = (int)col[base + k * 64 + ln];
-                if (j < i) {
-                    const double2 sj = unit64(A[(int64_t)j * R + slot], t64);
-                    e += si.x * sj.x + si.y * sj.y;
+            const int dg = deg[i];
+            const uint2 me = A[(uint32_t)i * (uint32_t)Lq + (uint32_t)q];
+            const uint32_t th[4] = {me.x & 0xFFFFu, me.x >> 16, me.y & 0xFFFFu, me.y >> 16};
+            double2 si[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) si[r] = unit64(th[r], t64);
+            // rows past a chunk's width hold valid sites (next chunk or padding)
+            int jj[8];
+            uint2 vv[8];
+            const Idx *cl = col + (uint32_t)(base + ln);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) jj[k] = k < dg ? (int)cl[k * 64] : i;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) vv[k] = A[(uint32_t)jj[k] * (uint32_t)Lq + (uint32_t)q];
+            double e[4] = {0.0, 0.0, 0.0, 0.0};
+            // each link once, at its higher endpoint (j < i), in row order;
+            // S_i . S_j = cos(theta_i - theta_j), the difference taken exactly
+            // on the 2^16 circle: cos(a + b) from the two-level table
+            auto link = [&](uint2 w) {
+                const uint32_t tj[4] = {w.x & 0xFFFFu, w.x >> 16, w.y & 0xFFFFu, w.y >> 16};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const uint32_t dl = (th[r] - tj[r]) & 0xFFFFu;
+                    const double2 a = t64[dl >> 8], cc = t64[256 + (dl & 255u)];
+                    e[r] += a.x * cc.x - a.y * cc.y;
                 }
+            };
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (k < dg && jj[k] < i) link(vv[k]);
+            for (int k = 8; k < dg; ++k) {
+                const int j = (int)cl[k * 64];
+                if (j < i) link(A[(uint32_t)j * (uint32_t)Lq + (uint32_t)q]);
             }
-            v[0] -= e;
-            if (full) {
-                const uint32_t p = xy[i];
-                const double2 ex = trig[p & 0xFFFFu], ey = trig[p >> 16];
-                v[1] += si.x; v[2] += si.y;
-                v[3] += si.x * ex.x; v[4] += si.x * ex.y; v[5] += si.y * ex.x; v[6] += si.y * ex.y;
-                v[7] += si.x * ey.x; v[8] += si.x * ey.y; v[9] += si.y * ey.x; v[10] += si.y * ey.y;
+            const uint32_t p = xy[i];
+            const double2 ex = trig[p & 0xFFFFu], ey = trig[p >> 16];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                v[0][r] -= e[r];
+                if (full) {
+                    v[1][r] += si[r].x; v[2][r] += si[r].y;
+                    v[3][r] += si[r].x * ex.x; v[4][r] += si[r].x * ex.y;
+                    v[5][r] += si[r].y * ex.x; v[6][r] += si[r].y * ex.y;
+                    v[7][r] += si[r].x * ey.x; v[8][r] += si[r].x * ey.y;
+                    v[9][r] += si[r].y * ey.x; v[10][r] += si[r].y * ey.y;
+                }
             }
         }
     }
-    for (int qq = 0; qq < kNRed; ++qq) red[t * kNRed + qq] = v[qq];
-    __syncthreads();
-    if (t < R) {
-        for (int qq = 0; qq < kNRed; ++qq) {
+    // per quantity: the block's sites added in a fixed order, per slot
+    for (int qq = 0; qq < kNRed; ++qq) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[t * 4 + r] = v[qq][r];
+        __syncthreads();
+        if (t < R) {
+            const int qd = t >> 2, r = t & 3;
             double acc = 0.0;
-            for (int k = 0; k < nsl; ++k) acc += red[(k * R + t) * kNRed + qq];
+            for (int k = 0; k < S; ++k) acc += red[(k * Lq + qd) * 4 + r];
             b.partial[(((int64_t)blockIdx.y * kObsBlocks + blockIdx.x) * R + t) * kNRed + qq] = acc;
         }
+        __syncthreads();
     }
 }
 
@@ -759,17 +575,6 @@ hipError_t launch_fix16_sweep(const DevBatch &b, const Item *items, int n_items,
     return launch_sweep_m<kAngGlobal, 512>(b, items, n_items, n_or, measure, lds_bytes, s);
 }
 
-int fix16_phase_sites_per_block(int R) { return kPhaseBlock / (R / 4); }
-
-hipError_t launch_fix16_phase(const DevBatch &b, const int4 *units, int colour, int sub,
-                              int last, int n_units, int max_blocks, hipStream_t s)
-{
-    if (n_units == 0) return hipSuccess;
-    auto k = b.idx16 ? (last ? k_fix16_phase<uint16_t, true> : k_fix16_phase<uint16_t, false>)
-                     : (last ? k_fix16_phase<int32_t, true> : k_fix16_phase<int32_t, false>);
-    hipLaunchKernelGGL(k, dim3((unsigned)n_units), dim3(kPhaseBlock), 0, s, b, units, colour, sub, max_blocks);
-    return hipGetLastError();
-}
 
 hipError_t launch_fix16_phase_energy(const DevBatch &b, const int32_t *phase_samples, int n_phase, int max_blocks,
                                      hipStream_t s)

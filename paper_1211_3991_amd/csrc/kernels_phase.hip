@@ -1,0 +1,156 @@
+// Fixed-point path, phase form (graphs from 16384 sites when the temperature
+// count is a multiple of 4): the state of a sample is site-major, [site][slot],
+// and one launch updates one colour class of all phase-form samples (App. B's
+// colour phases as launches over the whole batch).
+#include <hip/hip_runtime.h>
+
+#include "fix16_common.hpp"
+#include "kernels.hpp"
+
+namespace xy {
+namespace {
+
+// Thread (site, q) updates slots 4q..4q+3 of one site: the neighbour index is
+// read once for the four slots and their four angles are one 8-byte load, so
+// graph and gather traffic are shared by four replicas.  Random words: one
+// Philox call per (site, sweep, slot 4q), word r for slot 4q + r.  (cos, sin)
+// is the hardware form.
+
+// The hardware deals the workgroups of a launch to the 8 XCDs in turn
+// (workgroup w to XCD w mod 8).  Work unit of workgroup `lin` out of `n`:
+// each XCD takes one contiguous run of units, so the neighbouring blocks of a
+// sample, whose gathers overlap, meet in the same L2.  A bijection on [0, n).
+__device__ __forceinline__ int xcd_contiguous(int lin, int n)
+{
+    const int x = lin & 7, k = lin >> 3, per = n >> 3, rem = n & 7;
+    return x * per + min(x, rem) + k;
+}
+
+template <typename Idx, bool kLast>
+__global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const int4 *units, int colour, int sub,
+                                                            int max_blocks)
+{
+    __shared__ float esum[kLast ? kPhaseBlock * 4 : 1];
+    const int R = b.R, Lq = R >> 2, S = kPhaseBlock / Lq;
+    const int t = threadIdx.x, q = t % Lq, sl = t / Lq;
+    // work unit: (sample, its phase-sample index, block of its colour class)
+    const int4 u = units[xcd_contiguous(blockIdx.x, gridDim.x)];
+    const int s = u.x, k_ph = u.y, bx = u.z;
+    const SampleDesc &d = b.desc[s];
+    if (colour >= d.Q) return;                                   // uniform over the block
+    const int c0 = d.colour_off[colour], c1 = d.colour_off[colour + 1];
+    const int r0 = bx * S;                                        // first site of the block, relative to c0
+    if (c0 + r0 >= c1) return;                                   // uniform: block past the class
+    // neighbour-count bounds of the block from its chunks' (wmin, wmax):
+    // rows below kmin are real for every site, rows from kmax on for none
+    int kmin = 255, kmax = 0;
+    {
+        const int32_t *cw = b.i32 + d.sell_w + d.chunk_off[colour];
+        const int ch1 = (min(r0 + S, c1 - c0) - 1) >> 6;
+        for (int ch = r0 >> 6; ch <= ch1; ++ch) {
+            const int w = cw[ch];
+            kmin = min(kmin, w & 255);
+            kmax = max(kmax, w >> 8);
+        }
+    }
+    const int i = c0 + r0 + sl;
+    const bool active = sl < S && i < c1;
+    float e_q[4] = {0.f, 0.f, 0.f, 0.f};                          // last sub-sweep: energy of links to lower colours
+    if (active) {
+        const int rel = i - c0, ln = rel & 63;
+        const int base = b.i32[d.sell_ptr + d.chunk_off[colour] + (rel >> 6)];
+        const Idx *col = reinterpret_cast<const Idx *>(sizeof(Idx) == 2 ? (const void *)b.u16 : (const void *)b.i32) + d.sell_col;
+        const int dg = b.u8[d.deg + i];
+        uint2 *A = reinterpret_cast<uint2 *>(static_cast<uint16_t *>(b.state) + d.state);   // [site][Lq] x 4 angles
+        float beta[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) beta[r] = (float)b.beta[s * R + b.T_of_slot[s * R + 4 * q + r]];
+
+        // 8 rows of neighbour indices (a row past a chunk's width holds a
+        // valid site: the next chunk's or the padding), then the 4-slot angle
+        // words of all 8, in flight before the first use (unconditional
+        // loads keep the wait counts exact); rows past a lane's degree read
+        // its own word (cached, not used)
+        int jj[8];
+        uint2 vv[8];
+        const Idx *cl = col + (uint32_t)(base + ln);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) jj[k] = (int)cl[k * 64];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            jj[k] = k < dg ? jj[k] : i;
+            vv[k] = A[(uint32_t)jj[k] * (uint32_t)Lq + (uint32_t)q];
+        }
+        float hx[4] = {0.f, 0.f, 0.f, 0.f}, hy[4] = {0.f, 0.f, 0.f, 0.f};
+        float lx[4] = {0.f, 0.f, 0.f, 0.f}, ly[4] = {0.f, 0.f, 0.f, 0.f};
+        auto add = [&](uint2 v, int j) {
+            const uint32_t th[4] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float2 u = Trig<2>::unit(th[r], nullptr);
+                hx[r] += u.x; hy[r] += u.y;
+                if (kLast && j < c0) { lx[r] += u.x; ly[r] += u.y; }
+            }
+        };
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k < kmin) add(vv[k], jj[k]);                     // uniform, unmasked
+            else if (k < kmax && k < dg) add(vv[k], jj[k]);
+        }
+        for (int k = 8; k < dg; ++k) {
+            const int j = (int)col[base + k * 64 + ln];
+            add(A[(uint32_t)j * (uint32_t)Lq + (uint32_t)q], j);
+        }
+        const uint32_t sweep = b.ctl->sweep;
+        const U4 w = philox4x32_10({(uint32_t)i, sweep, (uint32_t)(4 * q), tag(sub == 0 ? kMet : kOR, (uint32_t)sub)},
+                                   d.seed_lo, d.seed_hi);
+        const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+        const uint2 me = A[(uint32_t)i * (uint32_t)Lq + (uint32_t)q];
+        const uint32_t cur_th[4] = {me.x & 0xFFFFu, me.x >> 16, me.y & 0xFFFFu, me.y >> 16};
+        uint32_t out[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int slot = 4 * q + r;
+            const uint32_t th = cur_th[r];
+            const uint32_t th_new = sub == 0 ? (words[r] & 0xFFFFu) : ((field_axis2(hx[r], hy[r]) - th) & 0xFFFFu);
+            const float2 cur = Trig<2>::unit(th, nullptr), nu = Trig<2>::unit(th_new, nullptr);
+            const float dE = hx[r] * (cur.x - nu.x) + hy[r] * (cur.y - nu.y);
+            const bool acc = accept_move(dE, beta[r], words[r], (uint32_t)i, sweep, (uint32_t)slot, (uint32_t)sub, d);
+            out[r] = acc ? th_new : th;
+            if (kLast) {
+                const float2 f = acc ? nu : cur;
+                e_q[r] = -(f.x * lx[r] + f.y * ly[r]);
+            }
+        }
+        A[(uint32_t)i * (uint32_t)Lq + (uint32_t)q] = make_uint2(out[0] | (out[1] << 16), out[2] | (out[3] << 16));
+    }
+    if constexpr (kLast) {
+        // per-slot energy of this block, summed in a fixed order, to
+        // epart[k_ph][colour][block][slot]; a final pass adds the blocks in order
+#pragma unroll
+        for (int r = 0; r < 4; ++r) esum[t * 4 + r] = e_q[r];
+        __syncthreads();
+        if (t < R) {
+            const int qq = t >> 2, r = t & 3;
+            double acc = 0.0;
+            for (int k = 0; k < S; ++k) acc += (double)esum[(k * Lq + qq) * 4 + r];
+            b.epart[(((int64_t)k_ph * kMaxColours + colour) * max_blocks + bx) * R + t] = acc;
+        }
+    }
+}
+
+}  // namespace
+
+int fix16_phase_sites_per_block(int R) { return kPhaseBlock / (R / 4); }
+
+hipError_t launch_fix16_phase(const DevBatch &b, const int4 *units, int colour, int sub,
+                              int last, int n_units, int max_blocks, hipStream_t s)
+{
+    if (n_units == 0) return hipSuccess;
+    auto k = b.idx16 ? (last ? k_fix16_phase<uint16_t, true> : k_fix16_phase<uint16_t, false>)
+                     : (last ? k_fix16_phase<int32_t, true> : k_fix16_phase<int32_t, false>);
+    hipLaunchKernelGGL(k, dim3((unsigned)n_units), dim3(kPhaseBlock), 0, s, b, units, colour, sub, max_blocks);
+    return hipGetLastError();
+}
+
+}  // namespace xy

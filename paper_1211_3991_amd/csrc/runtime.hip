@@ -497,9 +497,12 @@ namespace {
 hipError_t next_events(xy_batch *b, hipEvent_t *start, hipEvent_t *stop)
 {
     if (b->events_used == b->events.size()) {
+        // timing only: no system-scope fence on record (that fence writes
+        // back and invalidates the caches, which costs the following kernels);
+        // xy_kernel_time synchronises the stream before reading them
         hipEvent_t a = nullptr, c = nullptr;
-        hipError_t e = hipEventCreate(&a);
-        if (e == hipSuccess) e = hipEventCreate(&c);
+        hipError_t e = hipEventCreateWithFlags(&a, hipEventDisableSystemFence);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c, hipEventDisableSystemFence);
         if (e != hipSuccess) return e;
         b->events.emplace_back(a, c);
     }
