@@ -156,10 +156,14 @@ Sell build_sell(const xy_graph &g, int window)
                 w = std::max(w, (int)S.deg[k]);
                 wmin = std::min(wmin, (int)S.deg[k]);
             }
-            S.chunk_ptr[ch + 1] = S.chunk_ptr[ch] + 64 * w;
+            // at least kSellRows rows per chunk, so a kernel may read its
+            // first kSellRows rows without a bound
+            S.chunk_ptr[ch + 1] = S.chunk_ptr[ch] + 64 * std::max(w, kSellRows);
             S.chunk_w[ch] = wmin | (w << 8);
         }
-    // 8 trailing padding rows let a kernel read 8 column rows past any chunk
+    // a site's rows past its degree hold the site itself, so reading them is
+    // valid and hits the site's own state (lanes past the class end hold 0);
+    // 8 trailing padding rows let a kernel read 8 rows past any chunk
     S.col.assign((size_t)S.chunk_ptr[n_chunks] + 8 * 64, 0);
     std::vector<int32_t> row;
     for (int c = 0; c < Q; ++c)
@@ -172,6 +176,8 @@ Sell build_sell(const xy_graph &g, int window)
                 for (int32_t &j : row) j = inv[j];
                 std::sort(row.begin(), row.end());
                 for (size_t a = 0; a < row.size(); ++a) S.col[S.chunk_ptr[ch] + a * 64 + (k - first)] = row[a];
+                const int rows = (S.chunk_ptr[ch + 1] - S.chunk_ptr[ch]) / 64;
+                for (int a = (int)row.size(); a < rows; ++a) S.col[S.chunk_ptr[ch] + a * 64 + (k - first)] = k;
             }
         }
     return S;

@@ -59,28 +59,34 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
     if (active) {
         const int rel = i - c0, ln = rel & 63;
         const int base = b.i32[d.sell_ptr + d.chunk_off[colour] + (rel >> 6)];
-        const Idx *col = reinterpret_cast<const Idx *>(sizeof(Idx) == 2 ? (const void *)b.u16 : (const void *)b.i32) + d.sell_col;
+        const char *colb = reinterpret_cast<const char *>(sizeof(Idx) == 2 ? (const void *)b.u16 : (const void *)b.i32) +
+                           d.sell_col * (int64_t)sizeof(Idx);
         const int dg = b.u8[d.deg + i];
-        uint2 *A = reinterpret_cast<uint2 *>(static_cast<uint16_t *>(b.state) + d.state);   // [site][Lq] x 4 angles
+        // [site][Lq] words of 4 angles; 32-bit byte offsets from the sample's base
+        char *Ab = reinterpret_cast<char *>(static_cast<uint16_t *>(b.state) + d.state);
+        const uint32_t q8 = 8u * (uint32_t)q, Lq8 = 8u * (uint32_t)Lq;
+        auto word = [&](int j) -> uint2 & { return *reinterpret_cast<uint2 *>(Ab + (__umul24((uint32_t)j, Lq8) + q8)); };
         float beta[4];
+        {
+            const int4 tq = *reinterpret_cast<const int4 *>(b.T_of_slot + s * R + 4 * q);
+            const int ts[4] = {tq.x, tq.y, tq.z, tq.w};
+            const char *bs = reinterpret_cast<const char *>(b.beta + s * R);   // this sample's ladder
 #pragma unroll
-        for (int r = 0; r < 4; ++r) beta[r] = (float)b.beta[s * R + b.T_of_slot[s * R + 4 * q + r]];
+            for (int r = 0; r < 4; ++r) beta[r] = (float)*reinterpret_cast<const double *>(bs + 8u * (uint32_t)ts[r]);
+        }
 
-        // 8 rows of neighbour indices (a row past a chunk's width holds a
-        // valid site: the next chunk's or the padding), then the 4-slot angle
-        // words of all 8, in flight before the first use (unconditional
-        // loads keep the wait counts exact); rows past a lane's degree read
-        // its own word (cached, not used)
+        // 8 rows of neighbour indices (every chunk has at least 8; a site's
+        // rows past its degree hold the site itself), then the 4-slot angle
+        // words of all 8, in flight before the first use (unconditional loads
+        // keep the wait counts exact; a padding row reads the site's own word)
+        static_assert(kSellRows >= 8, "the phase kernel reads 8 rows of every chunk");
         int jj[8];
         uint2 vv[8];
-        const Idx *cl = col + (uint32_t)(base + ln);
+        const uint32_t off0 = (uint32_t)(base + ln) * (uint32_t)sizeof(Idx);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) jj[k] = (int)cl[k * 64];
+        for (int k = 0; k < 8; ++k) jj[k] = (int)*reinterpret_cast<const Idx *>(colb + off0 + k * 64 * sizeof(Idx));
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            jj[k] = k < dg ? jj[k] : i;
-            vv[k] = A[(uint32_t)jj[k] * (uint32_t)Lq + (uint32_t)q];
-        }
+        for (int k = 0; k < 8; ++k) vv[k] = word(jj[k]);
         float hx[4] = {0.f, 0.f, 0.f, 0.f}, hy[4] = {0.f, 0.f, 0.f, 0.f};
         float lx[4] = {0.f, 0.f, 0.f, 0.f}, ly[4] = {0.f, 0.f, 0.f, 0.f};
         auto add = [&](uint2 v, int j) {
@@ -98,14 +104,14 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
             else if (k < kmax && k < dg) add(vv[k], jj[k]);
         }
         for (int k = 8; k < dg; ++k) {
-            const int j = (int)col[base + k * 64 + ln];
-            add(A[(uint32_t)j * (uint32_t)Lq + (uint32_t)q], j);
+            const int j = (int)*reinterpret_cast<const Idx *>(colb + k * 64 * (int)sizeof(Idx) + off0);
+            add(word(j), j);
         }
         const uint32_t sweep = b.ctl->sweep;
         const U4 w = philox4x32_10({(uint32_t)i, sweep, (uint32_t)(4 * q), tag(sub == 0 ? kMet : kOR, (uint32_t)sub)},
                                    d.seed_lo, d.seed_hi);
         const uint32_t words[4] = {w.x, w.y, w.z, w.w};
-        const uint2 me = A[(uint32_t)i * (uint32_t)Lq + (uint32_t)q];
+        const uint2 me = word(i);
         const uint32_t cur_th[4] = {me.x & 0xFFFFu, me.x >> 16, me.y & 0xFFFFu, me.y >> 16};
         uint32_t out[4];
 #pragma unroll
@@ -122,7 +128,7 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
                 e_q[r] = -(f.x * lx[r] + f.y * ly[r]);
             }
         }
-        A[(uint32_t)i * (uint32_t)Lq + (uint32_t)q] = make_uint2(out[0] | (out[1] << 16), out[2] | (out[3] << 16));
+        word(i) = make_uint2(out[0] | (out[1] << 16), out[2] | (out[3] << 16));
     }
     if constexpr (kLast) {
         // per-slot energy of this block, summed in a fixed order, to

@@ -136,7 +136,9 @@ struct GraphLayout {
 // consecutive sites (ties: colour-major order), so the 64 sites of a chunk
 // have nearly equal degree; chunk columns
 // are stored k-major ([k][lane]) so that the k-th neighbour loads of a wave are
-// contiguous.  Padding entries hold 0 and are skipped through the degree.
+// contiguous.  A chunk has at least kSellRows rows; a site's rows past its
+// degree hold the site itself (lanes past the class end hold 0).
+constexpr int kSellRows = 8;
 struct Sell {
     std::vector<int32_t> order;      // fix16 index -> colour-major index
     std::vector<int32_t> chunk_ptr;  // n_chunks + 1
