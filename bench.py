@@ -147,26 +147,53 @@ def write_traffic(wl, paths, argv):
     print(json.dumps(out))
 
 
-def cpu_baseline(wl, seconds):
-    """The oracle, single-threaded, on sample 0 of the workload (all its
-    temperatures), as many whole sweeps as fit in about `seconds`."""
+def cpu_baseline(wl, seconds, workers):
+    """The oracle (sequential FP64 C) on the host cores: `workers` threads,
+    each sweeping its own sample of the workload (all temperatures, PT every
+    sweep) for about `seconds`.  The oracle's C calls release the GIL, so the
+    threads run in parallel; the rate is all updates over the wall time from a
+    common start to the last thread's end."""
+    import threading
     import oracle
-    s = wl.samples[0]
-    e, _ = oracle.levy_graph(s.L, s.z, s.rho, s.seed)
-    col, _ = oracle.slo_colour(s.L * s.L, e)
-    sim = oracle.Sim(s.L * s.L, e, col, s.L, wl.T, s.seed)
-    sim.init_random()
-    t = time.perf_counter()
-    sim.run(1, n_or=wl.n_or, pt_every=wl.pt_every, meas_every=0)
-    one = time.perf_counter() - t
-    n = max(1, int(seconds / max(one, 1e-9)) - 1)
-    t = time.perf_counter()
-    sim.run(n, n_or=wl.n_or, pt_every=wl.pt_every, meas_every=0)
-    dt = time.perf_counter() - t
-    upd = s.L * s.L * wl.n_T * (1 + wl.n_or) * n
-    return {"value": upd / (dt * 1e9), "unit": "spin updates/ns", "cores": 1, "kind": "oracle",
-            "sample": f"sample 0 of the workload (L={s.L}, {wl.n_T} T), {n} sweeps with PT, "
-                      f"{upd} updates in {dt:.1f} s, one thread"}
+    plans, done, errors = [None] * workers, [None] * workers, []
+    ready = threading.Barrier(workers + 1)       # the workers and this thread
+
+    def run(k):
+        try:
+            s = wl.samples[k % len(wl.samples)]
+            e, _ = oracle.levy_graph(s.L, s.z, s.rho, s.seed)
+            col, _ = oracle.slo_colour(s.L * s.L, e)
+            sim = oracle.Sim(s.L * s.L, e, col, s.L, wl.T, s.seed)
+            sim.init_random()
+            t = time.perf_counter()
+            sim.run(1, n_or=wl.n_or, pt_every=wl.pt_every, meas_every=0)
+            n = max(1, int(seconds / max(time.perf_counter() - t, 1e-9)))
+            plans[k] = (n, s.L * s.L * wl.n_T * (1 + wl.n_or) * n)
+            ready.wait()
+            sim.run(n, n_or=wl.n_or, pt_every=wl.pt_every, meas_every=0)
+            done[k] = time.perf_counter()
+        except BaseException as exc:             # noqa: BLE001 - reported by the caller
+            errors.append(exc)
+            ready.abort()
+
+    threads = [threading.Thread(target=run, args=(k,)) for k in range(workers)]
+    for th in threads:
+        th.start()
+    try:
+        ready.wait()                             # the common start
+    except threading.BrokenBarrierError:
+        pass
+    t0 = time.perf_counter()
+    for th in threads:
+        th.join()
+    if errors:
+        raise errors[0]
+    wall = max(done) - t0
+    upd = sum(u for _, u in plans)
+    sweeps = sorted(set(n for n, _ in plans))
+    return {"value": upd / (wall * 1e9), "unit": "spin updates/ns", "cores": workers, "kind": "oracle",
+            "sample": f"samples 0-{workers - 1} of the workload (L={wl.samples[0].L}, {wl.n_T} T), one per thread, "
+                      f"{sweeps[0]}-{sweeps[-1]} sweeps each with PT, {upd} updates in {wall:.1f} s"}
 
 
 def main():
@@ -178,6 +205,8 @@ def main():
     ap.add_argument("--precision", default="fix16", choices=["fix16", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=8, help="sweeps of the FP64 plain comparison (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle time budget (0 = skip)")
+    ap.add_argument("--cpu-workers", type=int, default=min(16, len(os.sched_getaffinity(0))),
+                    help="oracle threads, one sample each (default: the host cores, at most 16)")
     ap.add_argument("--split-steps", type=int, default=8,
                     help="sweeps of the Metropolis-only run that splits the rate into Met and OR (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -269,7 +298,7 @@ def main():
                  "note": "Metropolis-only sweeps (n_or=0) timed separately; OR from the difference"}
         print(f"# split: Met {split['met_only']} / OR {split['or_only']} updates/ns", file=sys.stderr, flush=True)
 
-    cpu = cpu_baseline(wl, args.cpu_seconds) if args.cpu_seconds > 0 else None
+    cpu = cpu_baseline(wl, args.cpu_seconds, args.cpu_workers) if args.cpu_seconds > 0 else None
     s0 = wl.samples[0]
     out = {
         "metric": "spin updates/ns at L=256 rho=3.5 (fixed-point batched vs FP64 plain), %HBM roof",
