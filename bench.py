@@ -295,7 +295,8 @@ def main():
         split = {"met_only": round(n_upd / (met["kernel_ms"] * 1e6), 2),
                  "or_only": round(wl.n_or * n_upd / (or_ms * 1e6), 2) if or_ms > 0 else None,
                  "unit": "spin updates/ns (kernel time)", "met_kernel_ms": round(met["kernel_ms"], 4),
-                 "note": "Metropolis-only sweeps (n_or=0) timed separately; OR from the difference"}
+                 "note": "Metropolis-only sweeps (n_or=0, whose one sub-sweep also sums the energy for tempering) "
+                         "timed separately; OR from the difference"}
         print(f"# split: Met {split['met_only']} / OR {split['or_only']} updates/ns", file=sys.stderr, flush=True)
 
     cpu = cpu_baseline(wl, args.cpu_seconds, args.cpu_workers) if args.cpu_seconds > 0 else None

@@ -112,6 +112,29 @@ def test_tiny_graphs_exact_energy(name, n, edges, trig, monkeypatch):
         assert abs(m - _tiny_exact(name, 1 / t)) < 4 * err, (name, t, m, _tiny_exact(name, 1 / t), err)
 
 
+@pytest.mark.parametrize("R", [8, 64, 256])
+@pytest.mark.parametrize("name,n,edges", [("triangle", 3, [(0, 1), (1, 2), (2, 0)]),
+                                          ("cycle4", 4, [(0, 1), (1, 2), (2, 3), (3, 0)])])
+def test_tiny_graphs_exact_energy_phase_form(name, n, edges, R, monkeypatch):
+    """The phase form at R = 8, 64, 256 (four temperatures, each repeated R/4
+    times: tempering between equal temperatures only permutes the labels)
+    against the exact energies; every (sample, label) is one chain."""
+    monkeypatch.setenv("XY_FIX16_PHASE", "1")
+    base = np.array([0.8, 1.2, 1.6, 2.0])
+    T = np.repeat(base, R // 4)
+    n_samples = max(4, 1024 // R)
+    g = xy.Graph.from_edges(n, edges)
+    b = xy.Batch([g] * n_samples, T, precision="fix16", seeds=np.arange(n_samples) + 300, max_records=250)
+    assert b.forms().all()
+    b.sweep(200, pt_every=1, meas_every=0)
+    b.sweep(2000, pt_every=1, meas_every=8)
+    rec = b.records().cpu().numpy()            # [250, samples, R, 8]
+    for k, t in enumerate(base):
+        chains = rec[:, :, k * (R // 4):(k + 1) * (R // 4), 0].mean(axis=0).ravel()
+        m, err = chains.mean(), chains.std(ddof=1) / np.sqrt(chains.size)
+        assert abs(m - _tiny_exact(name, 1 / t)) < 4 * err, (name, R, t, m, _tiny_exact(name, 1 / t), err)
+
+
 def _set_form(monkeypatch, form):
     """Storage form of the fixed-point sweep: unit vectors in LDS (default for
     small graphs), angles in LDS, angles in global memory, or the phase form
