@@ -215,6 +215,35 @@ xy_status xy_batch_set_fix16_form(xy_batch *b, int trig, int allow_unit, int for
  * for every sample).  out: host int32[n_graphs], caller-owned. */
 xy_status xy_batch_forms(const xy_batch *b, int32_t *out);
 
+/* ----------------------------------------------------------------------- */
+/* Random walks for the spectral dimension (Sec. 2, spectral dimension;    */
+/* App. A): P(tau), the probability that a walker is back at its starting  */
+/* site after tau steps, behaves as tau^(-dbar/2).                          */
+/* ----------------------------------------------------------------------- */
+
+/* Device bytes for the walk graphs of xy_random_walk (n_graphs >= 1). */
+xy_status xy_walk_bytes(const xy_graph *const *g, int n_graphs, size_t *graph_bytes);
+
+/* Self-return histograms of n_walkers walkers on each graph, into
+ * caller-owned device memory d_hist: uint64[n_graphs][n_steps + 1], entry
+ * (g, t) = walkers of graph g at their start after t steps (t = 0 counts
+ * them all).  Walker w of graph g, under the Philox key seeds[g], starts at
+ *   start_mode 0: the lattice centre, site (L/2) L + L/2 (needs N = L*L);
+ *   start_mode 1: the k-th site, in lattice order, of degree larger than
+ *     two, k = floor(x * count / 2^32), x word 0 of counter (w, 0, 0, 8<<24);
+ * step t moves to the site's neighbour number floor(x * deg / 2^32),
+ * neighbours in ascending lattice index, x word t mod 4 of counter
+ * (w, floor(t/4), 0, 7<<24); a walker on a site of degree 0 stays.
+ * d_graph: graph_bytes (xy_walk_bytes) of device memory, 256-byte aligned,
+ * filled by this call.  0 <= n_walkers, 0 <= n_steps < 2^24.  The call
+ * uploads the graphs on `stream` and synchronises it before returning (the
+ * host staging buffer is released); the walks run asynchronously after.
+ * Errors: XY_EINVAL for bad arguments or start_mode 0 on a graph that is not
+ * L x L, XY_EUNSUP for start_mode 1 on a graph with no site of degree > 2. */
+xy_status xy_random_walk(const xy_graph *const *g, int n_graphs, int n_walkers, int n_steps,
+                         const uint64_t *seeds, int start_mode, void *d_graph, size_t graph_bytes,
+                         uint64_t *d_hist, void *stream);
+
 const char *xy_last_error(void);
 void xy_batch_free(xy_batch *b);
 

@@ -60,6 +60,9 @@ def lib():
     L.oxy_levy_weight_total.restype = ctypes.c_double
     L.oxy_slo_colour.argtypes = [ctypes.c_int, ctypes.c_int, _i32p, _i32p]
     L.oxy_slo_colour.restype = ctypes.c_int
+    L.oxy_random_walk.argtypes = [ctypes.c_int, ctypes.c_int, _i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    L.oxy_random_walk.restype = ctypes.c_int
     L.oxy_frozen_field_chain.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_uint64, ctypes.c_int, ctypes.c_int, _f64p]
     L.oxy_frozen_field_chain.restype = ctypes.c_int
@@ -135,6 +138,20 @@ def slo_colour(n, edges):
     if q < 0:
         raise MemoryError("oxy_slo_colour")
     return colour, q
+
+
+def random_walk(n, edges, L, n_walkers, n_steps, seed, start_mode=1, return_starts=False):
+    """Self-return histogram of random walkers (App. A): uint64[n_steps + 1],
+    entry t = walkers at their start after t steps.  start_mode 0: the lattice
+    centre; 1: a random site of degree > 2 per walker."""
+    edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+    hist = np.zeros(n_steps + 1, dtype=np.uint64)
+    starts = np.zeros(max(n_walkers, 1), dtype=np.int32)
+    rc = lib().oxy_random_walk(n, edges.shape[0], edges, L, n_walkers, n_steps, seed, start_mode,
+                               hist.ctypes.data, starts.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oxy_random_walk: {rc}")
+    return (hist, starts[:n_walkers]) if return_starts else hist
 
 
 def frozen_field_chain(hx, hy, beta, seed, n_moves, or_every=0):

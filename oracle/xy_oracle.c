@@ -24,6 +24,9 @@
  * Philox counter layout, smallest-index tie break in SLO, even/odd PT pairing
  * by sweep parity, swap of temperature labels (not spins).
  *
+ *   - random walks, histogram of self-return times                   (Sec. 2, spectral dimension;
+ *                                                                    App. A)
+ *
  * Parity status of each function is stated in its comment ("pinned by ...").
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -std=c99 -shared -fPIC.
  */
@@ -63,7 +66,7 @@ void oxy_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
 }
 
 /* Purposes of a draw (top byte of counter word 3). */
-enum { P_GRAPH = 1, P_INIT = 2, P_MET = 3, P_MET_ACC = 4, P_OR = 5, P_PT = 6 };
+enum { P_GRAPH = 1, P_INIT = 2, P_MET = 3, P_MET_ACC = 4, P_OR = 5, P_PT = 6, P_RW = 7, P_RW_START = 8 };
 
 static void draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
                  uint32_t c3, uint32_t w[4])
@@ -673,4 +676,80 @@ int oxy_frozen_field_chain(double hx, double hy, double beta, uint64_t seed,
         ang_out[t] = atan2(y, x);
     }
     return acc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Random walks on the graph (Sec. 2, spectral dimension; App. A).  P(tau), */
+/* the probability that a walker is back at its starting site after tau     */
+/* steps, behaves as tau^(-dbar/2), dbar the spectral dimension.            */
+/*                                                                          */
+/* Walker w (0..n_walkers-1) starts at                                      */
+/*   start_mode 0: the lattice centre, site (L/2) L + L/2;                  */
+/*   start_mode 1: the k-th site, in lattice order, of degree larger than   */
+/*     two, k = (x count) >> 32, x word 0 of the draw (w, 0, 0, P_RW_START).*/
+/* Step t (t = 0 .. n_steps-1) moves from the current site to its neighbour */
+/* number (x deg) >> 32, neighbours in ascending lattice index, x word      */
+/* t mod 4 of the draw (w, t / 4, 0, P_RW).  A walker on a site of degree 0 */
+/* stays.  hist[t] (t = 0 .. n_steps) counts the walkers at their start     */
+/* after t steps, so hist[0] = n_walkers.  starts (may be NULL) receives    */
+/* the starting sites.                                                      */
+/* Pinned by: the square lattice, whose return probability after 2n steps   */
+/* is (C(2n,n)/4^n)^2 and after an odd number 0, and the start-site rule.   */
+/* Returns 0, -1 on bad arguments, -2 without an eligible start, -3 on      */
+/* allocation failure.                                                      */
+/* ------------------------------------------------------------------------ */
+static int cmp_i32(const void *a, const void *b)
+{
+    const int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+int oxy_random_walk(int n, int m, const int32_t *edges, int L, int n_walkers, int n_steps,
+                    uint64_t seed, int start_mode, uint64_t *hist, int32_t *starts)
+{
+    int32_t *deg, *off, *nbr, *fill, *elig = NULL;
+    int i, e, w, t, n_elig = 0, rc = 0;
+    if (n < 1 || m < 0 || n_walkers < 0 || n_steps < 0 || (start_mode != 0 && start_mode != 1)) return -1;
+    if (start_mode == 0 && (L < 2 || L * L != n)) return -1;
+    deg = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+    off = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+    fill = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+    nbr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * m + 1));
+    if (!deg || !off || !fill || !nbr) { rc = -3; goto done; }
+    for (e = 0; e < m; e++) { deg[edges[2 * e]]++; deg[edges[2 * e + 1]]++; }
+    for (i = 0; i < n; i++) off[i + 1] = off[i] + deg[i];
+    for (e = 0; e < m; e++) {
+        const int32_t a = edges[2 * e], b = edges[2 * e + 1];
+        nbr[off[a] + fill[a]++] = b;
+        nbr[off[b] + fill[b]++] = a;
+    }
+    for (i = 0; i < n; i++) qsort(nbr + off[i], (size_t)deg[i], sizeof(int32_t), cmp_i32);
+    if (start_mode == 1) {
+        elig = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+        if (!elig) { rc = -3; goto done; }
+        for (i = 0; i < n; i++) if (deg[i] > 2) elig[n_elig++] = i;
+        if (n_elig == 0) { rc = -2; goto done; }
+    }
+    for (t = 0; t <= n_steps; t++) hist[t] = 0;
+    for (w = 0; w < n_walkers; w++) {
+        uint32_t x[4];
+        int32_t s0, cur;
+        if (start_mode == 0) {
+            s0 = (L / 2) * L + L / 2;
+        } else {
+            draw(seed, (uint32_t)w, 0u, 0u, (uint32_t)P_RW_START << 24, x);
+            s0 = elig[(uint32_t)(((uint64_t)x[0] * (uint64_t)n_elig) >> 32)];
+        }
+        if (starts) starts[w] = s0;
+        cur = s0;
+        hist[0]++;
+        for (t = 0; t < n_steps; t++) {
+            if ((t & 3) == 0) draw(seed, (uint32_t)w, (uint32_t)(t >> 2), 0u, (uint32_t)P_RW << 24, x);
+            if (deg[cur] > 0) cur = nbr[off[cur] + (int32_t)(((uint64_t)x[t & 3] * (uint64_t)deg[cur]) >> 32)];
+            if (cur == s0) hist[t + 1]++;
+        }
+    }
+done:
+    free(deg); free(off); free(fill); free(nbr); free(elig);
+    return rc;
 }

@@ -7,8 +7,9 @@ sweeps with parallel tempering (App. B) of O(2) spins on Levy graphs
 
 This package is a thin Python face of ``libxylevy.so`` (C ABI declared in
 ``include/xy_levy.h``): ``Graph`` wraps the host graph path (sampling,
-smallest-last colouring, colour-sorted CSR) and ``Batch`` wraps the device
-path (HIP kernels for gfx950).  PyTorch only provides device memory and the
+smallest-last colouring, colour-sorted CSR), ``Batch`` wraps the device
+path (HIP kernels for gfx950) and ``random_walk`` the self-return histograms
+of random walkers (App. A).  PyTorch only provides device memory and the
 stream; every step of the computation runs in the library.
 """
 import ctypes
@@ -18,7 +19,7 @@ import numpy as np
 from . import _lib
 from ._lib import XY_FIX16, XY_FP64, XY_NOBS, XYError
 
-__all__ = ["Graph", "Batch", "XYError", "XY_FP64", "XY_FIX16", "XY_NOBS", "OBS_NAMES"]
+__all__ = ["Graph", "Batch", "random_walk", "XYError", "XY_FP64", "XY_FIX16", "XY_NOBS", "OBS_NAMES"]
 
 OBS_NAMES = ("E", "m2", "m4", "Fx", "Fy", "mx", "my", "pad")
 _PREC = {"fp64": XY_FP64, "fix16": XY_FIX16}
@@ -231,3 +232,32 @@ class Batch:
 
     def __del__(self):
         self.close()
+
+
+_WALK_START = {"centre": 0, "degree3": 1}
+
+
+def random_walk(graphs, n_walkers, n_steps, seeds=None, start="degree3", stream=None):
+    """Self-return histograms of random walkers on each graph (Sec. 2, spectral
+    dimension; App. A): a torch.int64 [n_graphs, n_steps + 1] device tensor,
+    entry (g, t) = walkers of graph g back at their start after t steps.
+    start: "centre" (the lattice centre) or "degree3" (a random site of degree
+    > 2 per walker).  The result is ready once `stream` (default: the current
+    stream) has reached it."""
+    import torch
+    G = len(graphs)
+    seeds = np.arange(G, dtype=np.uint64) if seeds is None else np.ascontiguousarray(seeds, dtype=np.uint64)
+    if seeds.shape != (G,):
+        raise ValueError("one seed per graph")
+    garr = (ctypes.c_void_p * G)(*[g._h.value for g in graphs])
+    nbytes = ctypes.c_size_t()
+    _lib.call("xy_walk_bytes", garr, G, ctypes.byref(nbytes))
+    st = stream if stream is not None else torch.cuda.current_stream()
+    with torch.cuda.stream(st):
+        d_graph = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device="cuda")
+        hist = torch.empty((G, n_steps + 1), dtype=torch.int64, device="cuda")
+    _lib.call("xy_random_walk", garr, G, int(n_walkers), int(n_steps), ctypes.c_void_p(seeds.ctypes.data),
+              _WALK_START[start], ctypes.c_void_p(d_graph.data_ptr()), nbytes.value,
+              ctypes.c_void_p(hist.data_ptr()), ctypes.c_void_p(st.cuda_stream))
+    # d_graph is released to the caching allocator on `st`, after the walk in stream order
+    return hist

@@ -190,3 +190,23 @@ def bethe_tc(excess_degree):
     from scipy.special import i0e, i1e
     f = lambda b: i1e(b) / i0e(b) - 1.0 / excess_degree
     return 1.0 / brentq(f, 1e-9, 50.0)
+
+
+def spectral_dimension(hist, t_min, t_max):
+    """Spectral dimension from a self-return histogram (Sec. 2, spectral
+    dimension; App. A): P(tau) ~ tau^(-dbar/2), so dbar = -2 x the slope of
+    log hist against log tau over t_min <= tau <= t_max (times with no return
+    are skipped, e.g. odd times on a bipartite graph).  Weighted least squares
+    with Poisson weights (variance of log count ~ 1 / count).  Returns
+    (dbar, its standard error from the fit)."""
+    h = np.asarray(hist, dtype=np.float64)
+    t = np.arange(h.size, dtype=np.float64)
+    sel = (t >= t_min) & (t <= t_max) & (h > 0)
+    if sel.sum() < 3:
+        raise ValueError("need at least three times with returns in the window")
+    x, y, w = np.log(t[sel]), np.log(h[sel]), h[sel]
+    A = np.stack([np.ones_like(x), x], axis=1)
+    Aw = A * w[:, None]
+    cov = np.linalg.inv(A.T @ Aw)
+    coef = cov @ (Aw.T @ y)
+    return float(-2.0 * coef[1]), float(2.0 * np.sqrt(cov[1, 1]))

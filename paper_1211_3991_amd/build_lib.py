@@ -22,6 +22,7 @@ HIP_SOURCES = {
     "kernels_fp64.hip": ["-ffp-contract=off"],
     "kernels_fix16.hip": [],
     "kernels_phase.hip": [],
+    "kernels_walk.hip": [],
     "runtime.hip": ["-ffp-contract=off"],
 }
 CXX_SOURCES = {"graph.cpp": ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wextra"]}

@@ -1,0 +1,200 @@
+// Random walks on the graphs (Sec. 2, spectral dimension; App. A): the
+// histogram of the times at which a walker is back at its starting site
+// estimates P(tau) ~ tau^(-dbar/2).  One thread per walker, all graphs in one
+// launch.  A step is two dependent loads: the site's (first neighbour, degree)
+// record, then the chosen neighbour; one Philox4x32-10 call serves four steps.
+// The per-block histogram lives in LDS (walks up to 8191 steps; longer ones
+// count in global memory) and is added to the caller's histogram with 64-bit
+// integer atomics, so the result does not depend on the order in which
+// walkers finish.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "xy_internal.hpp"
+
+namespace xy {
+namespace {
+
+struct WalkDesc {
+    int64_t od;        // int2 pool: (first neighbour, degree) per site
+    int64_t nbr;       // int32 pool: neighbours, ascending lattice index per site
+    int64_t elig;      // int32 pool: sites of degree > 2, ascending
+    int32_t n, n_elig, centre, pad_;
+    uint32_t seed_lo, seed_hi;
+};
+
+constexpr int kWalkBlock = 256;
+constexpr int kWalkLdsBins = 8192;      // steps + 1 up to this: LDS histogram
+
+template <bool kLds>
+__global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkDesc *desc, const int2 *od_pool, const int32_t *i32,
+                                                    int n_walkers, int n_steps, int start_mode,
+                                                    unsigned long long *hist)
+{
+    __shared__ uint32_t lds[kLds ? kWalkLdsBins : 1];
+    const WalkDesc d = desc[blockIdx.y];
+    unsigned long long *h = hist + (int64_t)blockIdx.y * (n_steps + 1);
+    const int w = blockIdx.x * kWalkBlock + threadIdx.x;
+    if constexpr (kLds) {
+        for (int t = threadIdx.x; t <= n_steps; t += kWalkBlock) lds[t] = 0u;
+        __syncthreads();
+    }
+    if (w < n_walkers) {
+        const int2 *od = od_pool + d.od;
+        const int32_t *nbr = i32 + d.nbr;
+        int s0 = d.centre;
+        if (start_mode == 1) {
+            const U4 x = philox4x32_10({(uint32_t)w, 0u, 0u, (uint32_t)kWalkStart << 24}, d.seed_lo, d.seed_hi);
+            s0 = i32[d.elig + (int)(((uint64_t)x.x * (uint32_t)d.n_elig) >> 32)];
+        }
+        int cur = s0;
+        U4 x{};
+        for (int t = 0; t < n_steps; ++t) {
+            if ((t & 3) == 0)
+                x = philox4x32_10({(uint32_t)w, (uint32_t)(t >> 2), 0u, (uint32_t)kWalk << 24}, d.seed_lo, d.seed_hi);
+            const uint32_t r = (t & 3) == 0 ? x.x : (t & 3) == 1 ? x.y : (t & 3) == 2 ? x.z : x.w;
+            const int2 e = od[cur];
+            if (e.y > 0) cur = nbr[e.x + (int)(((uint64_t)r * (uint32_t)e.y) >> 32)];
+            if (cur == s0) {
+                if constexpr (kLds) atomicAdd(&lds[t + 1], 1u); else atomicAdd(&h[t + 1], 1ull);
+            }
+        }
+    }
+    if constexpr (kLds) {
+        __syncthreads();
+        for (int t = threadIdx.x + 1; t <= n_steps; t += kWalkBlock)
+            if (lds[t]) atomicAdd(&h[t], (unsigned long long)lds[t]);
+    }
+}
+
+// The histograms before the walks: every walker is at its start at t = 0.
+__global__ void k_walk_hist_init(unsigned long long *p, int64_t n, int bins, int n_walkers)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (i % bins) == 0 ? (unsigned long long)n_walkers : 0ull;
+}
+
+struct WalkPlan {
+    std::vector<WalkDesc> desc;
+    size_t n_od = 0, n_i32 = 0;
+    size_t off_desc = 0, off_od = 0, off_i32 = 0, total = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+xy_status plan_walk(const xy_graph *const *g, int G, WalkPlan &p)
+{
+    if (!g || G < 1 || G > 65535) return set_error(XY_EINVAL, "walk: need 1 to 65535 graphs");
+    p.desc.assign(G, WalkDesc{});
+    for (int k = 0; k < G; ++k) {
+        if (!g[k]) return set_error(XY_EINVAL, "walk: NULL graph");
+        const xy_graph &gr = *g[k];
+        WalkDesc &d = p.desc[k];
+        d.n = gr.n;
+        d.od = (int64_t)p.n_od;     p.n_od += gr.n;
+        d.nbr = (int64_t)p.n_i32;   p.n_i32 += 2 * (size_t)gr.m;
+        d.elig = (int64_t)p.n_i32;  p.n_i32 += gr.n;
+    }
+    p.off_desc = 0;
+    p.off_od = align256(sizeof(WalkDesc) * G);
+    p.off_i32 = align256(p.off_od + 8 * p.n_od);
+    p.total = align256(p.off_i32 + 4 * p.n_i32);
+    return XY_OK;
+}
+
+}  // namespace
+}  // namespace xy
+
+using namespace xy;
+
+extern "C" xy_status xy_walk_bytes(const xy_graph *const *g, int n_graphs, size_t *graph_bytes)
+{
+    if (!graph_bytes) return set_error(XY_EINVAL, "xy_walk_bytes: graph_bytes is NULL");
+    WalkPlan p;
+    const xy_status st = plan_walk(g, n_graphs, p);
+    if (st != XY_OK) return st;
+    *graph_bytes = p.total;
+    return XY_OK;
+}
+
+extern "C" xy_status xy_random_walk(const xy_graph *const *g, int n_graphs, int n_walkers, int n_steps,
+                                    const uint64_t *seeds, int start_mode, void *d_graph, size_t graph_bytes,
+                                    uint64_t *d_hist, void *stream)
+{
+    if (n_walkers < 0 || n_steps < 0 || n_steps >= (1 << 24) || !seeds || !d_graph || !d_hist ||
+        (start_mode != 0 && start_mode != 1))
+        return set_error(XY_EINVAL, "xy_random_walk: bad arguments");
+    if ((reinterpret_cast<uintptr_t>(d_graph) & 255) != 0)
+        return set_error(XY_EINVAL, "xy_random_walk: d_graph must be 256-byte aligned");
+    try {
+        WalkPlan p;
+        const xy_status st = plan_walk(g, n_graphs, p);
+        if (st != XY_OK) return st;
+        if (graph_bytes < p.total) return set_error(XY_EINVAL, "xy_random_walk: d_graph smaller than xy_walk_bytes");
+        std::vector<unsigned char> img(p.total, 0);
+        int2 *od = reinterpret_cast<int2 *>(img.data() + p.off_od);
+        int32_t *i32 = reinterpret_cast<int32_t *>(img.data() + p.off_i32);
+        std::vector<int32_t> deg, fill;
+        for (int k = 0; k < n_graphs; ++k) {
+            const xy_graph &gr = *g[k];
+            WalkDesc &d = p.desc[k];
+            const int n = gr.n;
+            deg.assign(n, 0);
+            for (int e = 0; e < gr.m; ++e) { ++deg[gr.edges[2 * e]]; ++deg[gr.edges[2 * e + 1]]; }
+            int32_t acc = 0;
+            for (int i = 0; i < n; ++i) { od[d.od + i] = make_int2(acc, deg[i]); acc += deg[i]; }
+            int32_t *nb = i32 + d.nbr;
+            fill.assign(n, 0);
+            for (int e = 0; e < gr.m; ++e) {
+                const int a = gr.edges[2 * e], b = gr.edges[2 * e + 1];
+                nb[od[d.od + a].x + fill[a]++] = b;
+                nb[od[d.od + b].x + fill[b]++] = a;
+            }
+            for (int i = 0; i < n; ++i) std::sort(nb + od[d.od + i].x, nb + od[d.od + i].x + deg[i]);
+            int n_elig = 0;
+            for (int i = 0; i < n; ++i)
+                if (deg[i] > 2) i32[d.elig + n_elig++] = i;
+            d.n_elig = n_elig;
+            if (start_mode == 1 && n_elig == 0)
+                return set_error(XY_EUNSUP, "xy_random_walk: a graph has no site of degree > 2");
+            if (start_mode == 0) {
+                if (gr.L < 2 || gr.L * gr.L != n) return set_error(XY_EINVAL, "xy_random_walk: centre start needs an L x L graph");
+                d.centre = (gr.L / 2) * gr.L + gr.L / 2;
+            }
+            d.seed_lo = (uint32_t)seeds[k];
+            d.seed_hi = (uint32_t)(seeds[k] >> 32);
+        }
+        std::memcpy(img.data() + p.off_desc, p.desc.data(), sizeof(WalkDesc) * n_graphs);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        hipError_t e = hipMemcpyAsync(d_graph, img.data(), p.total, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        const int64_t n_hist = (int64_t)n_graphs * (n_steps + 1);
+        auto *h = reinterpret_cast<unsigned long long *>(d_hist);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_walk_hist_init, dim3((unsigned)((n_hist + 255) / 256)), dim3(256), 0, s, h, n_hist,
+                               n_steps + 1, n_walkers);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess && n_walkers > 0) {
+            unsigned char *base = static_cast<unsigned char *>(d_graph);
+            const auto *dd = reinterpret_cast<const WalkDesc *>(base + p.off_desc);
+            const auto *dod = reinterpret_cast<const int2 *>(base + p.off_od);
+            const auto *di = reinterpret_cast<const int32_t *>(base + p.off_i32);
+            const dim3 grid((unsigned)((n_walkers + kWalkBlock - 1) / kWalkBlock), (unsigned)n_graphs);
+            if (n_steps + 1 <= kWalkLdsBins)
+                hipLaunchKernelGGL(k_walk<true>, grid, dim3(kWalkBlock), 0, s, dd, dod, di, n_walkers, n_steps,
+                                   start_mode, h);
+            else
+                hipLaunchKernelGGL(k_walk<false>, grid, dim3(kWalkBlock), 0, s, dd, dod, di, n_walkers, n_steps,
+                                   start_mode, h);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess) return set_error(XY_EHIP, std::string("xy_random_walk: ") + hipGetErrorString(e));
+        return XY_OK;
+    } catch (const std::bad_alloc &) {
+        return set_error(XY_ENOMEM, "xy_random_walk: host allocation failed");
+    }
+}

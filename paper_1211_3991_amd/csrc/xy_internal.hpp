@@ -49,7 +49,7 @@ XY_HD U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
 
 // Draw purposes: top byte of counter word w.  Word z carries the slot,
 // word y the sweep, word x the site (or the draw index).
-enum Purpose : uint32_t { kGraph = 1, kInit = 2, kMet = 3, kMetAcc = 4, kOR = 5, kPT = 6 };
+enum Purpose : uint32_t { kGraph = 1, kInit = 2, kMet = 3, kMetAcc = 4, kOR = 5, kPT = 6, kWalk = 7, kWalkStart = 8 };
 
 XY_HD uint32_t tag(Purpose p, uint32_t sub = 0, uint32_t attempt = 0)
 {

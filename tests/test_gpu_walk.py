@@ -1,0 +1,82 @@
+"""GPU random walks (Sec. 2, spectral dimension; App. A) against the oracle.
+
+The walks are integer work driven by counter-based draws, so the bar is exact:
+every histogram entry equals the oracle's, for both start rules, ragged walker
+counts, short walks (LDS histogram) and long ones (global histogram), and the
+full benchmark shape (20 graphs of L=196, rho=3.5, z=4, 4x10^4 walkers each,
+4096 steps) on sampled graphs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1211_3991_amd as xy  # noqa: E402
+from paper_1211_3991_amd import analysis  # noqa: E402
+
+
+def _oracle_hist(L, z, rho, gseed, n_walkers, n_steps, wseed, mode):
+    e, _ = oracle.levy_graph(L, z, rho, gseed)
+    return oracle.random_walk(L * L, e, L, n_walkers, n_steps, wseed, start_mode=mode)
+
+
+@pytest.mark.parametrize("start,mode", [("degree3", 1), ("centre", 0)])
+@pytest.mark.parametrize("n_walkers,n_steps", [(3000, 300), (1, 40), (257, 1000), (300, 9000)])
+def test_histograms_equal_oracle(start, mode, n_walkers, n_steps):
+    specs = [(32, 6, 3.5, 1), (32, 4, 2.5, 2), (16, 6, 4.5, 3)]
+    graphs = [xy.Graph.levy(L, z, rho, s) for L, z, rho, s in specs]
+    seeds = np.array([11, 12, 13], dtype=np.uint64)
+    h = xy.random_walk(graphs, n_walkers, n_steps, seeds=seeds, start=start)
+    torch.cuda.synchronize()
+    h = h.cpu().numpy().view(np.uint64)
+    assert h.shape == (3, n_steps + 1)
+    for k, (L, z, rho, s) in enumerate(specs):
+        ref = _oracle_hist(L, z, rho, s, n_walkers, n_steps, int(seeds[k]), mode)
+        assert np.array_equal(h[k], ref), f"graph {k}: first difference at t = {np.flatnonzero(h[k] != ref)[:1]}"
+
+
+def test_degenerate_sizes_and_isolated_centre():
+    g = xy.Graph.levy(16, 6, 3.5, 4)
+    h = xy.random_walk([g], 10, 0).cpu().numpy()
+    assert h.shape == (1, 1) and h[0, 0] == 10
+    h = xy.random_walk([g], 0, 20).cpu().numpy()
+    assert not h.any()
+    # the centre of this 4 x 4 graph, site 10, has no link: the walker stays
+    iso = xy.Graph.from_edges(16, [(0, 1), (1, 2)], L=4)
+    h = xy.random_walk([iso], 3, 5, start="centre").cpu().numpy()
+    assert np.array_equal(h[0], np.full(6, 3))
+
+
+def test_errors():
+    ring = xy.Graph.from_edges(6, [(i, (i + 1) % 6) for i in range(6)])
+    with pytest.raises(xy.XYError):
+        xy.random_walk([ring], 10, 10, start="degree3")       # no site of degree > 2
+    g = xy.Graph.levy(16, 6, 3.5, 4)
+    with pytest.raises(xy.XYError):
+        xy.random_walk([g], -1, 10)
+
+
+def test_benchmark_shape_sampled():
+    """20 graphs of L=196, rho=3.5, z=4, 4x10^4 walkers each, 4096 steps:
+    graphs 0 and 19 equal the oracle entry by entry."""
+    G, W, T = 20, 40000, 4096
+    graphs = [xy.Graph.levy(196, 4, 3.5, 500 + k) for k in range(G)]
+    seeds = np.arange(G, dtype=np.uint64) + 900
+    h = xy.random_walk(graphs, W, T, seeds=seeds).cpu().numpy().view(np.uint64)
+    for k in (0, 19):
+        ref = _oracle_hist(196, 4, 3.5, 500 + k, W, T, int(seeds[k]), 1)
+        assert np.array_equal(h[k], ref), k
+
+
+def test_square_lattice_spectral_dimension():
+    """The z = 4, large-rho graph is the square lattice: dbar = 2."""
+    g = xy.Graph.levy(256, 4, 60.0, 1)
+    h = xy.random_walk([g], 200000, 1024, start="centre").cpu().numpy()[0]
+    d, err = analysis.spectral_dimension(h, 32, 1024)
+    assert abs(d - 2.0) < max(0.05, 4 * err), (d, err)
