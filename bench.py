@@ -94,6 +94,29 @@ def time_gpu(wl, precision, steps, warmup, graphs, torch, xy, n_or=None, form=No
             "pt_rate": float(acc.sum()) / max(float(tries.sum()), 1.0), "autotune": tune}
 
 
+def time_walk(xy):
+    """The random-walk workload of App. A: 20 graphs of L=196 (rho=3.5, z=4),
+    4x10^4 walkers each starting on sites of degree > 2, 4096 steps.  Rate
+    from the walk kernel's own duration (HIP events around it)."""
+    from paper_1211_3991_amd import analysis
+    G, W, T, L, rho = 20, 40000, 4096, 196, 3.5
+    graphs = [xy.Graph.levy(L, 4, rho, 500 + k) for k in range(G)]
+    seeds = np.arange(G, dtype=np.uint64) + 900
+    xy.random_walk(graphs, W, 16, seeds=seeds, timing=True)          # first launch
+    hist, ms = xy.random_walk(graphs, W, T, seeds=seeds, timing=True)
+    steps = G * W * T
+    d, err = analysis.spectral_dimension(hist.cpu().numpy().sum(axis=0), 32, 1024)
+    bps = 12                       # (first neighbour, degree) record + one neighbour index per step
+    gbs = bps * steps / (ms * 1e6)
+    return {"value": round(steps / (ms * 1e6), 2), "unit": "walker steps/ns", "kernel_ms": round(ms, 3),
+            "workload": f"{G} graphs of L={L} (rho={rho}, z=4), {W} walkers each from sites of degree > 2, {T} steps",
+            "dbar": round(d, 3), "dbar_err": round(err, 3), "dbar_formula": round(2 * 2 / (rho - 2), 3),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes_per_step": bps,
+                         "note": "two dependent gathers per step; the graphs (about 21 MB) stay in L2/MALL, "
+                                 "so latency, not HBM bandwidth, binds"}}
+
+
 def _pmc_rows(path):
     with open(path, newline="") as fh:
         rows = list(csv.DictReader(fh))
@@ -207,6 +230,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle time budget (0 = skip)")
     ap.add_argument("--cpu-workers", type=int, default=min(16, len(os.sched_getaffinity(0))),
                     help="oracle threads, one sample each (default: the host cores, at most 16)")
+    ap.add_argument("--no-walk", action="store_true", help="skip the random-walk workload (App. A)")
     ap.add_argument("--split-steps", type=int, default=8,
                     help="sweeps of the Metropolis-only run that splits the rate into Met and OR (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -299,6 +323,12 @@ def main():
                          "timed separately; OR from the difference"}
         print(f"# split: Met {split['met_only']} / OR {split['or_only']} updates/ns", file=sys.stderr, flush=True)
 
+    walk = None
+    if not args.no_walk:
+        walk = time_walk(xy)
+        print(f"# random walk: {walk['value']} walker steps/ns, dbar {walk['dbar']} (formula {walk['dbar_formula']})",
+              file=sys.stderr, flush=True)
+
     cpu = cpu_baseline(wl, args.cpu_seconds, args.cpu_workers) if args.cpu_seconds > 0 else None
     s0 = wl.samples[0]
     out = {
@@ -315,6 +345,7 @@ def main():
         "roofline": roofline,
         "fp64_plain": fp64,
         "sub_sweep_rates": split,
+        "random_walk": walk,
         "cpu_baseline": cpu,
         "pt_acceptance": round(main_run["pt_rate"], 4),
         "autotune": main_run["autotune"],

@@ -237,12 +237,14 @@ xy_status xy_walk_bytes(const xy_graph *const *g, int n_graphs, size_t *graph_by
  * d_graph: graph_bytes (xy_walk_bytes) of device memory, 256-byte aligned,
  * filled by this call.  0 <= n_walkers, 0 <= n_steps < 2^24.  The call
  * uploads the graphs on `stream` and synchronises it before returning (the
- * host staging buffer is released); the walks run asynchronously after.
+ * host staging buffer is released); the walks run asynchronously after,
+ * unless kernel_ms is not NULL: then the call waits for them and stores the
+ * duration of the walk kernel in milliseconds (HIP events on `stream`).
  * Errors: XY_EINVAL for bad arguments or start_mode 0 on a graph that is not
  * L x L, XY_EUNSUP for start_mode 1 on a graph with no site of degree > 2. */
 xy_status xy_random_walk(const xy_graph *const *g, int n_graphs, int n_walkers, int n_steps,
                          const uint64_t *seeds, int start_mode, void *d_graph, size_t graph_bytes,
-                         uint64_t *d_hist, void *stream);
+                         uint64_t *d_hist, void *stream, float *kernel_ms);
 
 const char *xy_last_error(void);
 void xy_batch_free(xy_batch *b);

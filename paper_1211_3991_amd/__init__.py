@@ -237,13 +237,14 @@ class Batch:
 _WALK_START = {"centre": 0, "degree3": 1}
 
 
-def random_walk(graphs, n_walkers, n_steps, seeds=None, start="degree3", stream=None):
+def random_walk(graphs, n_walkers, n_steps, seeds=None, start="degree3", stream=None, timing=False):
     """Self-return histograms of random walkers on each graph (Sec. 2, spectral
     dimension; App. A): a torch.int64 [n_graphs, n_steps + 1] device tensor,
     entry (g, t) = walkers of graph g back at their start after t steps.
     start: "centre" (the lattice centre) or "degree3" (a random site of degree
     > 2 per walker).  The result is ready once `stream` (default: the current
-    stream) has reached it."""
+    stream) has reached it.  timing=True waits for the walks and returns
+    (histograms, milliseconds of the walk kernel)."""
     import torch
     G = len(graphs)
     seeds = np.arange(G, dtype=np.uint64) if seeds is None else np.ascontiguousarray(seeds, dtype=np.uint64)
@@ -256,8 +257,10 @@ def random_walk(graphs, n_walkers, n_steps, seeds=None, start="degree3", stream=
     with torch.cuda.stream(st):
         d_graph = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device="cuda")
         hist = torch.empty((G, n_steps + 1), dtype=torch.int64, device="cuda")
+    ms = ctypes.c_float()
     _lib.call("xy_random_walk", garr, G, int(n_walkers), int(n_steps), ctypes.c_void_p(seeds.ctypes.data),
               _WALK_START[start], ctypes.c_void_p(d_graph.data_ptr()), nbytes.value,
-              ctypes.c_void_p(hist.data_ptr()), ctypes.c_void_p(st.cuda_stream))
+              ctypes.c_void_p(hist.data_ptr()), ctypes.c_void_p(st.cuda_stream),
+              ctypes.byref(ms) if timing else None)
     # d_graph is released to the caching allocator on `st`, after the walk in stream order
-    return hist
+    return (hist, ms.value) if timing else hist

@@ -66,7 +66,8 @@ _sigs = {
     "xy_batch_set_fix16_form": ([_vp, _i32, _i32, _i32, _vp], _i32),
     "xy_batch_forms": ([_vp, _vp], _i32),
     "xy_walk_bytes": ([_vp, _i32, ctypes.POINTER(ctypes.c_size_t)], _i32),
-    "xy_random_walk": ([_vp, _i32, _i32, _i32, _vp, _i32, _vp, ctypes.c_size_t, _vp, _vp], _i32),
+    "xy_random_walk": ([_vp, _i32, _i32, _i32, _vp, _i32, _vp, ctypes.c_size_t, _vp, _vp,
+                        ctypes.POINTER(ctypes.c_float)], _i32),
     "xy_kernel_timing": ([_vp, _i32], _i32),
     "xy_kernel_time": ([_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_i32)], _i32),
     "xy_last_error": ([], ctypes.c_char_p),

@@ -27,38 +27,67 @@ struct WalkDesc {
 };
 
 constexpr int kWalkBlock = 256;
-constexpr int kWalkLdsBins = 8192;      // steps + 1 up to this: LDS histogram
+constexpr int kWalkers = 2;             // walkers per thread
+constexpr int kWalkLdsBins = 8192;      // steps + 1 up to this: LDS histogram (dynamic, 4 B a bin)
 
-template <bool kLds>
+// Each XCD takes one contiguous run of the (graph, block) units (the
+// hardware deals workgroup w to XCD w mod 8), so an XCD's L2 holds the few
+// graphs its walkers visit.  A bijection on [0, n).
+__device__ __forceinline__ int xcd_run(int lin, int n)
+{
+    const int x = lin & 7, k = lin >> 3, per = n >> 3, rem = n & 7;
+    return x * per + min(x, rem) + k;
+}
+
+// One thread runs kW walkers in lock step (their loads overlap).
+template <bool kLds, int kW>
 __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkDesc *desc, const int2 *od_pool, const int32_t *i32,
-                                                    int n_walkers, int n_steps, int start_mode,
+                                                    int n_walkers, int n_steps, int start_mode, int blocks_per_graph,
                                                     unsigned long long *hist)
 {
-    __shared__ uint32_t lds[kLds ? kWalkLdsBins : 1];
-    const WalkDesc d = desc[blockIdx.y];
-    unsigned long long *h = hist + (int64_t)blockIdx.y * (n_steps + 1);
-    const int w = blockIdx.x * kWalkBlock + threadIdx.x;
+    extern __shared__ uint32_t lds[];   // n_steps + 1 bins when kLds
+    const int unit = xcd_run(blockIdx.x, gridDim.x);
+    const int gi = unit / blocks_per_graph, bx = unit % blocks_per_graph;
+    const WalkDesc d = desc[gi];
+    unsigned long long *h = hist + (int64_t)gi * (n_steps + 1);
     if constexpr (kLds) {
         for (int t = threadIdx.x; t <= n_steps; t += kWalkBlock) lds[t] = 0u;
         __syncthreads();
     }
-    if (w < n_walkers) {
-        const int2 *od = od_pool + d.od;
-        const int32_t *nbr = i32 + d.nbr;
-        int s0 = d.centre;
-        if (start_mode == 1) {
-            const U4 x = philox4x32_10({(uint32_t)w, 0u, 0u, (uint32_t)kWalkStart << 24}, d.seed_lo, d.seed_hi);
-            s0 = i32[d.elig + (int)(((uint64_t)x.x * (uint32_t)d.n_elig) >> 32)];
+    const int2 *od = od_pool + d.od;
+    const int32_t *nbr = i32 + d.nbr;
+    int w[kW], s0[kW], cur[kW];
+    bool live[kW];
+#pragma unroll
+    for (int a = 0; a < kW; ++a) {
+        w[a] = (bx * kW + a) * kWalkBlock + threadIdx.x;
+        live[a] = w[a] < n_walkers;
+        s0[a] = d.centre;
+        if (live[a] && start_mode == 1) {
+            const U4 x = philox4x32_10({(uint32_t)w[a], 0u, 0u, (uint32_t)kWalkStart << 24}, d.seed_lo, d.seed_hi);
+            s0[a] = i32[d.elig + (int)(((uint64_t)x.x * (uint32_t)d.n_elig) >> 32)];
         }
-        int cur = s0;
-        U4 x{};
-        for (int t = 0; t < n_steps; ++t) {
+        cur[a] = s0[a];
+    }
+    U4 x[kW];
+    for (int t = 0; t < n_steps; ++t) {
+#pragma unroll
+        for (int a = 0; a < kW; ++a) {
             if ((t & 3) == 0)
-                x = philox4x32_10({(uint32_t)w, (uint32_t)(t >> 2), 0u, (uint32_t)kWalk << 24}, d.seed_lo, d.seed_hi);
-            const uint32_t r = (t & 3) == 0 ? x.x : (t & 3) == 1 ? x.y : (t & 3) == 2 ? x.z : x.w;
-            const int2 e = od[cur];
-            if (e.y > 0) cur = nbr[e.x + (int)(((uint64_t)r * (uint32_t)e.y) >> 32)];
-            if (cur == s0) {
+                x[a] = philox4x32_10({(uint32_t)w[a], (uint32_t)(t >> 2), 0u, (uint32_t)kWalk << 24}, d.seed_lo,
+                                     d.seed_hi);
+        }
+        int2 e[kW];
+#pragma unroll
+        for (int a = 0; a < kW; ++a) e[a] = od[cur[a]];
+#pragma unroll
+        for (int a = 0; a < kW; ++a) {
+            const uint32_t r = (t & 3) == 0 ? x[a].x : (t & 3) == 1 ? x[a].y : (t & 3) == 2 ? x[a].z : x[a].w;
+            if (e[a].y > 0) cur[a] = nbr[e[a].x + (int)(((uint64_t)r * (uint32_t)e[a].y) >> 32)];
+        }
+#pragma unroll
+        for (int a = 0; a < kW; ++a) {
+            if (live[a] && cur[a] == s0[a]) {
                 if constexpr (kLds) atomicAdd(&lds[t + 1], 1u); else atomicAdd(&h[t + 1], 1ull);
             }
         }
@@ -122,7 +151,7 @@ extern "C" xy_status xy_walk_bytes(const xy_graph *const *g, int n_graphs, size_
 
 extern "C" xy_status xy_random_walk(const xy_graph *const *g, int n_graphs, int n_walkers, int n_steps,
                                     const uint64_t *seeds, int start_mode, void *d_graph, size_t graph_bytes,
-                                    uint64_t *d_hist, void *stream)
+                                    uint64_t *d_hist, void *stream, float *kernel_ms)
 {
     if (n_walkers < 0 || n_steps < 0 || n_steps >= (1 << 24) || !seeds || !d_graph || !d_hist ||
         (start_mode != 0 && start_mode != 1))
@@ -178,20 +207,38 @@ extern "C" xy_status xy_random_walk(const xy_graph *const *g, int n_graphs, int 
                                n_steps + 1, n_walkers);
             e = hipGetLastError();
         }
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        if (e == hipSuccess && kernel_ms) {
+            *kernel_ms = 0.f;
+            e = hipEventCreateWithFlags(&ev[0], hipEventDisableSystemFence);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[1], hipEventDisableSystemFence);
+            if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+        }
         if (e == hipSuccess && n_walkers > 0) {
             unsigned char *base = static_cast<unsigned char *>(d_graph);
             const auto *dd = reinterpret_cast<const WalkDesc *>(base + p.off_desc);
             const auto *dod = reinterpret_cast<const int2 *>(base + p.off_od);
             const auto *di = reinterpret_cast<const int32_t *>(base + p.off_i32);
-            const dim3 grid((unsigned)((n_walkers + kWalkBlock - 1) / kWalkBlock), (unsigned)n_graphs);
+            // kWalkers walkers per thread; one flat grid of (graph, block) units
+            const int64_t per = (n_walkers + kWalkBlock * kWalkers - 1) / (kWalkBlock * kWalkers);
+            const int64_t units = per * n_graphs;
+            if (units > 0x7fffffff) return set_error(XY_EINVAL, "xy_random_walk: too many walkers");
             if (n_steps + 1 <= kWalkLdsBins)
-                hipLaunchKernelGGL(k_walk<true>, grid, dim3(kWalkBlock), 0, s, dd, dod, di, n_walkers, n_steps,
-                                   start_mode, h);
+                hipLaunchKernelGGL((k_walk<true, kWalkers>), dim3((unsigned)units), dim3(kWalkBlock),
+                                   4 * (size_t)(n_steps + 1), s, dd, dod, di, n_walkers, n_steps, start_mode, (int)per,
+                                   h);
             else
-                hipLaunchKernelGGL(k_walk<false>, grid, dim3(kWalkBlock), 0, s, dd, dod, di, n_walkers, n_steps,
-                                   start_mode, h);
+                hipLaunchKernelGGL((k_walk<false, kWalkers>), dim3((unsigned)units), dim3(kWalkBlock), 0, s, dd, dod,
+                                   di, n_walkers, n_steps, start_mode, (int)per, h);
             e = hipGetLastError();
         }
+        if (e == hipSuccess && kernel_ms) {
+            e = hipEventRecord(ev[1], s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e == hipSuccess) e = hipEventElapsedTime(kernel_ms, ev[0], ev[1]);
+        }
+        for (hipEvent_t x : ev)
+            if (x) (void)hipEventDestroy(x);
         if (e != hipSuccess) return set_error(XY_EHIP, std::string("xy_random_walk: ") + hipGetErrorString(e));
         return XY_OK;
     } catch (const std::bad_alloc &) {
