@@ -129,7 +129,7 @@ def write_traffic(wl, paths, argv):
     dispatches), each scaled by what the same counter reads for a plain 512 MiB
     device copy."""
     fetch, write, cal_f, cal_w = (_pmc_rows(p) for p in paths)
-    pat = "k_fix16_phase" if uses_phase_form(wl) else "k_fix16_sweep"
+    pat = "k_fix16_phase<" if uses_phase_form(wl) else "k_fix16_sweep<"
 
     def per_sweep(rows, counter, n_last=4):
         # counter summed over the dominant kernel's dispatches of each sweep
