@@ -77,6 +77,16 @@ typedef struct xy_batch xy_batch;
  * not give M links, XY_ENOMEM. */
 xy_status xy_graph_levy(int L, int z, double rho, uint64_t seed, xy_graph **out);
 
+/* The same graph with free boundaries (Sec. 2: distances within the L x L
+ * square, r_max = L sqrt 2; the paper's degree distributions and one FSS check
+ * use it).  Raw draw t takes counter (t lo, t hi, 1, 1<<24); the displacement
+ * set is dx, dy in {-(L-1)..L-1}, d != 0, in the same raster order and by the
+ * same inversion; a draw whose j = i + d leaves the square is rejected like a
+ * repeated link, so every pair is drawn with probability proportional to
+ * r^-rho.  2 <= L <= 4096 (any parity); errors as xy_graph_levy (at large rho
+ * and z = 4 the open square has too few short pairs: XY_ECONVERGE). */
+xy_status xy_graph_levy_free(int L, int z, double rho, uint64_t seed, xy_graph **out);
+
 /* Graph from an explicit edge list (tiny exact-physics graphs, tests).
  *   edges  : int32[2*m], pairs (i, j), 0 <= i, j < n, no self or repeated links.
  *   coords : int32[2*n] lattice coordinates (x, y) of each site, 0 <= x, y < L,

@@ -53,6 +53,8 @@ def lib():
     L.oxy_levy_graph.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
                                  _i32p, ctypes.POINTER(ctypes.c_int64)]
     L.oxy_levy_graph.restype = ctypes.c_int
+    L.oxy_levy_graph_free.argtypes = L.oxy_levy_graph.argtypes
+    L.oxy_levy_graph_free.restype = ctypes.c_int
     L.oxy_levy_raw_draws.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_uint64,
                                      ctypes.c_int64, _i32p]
     L.oxy_levy_raw_draws.restype = ctypes.c_int
@@ -106,13 +108,15 @@ def philox(ctr, key):
     return out
 
 
-def levy_graph(L, z, rho, seed):
-    """Edge list int32[M,2] in acceptance order, and the number of raw draws."""
+def levy_graph(L, z, rho, seed, boundary="periodic"):
+    """Edge list int32[M,2] in acceptance order, and the number of raw draws.
+    boundary: "periodic" (the torus) or "free" (the open square)."""
     n = L * L
     m = n * z // 2
     edges = np.empty((m, 2), dtype=np.int32)
     att = ctypes.c_int64(0)
-    rc = lib().oxy_levy_graph(L, z, float(rho), seed, edges, ctypes.byref(att))
+    fn = {"periodic": lib().oxy_levy_graph, "free": lib().oxy_levy_graph_free}[boundary]
+    rc = fn(L, z, float(rho), seed, edges, ctypes.byref(att))
     if rc != 0:
         raise ValueError(f"oxy_levy_graph failed with {rc} (L={L}, z={z}, rho={rho})")
     return edges, att.value

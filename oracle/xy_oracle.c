@@ -228,6 +228,76 @@ out:
 }
 
 /* ------------------------------------------------------------------------ */
+/* Levy graph with free boundaries (Sec. 2: distances within the L x L      */
+/* square, no wrap; r_max = L sqrt 2).  A raw draw t takes counter          */
+/* (t lo, t hi, 1, P_GRAPH << 24): site i uniform; a displacement d with    */
+/* dx, dy in {-(L-1)..L-1}, d != 0, raster order (dy outer, dx inner),      */
+/* weight (dx^2+dy^2)^(-rho/2), by the same inversion; j = i + d.  A draw   */
+/* with j outside the square is rejected, as is one that repeats a link.    */
+/* Every unordered pair {i, j} is then drawn with probability proportional  */
+/* to r^-rho (from i with d, or from j with -d).                            */
+/* Pinned by: the exact pair law on a 4 x 4 square (brute force), rho = 0   */
+/* (every pair equally likely), exact link count and invariants.           */
+/* ------------------------------------------------------------------------ */
+static int disp_table_free(int L, double rho, int32_t *ddx, int32_t *ddy, double *cum)
+{
+    int K = 0, dx, dy;
+    double acc = 0.0;
+    for (dy = -(L - 1); dy <= L - 1; dy++) {
+        for (dx = -(L - 1); dx <= L - 1; dx++) {
+            double r2;
+            if (dx == 0 && dy == 0) continue;
+            r2 = (double)(dx * dx + dy * dy);
+            acc = acc + pow(r2, -0.5 * rho);
+            ddx[K] = dx; ddy[K] = dy; cum[K] = acc;
+            K++;
+        }
+    }
+    return K;
+}
+
+int oxy_levy_graph_free(int L, int z, double rho, uint64_t seed, int32_t *edges, int64_t *n_attempts)
+{
+    int64_t N, M, m = 0, t = 0, cap;
+    int K, a, rc = 0;
+    int32_t *ddx, *ddy;
+    double *cum;
+    ilist *adj;
+    if (L < 2 || z < 1 || !(rho >= 0.0)) return -1;
+    N = (int64_t)L * L;
+    if ((N * z) % 2 != 0 || z >= N - 1) return -1;
+    M = N * z / 2;
+    K = (2 * L - 1) * (2 * L - 1) - 1;
+    ddx = malloc(sizeof(int32_t) * K); ddy = malloc(sizeof(int32_t) * K);
+    cum = malloc(sizeof(double) * K);
+    adj = calloc((size_t)N, sizeof(ilist));
+    if (!ddx || !ddy || !cum || !adj) { rc = -1; goto out; }
+    disp_table_free(L, rho, ddx, ddy, cum);
+    cap = 1000 * M + 1000000;
+    while (m < M) {
+        uint32_t w[4];
+        int32_t i, j, xj, yj, k;
+        if (t >= cap) { rc = -2; break; }
+        draw(seed, (uint32_t)t, (uint32_t)(t >> 32), 1u, (uint32_t)P_GRAPH << 24, w);
+        t++;
+        i = (int32_t)(((uint64_t)w[0] * (uint64_t)N) >> 32);
+        k = first_above(cum, K, u53(w[1], w[2]) * cum[K - 1]);
+        xj = i % L + ddx[k]; yj = i / L + ddy[k];
+        if (xj < 0 || xj >= L || yj < 0 || yj >= L) continue;   /* outside the square */
+        j = yj * L + xj;
+        if (ilist_has(&adj[i], j)) continue;                    /* multi-edge: reject */
+        if (ilist_push(&adj[i], j) || ilist_push(&adj[j], i)) { rc = -1; break; }
+        edges[2 * m] = i; edges[2 * m + 1] = j;
+        m++;
+    }
+    if (n_attempts) *n_attempts = t;
+out:
+    if (adj) for (a = 0; a < N; a++) free(adj[a].v);
+    free(adj); free(ddx); free(ddy); free(cum);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Smallest-last ordering colouring (App. B, "Graph coloring"): repeatedly  */
 /* remove a site of minimum remaining degree (ties: smallest index), then   */
 /* colour sites in reverse removal order with the smallest colour that no   */

@@ -42,9 +42,11 @@ class Graph:
         self.n, self.m, self.n_colours, self.max_degree, self.attempts = n.value, m.value, q.value, md.value, att.value
 
     @classmethod
-    def levy(cls, L, z, rho, seed):
+    def levy(cls, L, z, rho, seed, boundary="periodic"):
+        """Dilute Levy graph on the L x L lattice, periodic or free boundaries."""
+        fn = {"periodic": "xy_graph_levy", "free": "xy_graph_levy_free"}[boundary]
         h = ctypes.c_void_p()
-        _lib.call("xy_graph_levy", int(L), int(z), float(rho), int(seed), ctypes.byref(h))
+        _lib.call(fn, int(L), int(z), float(rho), int(seed), ctypes.byref(h))
         g = cls(h.value)
         g.L = int(L)
         return g

@@ -16,7 +16,7 @@ XY_NOBS = 8
 STATUS_NAMES = {0: "XY_OK", -1: "XY_EINVAL", -2: "XY_ENOMEM", -3: "XY_EHIP", -4: "XY_ESTATE",
                 -5: "XY_EUNSUP", -6: "XY_ECONVERGE"}
 
-EXPORTS = ("xy_graph_levy", "xy_graph_from_edges", "xy_graph_info", "xy_graph_export", "xy_graph_free",
+EXPORTS = ("xy_graph_levy", "xy_graph_levy_free", "xy_graph_from_edges", "xy_graph_info", "xy_graph_export", "xy_graph_free",
            "xy_batch_sizes", "xy_batch_init", "xy_sweep", "xy_measure", "xy_pt_swap", "xy_get_state",
            "xy_set_state", "xy_get_counters", "xy_decision_log", "xy_batch_use_graph", "xy_batch_set_fix16_form", "xy_batch_forms", "xy_walk_bytes", "xy_random_walk", "xy_kernel_timing",
            "xy_kernel_time", "xy_last_error", "xy_batch_free")
@@ -48,6 +48,7 @@ _c = ctypes.CDLL(LIB_PATH)
 _vp, _i32, _u32, _u64, _dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
 _sigs = {
     "xy_graph_levy": ([_i32, _i32, _dbl, _u64, ctypes.POINTER(_vp)], _i32),
+    "xy_graph_levy_free": ([_i32, _i32, _dbl, _u64, ctypes.POINTER(_vp)], _i32),
     "xy_graph_from_edges": ([_i32, _i32, _vp, _vp, _i32, ctypes.POINTER(_vp)], _i32),
     "xy_graph_info": ([_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                        ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_int64)], _i32),

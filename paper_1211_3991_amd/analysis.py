@@ -210,3 +210,18 @@ def spectral_dimension(hist, t_min, t_max):
     cov = np.linalg.inv(A.T @ Aw)
     coef = cov @ (Aw.T @ y)
     return float(-2.0 * coef[1]), float(2.0 * np.sqrt(cov[1, 1]))
+
+
+def degree_distribution(edges, n):
+    """P(k), the fraction of the n sites with k links (Sec. 2, the degree
+    distributions of the dilute graphs): float64[k_max + 1]."""
+    e = np.asarray(edges).reshape(-1, 2)
+    deg = np.bincount(e.ravel(), minlength=n)
+    return np.bincount(deg) / float(n)
+
+
+def colour_fractions(colour):
+    """Fraction of the sites in each colour class (App. B, "Graph coloring":
+    the sizes of the sets updated in parallel): float64[Q]."""
+    c = np.asarray(colour)
+    return np.bincount(c) / float(c.size)

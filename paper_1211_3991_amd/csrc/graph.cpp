@@ -189,39 +189,49 @@ using namespace xy;
 
 extern "C" const char *xy_last_error(void) { return g_last_error.c_str(); }
 
-extern "C" xy_status xy_graph_levy(int L, int z, double rho, uint64_t seed, xy_graph **out)
+namespace {
+
+// Dilute Levy graph, periodic (the torus) or free (the open square).  The
+// displacement set is listed in raster order (dy outer, dx inner) and drawn
+// by inverting the sequential prefix sums of (dx^2 + dy^2)^(-rho/2).
+xy_status levy_build(int L, int z, double rho, uint64_t seed, bool free_bc, const char *who, xy_graph **out)
 {
-    if (!out) return set_error(XY_EINVAL, "xy_graph_levy: out is NULL");
+    if (!out) return set_error(XY_EINVAL, std::string(who) + ": out is NULL");
     *out = nullptr;
-    if (L < 2 || (L & 1)) return set_error(XY_EINVAL, "xy_graph_levy: L must be even and >= 2");
-    if (L > 46340) return set_error(XY_EINVAL, "xy_graph_levy: L too large");
-    if (!(rho >= 0.0) || !std::isfinite(rho)) return set_error(XY_EINVAL, "xy_graph_levy: rho must be finite and >= 0");
+    if (!free_bc && (L < 2 || (L & 1))) return set_error(XY_EINVAL, std::string(who) + ": L must be even and >= 2");
+    if (free_bc && L < 2) return set_error(XY_EINVAL, std::string(who) + ": L must be >= 2");
+    if (L > (free_bc ? 4096 : 46340)) return set_error(XY_EINVAL, std::string(who) + ": L too large");
+    if (!(rho >= 0.0) || !std::isfinite(rho))
+        return set_error(XY_EINVAL, std::string(who) + ": rho must be finite and >= 0");
     const int64_t N = (int64_t)L * L;
     if (z < 1 || (N * z) % 2 != 0 || z >= N - 1)
-        return set_error(XY_EINVAL, "xy_graph_levy: need z >= 1, N*z even and z < N-1");
+        return set_error(XY_EINVAL, std::string(who) + ": need z >= 1, N*z even and z < N-1");
     const int64_t M = N * z / 2;
-    if (M > (int64_t)1 << 30) return set_error(XY_EINVAL, "xy_graph_levy: too many links");
+    if (M > (int64_t)1 << 30) return set_error(XY_EINVAL, std::string(who) + ": too many links");
 
     xy_graph *g = new (std::nothrow) xy_graph;
-    if (!g) return set_error(XY_ENOMEM, "xy_graph_levy: out of memory");
+    if (!g) return set_error(XY_ENOMEM, std::string(who) + ": out of memory");
     try {
         g->n = (int)N; g->m = (int)M; g->L = L;
-        // displacement weights w(d) = (dx^2 + dy^2)^(-rho/2), prefix sums in
-        // raster order (dy outer, dx inner), added one at a time
-        const int K = (int)(N - 1);
-        std::vector<int32_t> dxs(K), dys(K);
-        std::vector<double> prefix(K);
+        // side of the displacement square and its offset: periodic dx, dy in
+        // {-L/2+1..L/2}, free in {-(L-1)..L-1}; entry f of the square is
+        // (f % side - lo, f / side - lo), the centre (d = 0) left out
+        const int64_t side = free_bc ? 2 * (int64_t)L - 1 : L, lo = free_bc ? L - 1 : L / 2 - 1;
+        const int64_t centre = lo * side + lo, K = side * side - 1;
+        auto disp = [&](int64_t k, int &dx, int &dy) {
+            const int64_t f = k < centre ? k : k + 1;
+            dx = (int)(f % side - lo);
+            dy = (int)(f / side - lo);
+        };
+        std::vector<double> prefix((size_t)K);
         {
             double run = 0.0;
-            int k = 0;
-            for (int dy = -L / 2 + 1; dy <= L / 2; ++dy)
-                for (int dx = -L / 2 + 1; dx <= L / 2; ++dx) {
-                    if (dx == 0 && dy == 0) continue;
-                    const double r2 = (double)(dx * dx + dy * dy);
-                    run = run + std::pow(r2, -0.5 * rho);
-                    dxs[k] = dx; dys[k] = dy; prefix[k] = run;
-                    ++k;
-                }
+            for (int64_t k = 0; k < K; ++k) {
+                int dx, dy;
+                disp(k, dx, dy);
+                run = run + std::pow((double)((int64_t)dx * dx + (int64_t)dy * dy), -0.5 * rho);
+                prefix[k] = run;
+            }
         }
         const double total = prefix[K - 1];
         std::unordered_set<uint64_t> linked;
@@ -233,16 +243,24 @@ extern "C" xy_status xy_graph_levy(int L, int z, double rho, uint64_t seed, xy_g
         while (have < M) {
             if (t >= cap) {
                 delete g;
-                return set_error(XY_ECONVERGE, "xy_graph_levy: attempt cap reached before N*z/2 links");
+                return set_error(XY_ECONVERGE, std::string(who) + ": attempt cap reached before N*z/2 links");
             }
-            const U4 w = philox4x32_10({(uint32_t)t, (uint32_t)(t >> 32), 0u, tag(kGraph)}, s0, s1);
+            const U4 w = philox4x32_10({(uint32_t)t, (uint32_t)(t >> 32), free_bc ? 1u : 0u, tag(kGraph)}, s0, s1);
             ++t;
             const int32_t i = (int32_t)(((uint64_t)w.x * (uint64_t)N) >> 32);
             const double target = unit53(w.y, w.z) * total;
-            int k = (int)(std::upper_bound(prefix.begin(), prefix.end(), target) - prefix.begin());
+            int64_t k = std::upper_bound(prefix.begin(), prefix.end(), target) - prefix.begin();
             if (k == K) k = K - 1;
+            int dx, dy;
+            disp(k, dx, dy);
             const int xi = i % L, yi = i / L;
-            const int xj = ((xi + dxs[k]) % L + L) % L, yj = ((yi + dys[k]) % L + L) % L;
+            int xj = xi + dx, yj = yi + dy;
+            if (free_bc) {
+                if (xj < 0 || xj >= L || yj < 0 || yj >= L) continue;     // outside the square
+            } else {
+                xj = (xj % L + L) % L;
+                yj = (yj % L + L) % L;
+            }
             const int32_t j = yj * L + xj;
             const uint64_t key = (uint64_t)std::min(i, j) * (uint64_t)N + (uint64_t)std::max(i, j);
             if (!linked.insert(key).second) continue;
@@ -257,10 +275,22 @@ extern "C" xy_status xy_graph_levy(int L, int z, double rho, uint64_t seed, xy_g
         if (st != XY_OK) { delete g; return st; }
     } catch (const std::bad_alloc &) {
         delete g;
-        return set_error(XY_ENOMEM, "xy_graph_levy: out of memory");
+        return set_error(XY_ENOMEM, std::string(who) + ": out of memory");
     }
     *out = g;
     return XY_OK;
+}
+
+}  // namespace
+
+extern "C" xy_status xy_graph_levy(int L, int z, double rho, uint64_t seed, xy_graph **out)
+{
+    return levy_build(L, z, rho, seed, false, "xy_graph_levy", out);
+}
+
+extern "C" xy_status xy_graph_levy_free(int L, int z, double rho, uint64_t seed, xy_graph **out)
+{
+    return levy_build(L, z, rho, seed, true, "xy_graph_levy_free", out);
 }
 
 extern "C" xy_status xy_graph_from_edges(int n, int m, const int32_t *edges, const int32_t *coords,

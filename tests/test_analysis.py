@@ -6,6 +6,7 @@ form mean^2 - s^2/n; on infinite-temperature oracle records (independent
 uniform spins) U4 = 1 - 1/N, chi(0)/chi(k_min) = 1 and xi_2 = 0 within errors.
 """
 import numpy as np
+import pytest
 
 import oracle
 from paper_1211_3991_amd import analysis
@@ -92,3 +93,27 @@ def test_bethe_tc():
     assert abs(analysis.bethe_tc(1.0 / 0.049937603987939) - 10.0) < 1e-8
     # the analytic value for the Erdos-Renyi graph of mean degree 4 (Sec. 5)
     assert abs(analysis.bethe_tc(4.0) - 1.9361) < 1e-4
+
+
+def test_degree_distribution_pins():
+    # the z = 4, large-rho periodic graph is the square lattice: P(k) = delta(k - 4)
+    e, _ = oracle.levy_graph(16, 4, 60.0, 1)
+    p = analysis.degree_distribution(e, 256)
+    assert p.size == 5 and p[4] == 1.0
+    # any graph: the mean degree is 2M/N = z exactly
+    for boundary in ("periodic", "free"):
+        e, _ = oracle.levy_graph(24, 6, 3.5, 2, boundary=boundary)
+        p = analysis.degree_distribution(e, 576)
+        assert abs(np.sum(np.arange(p.size) * p) - 6.0) < 1e-12 and abs(p.sum() - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("rho", [0.5, 1.0, 7 / 3, 10 / 3, 14 / 3])
+def test_colour_classes_at_most_six_at_z4(rho):
+    """App. B: for N <= 2^16 and z = 4 the colouring never needs more than 6
+    colours; the classes partition the sites."""
+    for L, seeds in ((64, range(4)), (256, range(2))):
+        for s in seeds:
+            e, _ = oracle.levy_graph(L, 4, rho, s)
+            colour, q = oracle.slo_colour(L * L, e)
+            f = analysis.colour_fractions(colour)
+            assert q <= 6 and f.size == q and abs(f.sum() - 1.0) < 1e-12 and (f > 0).all()

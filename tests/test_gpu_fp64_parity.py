@@ -167,3 +167,22 @@ def test_checkpoint_resume_is_bitwise(precision):
     assert got_sw == 30 and np.array_equal(got_sot, ref_sot)
     for a, c in zip(got, ref_state):
         assert np.array_equal(np.ascontiguousarray(a).view(np.uint8), np.ascontiguousarray(c).view(np.uint8))
+
+
+def test_free_boundary_graph_exact():
+    """A free-boundary graph (Sec. 2) through the FP64 path: bit-identical to
+    the oracle after 20 sweeps with PT."""
+    L, z, rho, sd = 16, 6, 2.5, 6
+    T = workloads.linear_ladder(0.8, 2.0, 4)
+    g = xy.Graph.levy(L, z, rho, sd, boundary="free")
+    b = xy.Batch([g], T, precision="fp64", seeds=[sd])
+    b.sweep(20, n_or=5, pt_every=1, meas_every=0)
+    st, sot, _ = b.get_state()
+    e, _ = oracle.levy_graph(L, z, rho, sd, boundary="free")
+    col, _ = oracle.slo_colour(L * L, e)
+    sim = oracle.Sim(L * L, e, col, L, T, sd)
+    sim.init_random()
+    sim.run(20, n_or=5, pt_every=1, meas_every=0)
+    ref, ref_sot, _ = sim.get_state()
+    assert np.array_equal(sot[0], ref_sot)
+    assert np.array_equal(_bits(st[0]), _bits(ref))

@@ -38,6 +38,21 @@ def test_graph_bitwise_equal_to_oracle(L, z, rho, seed):
     assert np.array_equal(ex["colour"], col)
 
 
+@pytest.mark.parametrize("L,z,rho,seed", [(16, 6, 3.5, 1), (17, 4, 2.5, 3), (32, 4, 14 / 3, 5), (20, 6, 0.0, 2)])
+def test_free_boundary_graph_bitwise_equal_to_oracle(L, z, rho, seed):
+    g = xy.Graph.levy(L, z, rho, seed, boundary="free")
+    e, att = oracle.levy_graph(L, z, rho, seed, boundary="free")
+    assert g.attempts == att and np.array_equal(g.export()["edges"], e)
+
+
+def test_free_boundary_errors():
+    for L in (1, 5000):
+        with pytest.raises(xy.XYError):
+            xy.Graph.levy(L, 4, 2.5, 1, boundary="free")
+    with pytest.raises(xy.XYError):
+        xy.Graph.levy(16, 4, 60.0, 1, boundary="free")      # too few short pairs: attempt cap
+
+
 def test_colour_sorted_csr_is_a_relabelling():
     L = 64
     n = L * L

@@ -191,3 +191,63 @@ def test_slo_tiny_graphs():
     assert q == 4 and sorted(col) == [0, 1, 2, 3]
     col, q = oracle.slo_colour(3, np.zeros((0, 2), dtype=np.int32))
     assert q == 1 and list(col) == [0, 0, 0]
+
+
+# --- free boundaries (Sec. 2: distances within the open L x L square) -------
+
+def _pair_weights_open_square(L, rho):
+    """Every unordered pair {i, j} of the open L x L square with weight r^-rho."""
+    n = L * L
+    xs, ys = np.arange(n) % L, np.arange(n) // L
+    i, j = np.triu_indices(n, 1)
+    r2 = (xs[i] - xs[j]) ** 2 + (ys[i] - ys[j]) ** 2
+    return i, j, r2.astype(np.float64) ** (-rho / 2)
+
+
+def test_free_boundary_pair_law_brute_force():
+    """The first accepted draw of a graph is an unordered pair {i, j} with
+    probability proportional to r^-rho over all pairs of the open square."""
+    L, rho, n_graphs = 4, 2.5, 30000
+    i, j, w = _pair_weights_open_square(L, rho)
+    index = {(a, b): k for k, (a, b) in enumerate(zip(i, j))}
+    counts = np.zeros(i.size)
+    for seed in range(n_graphs):
+        e, _ = oracle.levy_graph(L, 1, rho, seed, boundary="free")
+        a, b = sorted(e[0])
+        counts[index[(a, b)]] += 1
+    expect = n_graphs * w / w.sum()
+    chi2 = np.sum((counts - expect) ** 2 / expect)
+    assert stats.chi2.sf(chi2, i.size - 1) > 1e-3, chi2
+
+
+@pytest.mark.parametrize("L,z,rho,seed", [(16, 6, 3.5, 1), (17, 4, 2.5, 3), (12, 4, 14 / 3, 5), (20, 6, 0.0, 2)])
+def test_free_boundary_invariants(L, z, rho, seed):
+    e, att = oracle.levy_graph(L, z, rho, seed, boundary="free")
+    n = L * L
+    assert e.shape == (n * z // 2, 2) and att >= e.shape[0]
+    assert (e >= 0).all() and (e < n).all() and (e[:, 0] != e[:, 1]).all()
+    key = np.minimum(e[:, 0], e[:, 1]) * n + np.maximum(e[:, 0], e[:, 1])
+    assert np.unique(key).size == key.size
+    dx = e[:, 0] % L - e[:, 1] % L
+    dy = e[:, 0] // L - e[:, 1] // L
+    assert (np.hypot(dx, dy) <= (L - 1) * np.sqrt(2) + 1e-12).all()
+    # with free boundaries no link wraps: its length is the plain distance,
+    # and the periodic graph of the same seed is a different graph
+    ep, _ = oracle.levy_graph(L - (L % 2), z, rho, seed)
+    assert L % 2 or not np.array_equal(e, ep)
+
+
+def test_free_boundary_rho_zero_is_erdos_renyi():
+    """rho = 0: every pair equally likely, as for the periodic graph (the
+    paper notes the Erdos-Renyi limit does not depend on the boundary)."""
+    L, z = 32, 4
+    n = L * L
+    deg = np.concatenate([np.bincount(oracle.levy_graph(L, z, 0.0, s, boundary="free")[0].ravel(), minlength=n)
+                          for s in range(20)])
+    kmax = 12
+    obs = np.bincount(np.minimum(deg, kmax), minlength=kmax + 1)
+    p = stats.binom.pmf(np.arange(kmax + 1), n - 1, z / (n - 1))
+    p[kmax] = stats.binom.sf(kmax - 1, n - 1, z / (n - 1))
+    chi2 = np.sum((obs - deg.size * p) ** 2 / (deg.size * p))
+    # sites are not independent (fixed link count), so the bound is loose
+    assert stats.chi2.sf(chi2, kmax) > 1e-4, chi2
