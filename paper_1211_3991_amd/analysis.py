@@ -225,3 +225,83 @@ def colour_fractions(colour):
     the sizes of the sets updated in parallel): float64[Q]."""
     c = np.asarray(colour)
     return np.bincount(c) / float(c.size)
+
+
+def _u4_curve(m4, m2sq):
+    """Disorder-averaged U4 (ratio of averages, Sec. 3) from per-sample arrays."""
+    return m4.mean(0) / m2sq.mean(0) - 1.0
+
+
+def u4_slope_at(T, U, u_target):
+    """(T*, dU/dT at T*) where the curve U(T) first crosses u_target, from
+    the linear segment of the ladder that brackets it; None if it does not."""
+    T = np.asarray(T, dtype=np.float64)
+    d = np.asarray(U, dtype=np.float64) - u_target
+    for k in range(len(T) - 1):
+        if d[k] == 0.0 or d[k] * d[k + 1] < 0.0:
+            slope = (d[k + 1] - d[k]) / (T[k + 1] - T[k])
+            return float(T[k] - d[k] / slope), float(slope)
+    return None
+
+
+def _jackknife_sizes(est, per_size):
+    """est(list of per-size argument tuples of sample means) -> scalar, with a
+    jackknife error over the samples of each size (independent sets, the
+    leave-one-out variances add).  per_size: list of tuples of [G, ...] arrays."""
+    means = [tuple(a.mean(0) for a in arrs) for arrs in per_size]
+    value = est(means)
+    var = 0.0
+    for s, arrs in enumerate(per_size):
+        n = arrs[0].shape[0]
+        tot = [a.sum(0) for a in arrs]
+        loo = []
+        for i in range(n):
+            trial = list(means)
+            trial[s] = tuple((t - a[i]) / (n - 1) for t, a in zip(tot, arrs))
+            v = est(trial)
+            if v is not None and np.isfinite(v):
+                loo.append(v)
+        loo = np.asarray(loo)
+        if loo.size > 1:
+            var += (n - 1) / n * np.sum((loo - loo.mean()) ** 2)
+    return value, float(np.sqrt(var))
+
+
+def nu_bar_from_u4(T, N, records, u_target, discard=0.5):
+    """nu_bar from dU4/dT at fixed U4 (Sec. 5, Eq. U4dot): |dU4/dT| at the
+    temperature where U4(T, N) = u_target grows as N^(1/nu_bar).  records:
+    one [n_rec, G, n_T, 8] array per size N.  Returns (nu_bar, error), the
+    error a jackknife over the samples of every size."""
+    per_size = [u4_samples(r, discard) for r in records]
+    lnN = np.log(np.asarray(N, dtype=np.float64))
+
+    def est(means):
+        ln_slopes = []
+        for m4, m2sq in means:
+            hit = u4_slope_at(T, m4 / m2sq - 1.0, u_target)
+            if hit is None:
+                return None
+            ln_slopes.append(np.log(abs(hit[1])))
+        inv_nu = np.polyfit(lnN, ln_slopes, 1)[0]
+        return 1.0 / inv_nu
+
+    return _jackknife_sizes(est, per_size)
+
+
+def gamma_over_nu_bar(T, N, records, T_ref, discard=0.5):
+    """gamma / nu_bar from chi = N <|m|^2> at T_ref (Sec. 3, Eq. chi; Sec. 5):
+    chi(T_ref, N) ~ N^(gamma/nu_bar), chi linearly interpolated along the
+    ladder.  Returns (gamma/nu_bar, jackknife error over samples)."""
+    T = np.asarray(T, dtype=np.float64)
+    per_size = []
+    for r in records:
+        rec = np.asarray(r, dtype=np.float64)
+        rec = rec[int(rec.shape[0] * discard):]
+        per_size.append((rec.mean(axis=0)[:, :, M2],))
+    Ns = np.asarray(N, dtype=np.float64)
+
+    def est(means):
+        ln_chi = [np.log(n * np.interp(T_ref, T, m2)) for n, (m2,) in zip(Ns, means)]
+        return np.polyfit(np.log(Ns), ln_chi, 1)[0]
+
+    return _jackknife_sizes(est, per_size)

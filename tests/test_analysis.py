@@ -117,3 +117,42 @@ def test_colour_classes_at_most_six_at_z4(rho):
             colour, q = oracle.slo_colour(L * L, e)
             f = analysis.colour_fractions(colour)
             assert q <= 6 and f.size == q and abs(f.sum() - 1.0) < 1e-12 and (f > 0).all()
+
+
+def _scaling_records(T, N, G, u_fn, m2_fn, rng=None):
+    """Records [n_rec, G, n_T, 8] whose thermal |m|^2 is m2_fn(T) and U4 is
+    u_fn(T) (|m|^4 = (1 + U4) |m|^2^2), optionally with per-sample noise."""
+    m2 = m2_fn(T)
+    u = u_fn(T)
+    rec = np.zeros((4, G, T.size, 8))
+    rec[:, :, :, 1] = m2
+    rec[:, :, :, 2] = (1.0 + u) * m2 ** 2
+    if rng is not None:
+        rec[:, :, :, 2] *= 1.0 + 0.01 * rng.normal(size=(1, G, 1))
+    return rec
+
+
+def test_nu_bar_and_gamma_over_nu_from_exact_scaling():
+    """U4 = 0.6 - 0.5 (T - 1.9) N^(1/2) and chi(T) = N^(1/2) c(T): nu_bar = 2
+    and gamma/nu_bar = 1/2 come out exactly (linear curves, no noise)."""
+    T = np.linspace(1.7, 2.2, 21)
+    N = [256, 1024, 4096, 16384]
+    recs = [_scaling_records(T, n, 5, lambda t, n=n: 0.6 - 0.5 * (t - 1.9) * n ** 0.5,
+                             lambda t, n=n: n ** -0.5 * (3.0 - t)) for n in N]
+    nu, err = analysis.nu_bar_from_u4(T, N, recs, u_target=0.6, discard=0.0)
+    assert abs(nu - 2.0) < 1e-10 and err < 1e-10
+    g, gerr = analysis.gamma_over_nu_bar(T, N, recs, T_ref=1.93, discard=0.0)
+    assert abs(g - 0.5) < 1e-12 and gerr < 1e-12
+    # sample-to-sample noise gives a finite jackknife error around the same value
+    rng = np.random.default_rng(3)
+    recs = [_scaling_records(T, n, 30, lambda t, n=n: 0.6 - 0.5 * (t - 1.9) * n ** 0.5,
+                             lambda t, n=n: n ** -0.5 * (3.0 - t), rng) for n in N]
+    nu, err = analysis.nu_bar_from_u4(T, N, recs, u_target=0.6, discard=0.0)
+    assert 0 < err < 0.2 and abs(nu - 2.0) < 5 * err
+
+
+def test_u4_slope_at():
+    T = np.array([1.0, 2.0, 3.0])
+    t, s = analysis.u4_slope_at(T, np.array([0.9, 0.5, 0.1]), 0.6)
+    assert abs(t - 1.75) < 1e-12 and abs(s + 0.4) < 1e-12
+    assert analysis.u4_slope_at(T, np.array([0.9, 0.8, 0.7]), 0.1) is None

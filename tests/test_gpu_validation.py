@@ -12,7 +12,11 @@ Here: 64 samples each of L = 16, 32, 64, 128, 16 temperatures in [1.7, 2.2],
 PT every sweep, 2^14 sweeps of 1 Metropolis + 5 OR (first half discarded),
 measurement every 16 sweeps, on the fixed-point path.  The extrapolated T_c
 must agree with the analytic value within three standard errors (jackknife
-over samples, propagated through the fit) plus the paper's own 0.01.
+over samples, propagated through the fit) plus the paper's own 0.01.  The
+same run gives the mean-field exponents the paper reports for this graph:
+nu_bar = 2 from dU4/dT at fixed U4 (Eq. U4dot; paper 2.00(2)), within three
+standard errors plus 0.1, and gamma/nu_bar = 1/2 from chi at T_c, within
+three standard errors plus 0.05 (finite-size corrections at these sizes).
 """
 import numpy as np
 import pytest
@@ -68,3 +72,16 @@ def test_erdos_renyi_z4_critical_temperature():
     ref = analysis.bethe_tc(4.0)
     print(f"T_c = {tc:.4f} +- {sigma:.4f} (C = {c:.3f}); analytic {ref:.4f}, paper 1.93(1)", flush=True)
     assert abs(tc - ref) <= 3.0 * sigma + 0.01
+
+    # nu_bar from dU4/dT at fixed U4 (Eq. U4dot), at the U4 value of the
+    # largest pair's crossing; mean field (and the paper's 2.00(2)): 2
+    m4, m2sq = analysis.u4_samples(rec[SIZES[-2]])
+    u_star = float(np.interp(Tx[-1], T, m4.mean(0) / m2sq.mean(0) - 1.0))
+    Ns = [L * L for L in SIZES]
+    nu, nu_err = analysis.nu_bar_from_u4(T, Ns, [rec[L] for L in SIZES], u_star)
+    print(f"nu_bar = {nu:.3f} +- {nu_err:.3f} at U4 = {u_star:.3f}; mean field 2, paper 2.00(2)", flush=True)
+    assert abs(nu - 2.0) <= 3.0 * nu_err + 0.1
+    # gamma / nu_bar from chi at the analytic T_c; mean field: 1 / 2
+    g, g_err = analysis.gamma_over_nu_bar(T, Ns, [rec[L] for L in SIZES], ref)
+    print(f"gamma/nu_bar = {g:.3f} +- {g_err:.3f}; mean field 0.5", flush=True)
+    assert abs(g - 0.5) <= 3.0 * g_err + 0.05
