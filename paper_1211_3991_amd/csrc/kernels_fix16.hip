@@ -2,10 +2,13 @@
 // uint16 (an exact representation of the 2^16-state clock model), local
 // fields are accumulated in FP32, and energies / observables in FP64.
 //
-// One workgroup runs one whole sweep of one (sample, temperature slot): the
-// replica's angles are staged in LDS (when they fit) and the colour phases of
-// App. B become workgroup barriers, so a sweep needs no grid-wide
-// synchronisation and no host round trip.  The graph is read in sliced-ELL
+// This file: the workgroup-per-replica forms, used for graphs below the
+// phase-form threshold (or any n_T not a multiple of 4), and the measurement
+// and tempering kernels of every form; the phase form's colour-phase kernel
+// is in kernels_phase.hip.  One workgroup runs one whole sweep of one (sample,
+// temperature slot): the replica's angles are staged in LDS (when they fit)
+// and the colour phases of App. B become workgroup barriers, so a sweep needs
+// no grid-wide synchronisation and no host round trip.  The graph is read in sliced-ELL
 // form (64-site chunks, columns stored [k][lane], sites degree-sorted inside
 // each colour class): a wave's k-th neighbour indices are one contiguous
 // load, and all indices of a site are in flight before the first is used.

@@ -380,8 +380,9 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
             (void)hipGetDevice(&dev);
             if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
                 lds_limit = 65536;
-            // XY_FIX16_GLOBAL=1 keeps every replica in global memory (the variant
-            // used for graphs too large for LDS); tests use it at small sizes
+            // XY_FIX16_GLOBAL=1 keeps every replica in global memory (the form
+            // for graphs too large for LDS when n_T is not a multiple of 4);
+            // tests use it at small sizes
             bool force_global = false;
             if (const char *env = std::getenv("XY_FIX16_GLOBAL"))
                 if (std::atoi(env) != 0) force_global = true;
