@@ -32,104 +32,103 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
 {
     __shared__ float esum[kLast ? kPhaseBlock * 4 : 1];
     const int R = b.R, Lq = R >> 2, S = kPhaseBlock / Lq;
-    const int t = threadIdx.x, q = t % Lq, sl = t / Lq;
-    // work unit: (sample, its phase-sample index, block of its colour class)
-    const int4 u = units[xcd_contiguous(blockIdx.x, gridDim.x)];
-    const int s = u.x, k_ph = u.y, bx = u.z;
+    const int t = threadIdx.x;
+    // t / Lq through the FP32 reciprocal: exact for t < 256, Lq <= 64, even
+    // with a reciprocal 1 ulp off (checked exhaustively)
+    const int sl = (int)(((float)t + 0.5f) * __builtin_amdgcn_rcpf((float)Lq)), q = t - sl * Lq;
+    // work unit, two int4: the pool offsets of the columns of the block's
+    // first two chunks, the sample's state base / 8, the block's first site;
+    // then sample, phase-sample index, block index in the colour class, and
+    // kmin | kmax << 8 | (sites - 1) << 16 | (first site's chunk lane) << 24.
+    // The index loads depend on nothing but the unit.
+    const int u = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int4 ua = units[2 * u], ub = units[2 * u + 1];
+    const int s = ub.x, k_ph = ub.y, bx = ub.z;
+    const int kmin = ub.w & 255, kmax = (ub.w >> 8) & 255, n_act = ((ub.w >> 16) & 255) + 1;
+    const int lnA = (int)((uint32_t)ub.w >> 24);
+    // lanes past the block's last site mirror that site and store nothing
+    const bool active = sl < n_act;
+    const int sc = min(sl, n_act - 1);
+    const int i = ua.w + sc;                                      // colour-major site index in the sample
     const SampleDesc &d = b.desc[s];
-    if (colour >= d.Q) return;                                   // uniform over the block
-    const int c0 = d.colour_off[colour], c1 = d.colour_off[colour + 1];
-    const int r0 = bx * S;                                        // first site of the block, relative to c0
-    if (c0 + r0 >= c1) return;                                   // uniform: block past the class
-    // neighbour-count bounds of the block from its chunks' (wmin, wmax):
-    // rows below kmin are real for every site, rows from kmax on for none
-    int kmin = 255, kmax = 0;
-    {
-        const int32_t *cw = b.i32 + d.sell_w + d.chunk_off[colour];
-        const int ch1 = (min(r0 + S, c1 - c0) - 1) >> 6;
-        for (int ch = r0 >> 6; ch <= ch1; ++ch) {
-            const int w = cw[ch];
-            kmin = min(kmin, w & 255);
-            kmax = max(kmax, w >> 8);
-        }
+    const int pos = lnA + sc, ln = pos & 63;
+    uint32_t cbase = pos < 64 ? (uint32_t)ua.x : (uint32_t)ua.y;  // pool element offset of the site's chunk
+    if (pos >= 128) {                                             // blocks of more than 64 sites (R < 16)
+        const int c0 = d.colour_off[colour];
+        cbase = (uint32_t)(d.sell_col + b.i32[d.sell_ptr + d.chunk_off[colour] + ((i - c0) >> 6)]);
     }
-    const int i = c0 + r0 + sl;
-    const bool active = sl < S && i < c1;
-    float e_q[4] = {0.f, 0.f, 0.f, 0.f};                          // last sub-sweep: energy of links to lower colours
-    if (active) {
-        const int rel = i - c0, ln = rel & 63;
-        const int base = b.i32[d.sell_ptr + d.chunk_off[colour] + (rel >> 6)];
-        const char *colb = reinterpret_cast<const char *>(sizeof(Idx) == 2 ? (const void *)b.u16 : (const void *)b.i32) +
-                           d.sell_col * (int64_t)sizeof(Idx);
-        const int dg = b.u8[d.deg + i];
-        // [site][Lq] words of 4 angles; 32-bit byte offsets from the sample's base
-        char *Ab = reinterpret_cast<char *>(static_cast<uint16_t *>(b.state) + d.state);
-        const uint32_t q8 = 8u * (uint32_t)q, Lq8 = 8u * (uint32_t)Lq;
-        auto word = [&](int j) -> uint2 & { return *reinterpret_cast<uint2 *>(Ab + (__umul24((uint32_t)j, Lq8) + q8)); };
-        float beta[4];
-        {
-            const int4 tq = *reinterpret_cast<const int4 *>(b.T_of_slot + s * R + 4 * q);
-            const int ts[4] = {tq.x, tq.y, tq.z, tq.w};
-            const char *bs = reinterpret_cast<const char *>(b.beta + s * R);   // this sample's ladder
-#pragma unroll
-            for (int r = 0; r < 4; ++r) beta[r] = (float)*reinterpret_cast<const double *>(bs + 8u * (uint32_t)ts[r]);
-        }
+    const char *colb = reinterpret_cast<const char *>(sizeof(Idx) == 2 ? (const void *)b.u16 : (const void *)b.i32) +
+                       ((uint64_t)cbase + (uint32_t)ln) * sizeof(Idx);
+    // [site][Lq] words of 4 angles; 32-bit byte offsets from the sample's base
+    char *Ab = reinterpret_cast<char *>(b.state) + (uint64_t)(uint32_t)ua.z * 16u;
+    const uint32_t q8 = 8u * (uint32_t)q, Lq8 = 8u * (uint32_t)Lq;
+    auto word = [&](int j) -> uint2 & { return *reinterpret_cast<uint2 *>(Ab + (__umul24((uint32_t)j, Lq8) + q8)); };
 
-        // 8 rows of neighbour indices (every chunk has at least 8; a site's
-        // rows past its degree hold the site itself), then the 4-slot angle
-        // words of all 8, in flight before the first use (unconditional loads
-        // keep the wait counts exact; a padding row reads the site's own word)
-        static_assert(kSellRows >= 8, "the phase kernel reads 8 rows of every chunk");
-        int jj[8];
-        uint2 vv[8];
-        const uint32_t off0 = (uint32_t)(base + ln) * (uint32_t)sizeof(Idx);
+    // 8 rows of neighbour indices (every chunk has at least 8; a site's rows
+    // past its degree hold the site itself, which is never its own
+    // neighbour), then the 4-slot angle words of all 8, in flight before the
+    // first use (unconditional loads keep the wait counts exact; a padding
+    // row reads the site's own word)
+    static_assert(kSellRows >= 8, "the phase kernel reads 8 rows of every chunk");
+    int jj[8];
+    uint2 vv[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) jj[k] = (int)*reinterpret_cast<const Idx *>(colb + off0 + k * 64 * sizeof(Idx));
+    for (int k = 0; k < 8; ++k) jj[k] = (int)*reinterpret_cast<const Idx *>(colb + k * 64 * sizeof(Idx));
 #pragma unroll
-        for (int k = 0; k < 8; ++k) vv[k] = word(jj[k]);
-        float hx[4] = {0.f, 0.f, 0.f, 0.f}, hy[4] = {0.f, 0.f, 0.f, 0.f};
-        float lx[4] = {0.f, 0.f, 0.f, 0.f}, ly[4] = {0.f, 0.f, 0.f, 0.f};
-        auto add = [&](uint2 v, int j) {
-            const uint32_t th[4] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16};
+    for (int k = 0; k < 8; ++k) vv[k] = word(jj[k]);
+    float beta[4];
+    {
+        const int4 tq = *reinterpret_cast<const int4 *>(b.T_of_slot + s * R + 4 * q);
+        const int ts[4] = {tq.x, tq.y, tq.z, tq.w};
+        const char *bs = reinterpret_cast<const char *>(b.beta + s * R);   // this sample's ladder
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float2 u = Trig<2>::unit(th[r], nullptr);
-                hx[r] += u.x; hy[r] += u.y;
-                if (kLast && j < c0) { lx[r] += u.x; ly[r] += u.y; }
-            }
-        };
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (k < kmin) add(vv[k], jj[k]);                     // uniform, unmasked
-            else if (k < kmax && k < dg) add(vv[k], jj[k]);
-        }
-        for (int k = 8; k < dg; ++k) {
-            const int j = (int)*reinterpret_cast<const Idx *>(colb + k * 64 * (int)sizeof(Idx) + off0);
-            add(word(j), j);
-        }
-        const uint32_t sweep = b.ctl->sweep;
-        const U4 w = philox4x32_10({(uint32_t)i, sweep, (uint32_t)(4 * q), tag(sub == 0 ? kMet : kOR, (uint32_t)sub)},
-                                   d.seed_lo, d.seed_hi);
-        const uint32_t words[4] = {w.x, w.y, w.z, w.w};
-        const uint2 me = word(i);
-        const uint32_t cur_th[4] = {me.x & 0xFFFFu, me.x >> 16, me.y & 0xFFFFu, me.y >> 16};
-        uint32_t out[4];
+        for (int r = 0; r < 4; ++r) beta[r] = (float)*reinterpret_cast<const double *>(bs + 8u * (uint32_t)ts[r]);
+    }
+    const int c0 = ua.w - bx * S;                                 // first site of the colour class
+    float hx[4] = {0.f, 0.f, 0.f, 0.f}, hy[4] = {0.f, 0.f, 0.f, 0.f};
+    float lx[4] = {0.f, 0.f, 0.f, 0.f}, ly[4] = {0.f, 0.f, 0.f, 0.f};   // last sub-sweep: links to lower colours
+    auto add = [&](uint2 v, int j) {
+        const uint32_t th[4] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16};
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int slot = 4 * q + r;
-            const uint32_t th = cur_th[r];
-            const uint32_t th_new = sub == 0 ? (words[r] & 0xFFFFu) : ((field_axis2(hx[r], hy[r]) - th) & 0xFFFFu);
-            const float2 cur = Trig<2>::unit(th, nullptr), nu = Trig<2>::unit(th_new, nullptr);
-            const float dE = hx[r] * (cur.x - nu.x) + hy[r] * (cur.y - nu.y);
-            const bool acc = accept_move(dE, beta[r], words[r], (uint32_t)i, sweep, (uint32_t)slot, (uint32_t)sub, d);
-            out[r] = acc ? th_new : th;
-            if (kLast) {
-                const float2 f = acc ? nu : cur;
-                e_q[r] = -(f.x * lx[r] + f.y * ly[r]);
-            }
+            const float2 u = Trig<2>::unit(th[r], nullptr);
+            hx[r] += u.x; hy[r] += u.y;
+            if (kLast && j < c0) { lx[r] += u.x; ly[r] += u.y; }
         }
-        word(i) = make_uint2(out[0] | (out[1] << 16), out[2] | (out[3] << 16));
+    };
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (k < kmin) add(vv[k], jj[k]);                         // uniform, unmasked
+        else if (k < kmax && jj[k] != i) add(vv[k], jj[k]);
     }
+    if (kmax > 8) {                                               // uniform: rows past the eighth
+        const int dg = b.u8[d.deg + i];
+        for (int k = 8; k < dg; ++k) {
+            const int j = (int)*reinterpret_cast<const Idx *>(colb + k * 64 * (int)sizeof(Idx));
+            add(word(j), j);
+        }
+    }
+    const uint32_t sweep = b.ctl->sweep;
+    const U4 w = philox4x32_10({(uint32_t)i, sweep, (uint32_t)(4 * q), tag(sub == 0 ? kMet : kOR, (uint32_t)sub)},
+                               d.seed_lo, d.seed_hi);
+    const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+    const uint2 me = word(i);
+    const uint32_t cur_th[4] = {me.x & 0xFFFFu, me.x >> 16, me.y & 0xFFFFu, me.y >> 16};
+    uint32_t out[4];
+    float e_q[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int slot = 4 * q + r;
+        const uint32_t th = cur_th[r];
+        const uint32_t th_new = sub == 0 ? (words[r] & 0xFFFFu) : ((field_axis2(hx[r], hy[r]) - th) & 0xFFFFu);
+        const float2 cur = Trig<2>::unit(th, nullptr), nu = Trig<2>::unit(th_new, nullptr);
+        const float dE = hx[r] * (cur.x - nu.x) + hy[r] * (cur.y - nu.y);
+        const bool acc = accept_move(dE, beta[r], words[r], (uint32_t)i, sweep, (uint32_t)slot, (uint32_t)sub, d);
+        out[r] = acc ? th_new : th;
+        const float2 f = acc ? nu : cur;
+        e_q[r] = active ? -(f.x * lx[r] + f.y * ly[r]) : 0.f;
+    }
+    if (active) word(i) = make_uint2(out[0] | (out[1] << 16), out[2] | (out[3] << 16));
     if constexpr (kLast) {
         // per-slot energy of this block, summed in a fixed order, to
         // epart[k_ph][colour][block][slot]; a final pass adds the blocks in order

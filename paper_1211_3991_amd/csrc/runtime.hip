@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -32,8 +33,8 @@ struct xy_batch {
     int n_phase = 0;
     int32_t *d_phase = nullptr;
     std::vector<int> phase_units;             // per colour: work units of its launch
-    std::vector<size_t> phase_unit_off;       // per colour: first unit in d_units
-    int4 *d_units = nullptr;                  // (sample, phase-sample index, block of its class, 0)
+    std::vector<size_t> phase_unit_off;       // per colour: first int4 of its units in d_units
+    int4 *d_units = nullptr;                  // two int4 per unit (see k_fix16_phase)
     int phase_stride = 0;                     // largest block count (energy partial stride)
     size_t item_cap = 0;
     Item *d_items = nullptr;
@@ -160,7 +161,7 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
     gl.u8_pool = off;   off = align_up(off + n_u8, 256);
     gl.items = off;     off = align_up(off + kGroups * sizeof(Item) * p.item_cap, 256);
     // phase-form sample list, then per colour the (sample, block) work units
-    gl.phase = off;     off = align_up(off + align_up(4 * (size_t)G, 16) + 16 * p.phase_units, 256);
+    gl.phase = off;     off = align_up(off + align_up(4 * (size_t)G, 16) + 32 * p.phase_units, 256);
     gl.tab32 = off;     off = align_up(off + 512 * 8, 256);
     gl.tab2k = off;     off = align_up(off + 2048 * 8, 256);
     gl.tab64 = off;     off = align_up(off + 512 * 16, 256);
@@ -404,17 +405,42 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
             b->phase_units.assign(p.Qmax, 0);
             b->phase_unit_off.assign(p.Qmax, 0);
             const int spb = R % 4 == 0 ? fix16_phase_sites_per_block(R) : 1;
+            bool fits = true;
+            auto u32 = [&fits](int64_t v) {
+                if (v < 0 || v > (int64_t)UINT32_MAX) fits = false;
+                return (int)(uint32_t)v;
+            };
             for (int c = 0; c < p.Qmax; ++c) {
                 b->phase_unit_off[c] = units.size();
                 for (int k = 0; k < (int)phase.size(); ++k) {
                     const SampleDesc &d = p.desc[phase[k]];
                     if (c >= d.Q) continue;
-                    const int nb = (d.colour_off[c + 1] - d.colour_off[c] + spb - 1) / spb;
-                    for (int bx = 0; bx < nb; ++bx) units.push_back(make_int4(phase[k], k, bx, 0));
+                    const Sell &Sl = p.sell[phase[k]];
+                    const int c0 = d.colour_off[c], c1 = d.colour_off[c + 1];
+                    const int nb = (c1 - c0 + spb - 1) / spb;
+                    for (int bx = 0; bx < nb; ++bx) {
+                        // unit of kernel_phase: two int4, see k_fix16_phase
+                        const int r0 = bx * spb, n_act = std::min(spb, c1 - c0 - r0);
+                        const int chA = Sl.chunk_off[c] + (r0 >> 6);
+                        int kmin = 255, kmax = 0;
+                        for (int ch = r0 >> 6; ch <= (r0 + n_act - 1) >> 6; ++ch) {
+                            const int w = Sl.chunk_w[Sl.chunk_off[c] + ch];
+                            kmin = std::min(kmin, w & 255);
+                            kmax = std::max(kmax, w >> 8);
+                        }
+                        const int64_t colA = d.sell_col + Sl.chunk_ptr[chA];
+                        const int64_t colB = chA + 1 < Sl.chunk_off[c + 1] ? d.sell_col + Sl.chunk_ptr[chA + 1] : colA;
+                        units.push_back(make_int4(u32(colA), u32(colB), u32(d.state / 8), c0 + r0));
+                        units.push_back(make_int4(phase[k], k, bx, kmin | kmax << 8 | (n_act - 1) << 16 | (r0 & 63) << 24));
+                    }
                 }
-                b->phase_units[c] = (int)(units.size() - b->phase_unit_off[c]);
+                b->phase_units[c] = (int)((units.size() - b->phase_unit_off[c]) / 2);
             }
-            if (units.size() != p.phase_units) {
+            if (!fits) {
+                delete b;
+                return set_error(XY_EUNSUP, "xy_batch_init: phase-form offsets exceed 32 bits (batch too large)");
+            }
+            if (units.size() != 2 * p.phase_units) {
                 delete b;
                 return set_error(XY_EUNSUP, "xy_batch_init: phase-form work units do not match the plan");
             }
