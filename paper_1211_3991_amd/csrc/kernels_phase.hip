@@ -87,25 +87,32 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
     const int c0 = ua.w - bx * S;                                 // first site of the colour class
     float hx[4] = {0.f, 0.f, 0.f, 0.f}, hy[4] = {0.f, 0.f, 0.f, 0.f};
     float lx[4] = {0.f, 0.f, 0.f, 0.f}, ly[4] = {0.f, 0.f, 0.f, 0.f};   // last sub-sweep: links to lower colours
-    auto add = [&](uint2 v, int j) {
+    // a row's neighbours are sorted by colour-major index, so the links to
+    // lower colours are a prefix: their field is the running sum taken after
+    // the last of them
+    auto add = [&](uint2 v, int j, bool first) {                // first: the sum starts here
         const uint32_t th[4] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16};
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const float2 u = Trig<2>::unit(th[r], nullptr);
-            hx[r] += u.x; hy[r] += u.y;
-            if (kLast && j < c0) { lx[r] += u.x; ly[r] += u.y; }
+            hx[r] = first ? u.x : hx[r] + u.x;
+            hy[r] = first ? u.y : hy[r] + u.y;
+        }
+        if (kLast && j < c0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { lx[r] = hx[r]; ly[r] = hy[r]; }
         }
     };
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        if (k < kmin) add(vv[k], jj[k]);                         // uniform, unmasked
-        else if (k < kmax && jj[k] != i) add(vv[k], jj[k]);
+        if (k < kmin) add(vv[k], jj[k], k == 0);                 // uniform, unmasked
+        else if (k < kmax && jj[k] != i) add(vv[k], jj[k], false);
     }
     if (kmax > 8) {                                               // uniform: rows past the eighth
         const int dg = b.u8[d.deg + i];
         for (int k = 8; k < dg; ++k) {
             const int j = (int)*reinterpret_cast<const Idx *>(colb + k * 64 * (int)sizeof(Idx));
-            add(word(j), j);
+            add(word(j), j, false);
         }
     }
     const uint32_t sweep = b.ctl->sweep;

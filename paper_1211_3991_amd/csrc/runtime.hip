@@ -36,6 +36,12 @@ struct xy_batch {
     std::vector<size_t> phase_unit_off;       // per colour: first int4 of its units in d_units
     int4 *d_units = nullptr;                  // two int4 per unit (see k_fix16_phase)
     int phase_stride = 0;                     // largest block count (energy partial stride)
+    // the phase launches of a sweep split by sample over the caller's stream
+    // and `aux`, so that the ramp and tail of one launch overlap the other
+    // stream's work; fork and join through events on the caller's stream
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    std::vector<int> phase_split;             // per colour: units on the caller's stream
     size_t item_cap = 0;
     Item *d_items = nullptr;
     int lds_limit = 0;
@@ -444,6 +450,36 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
                 delete b;
                 return set_error(XY_EUNSUP, "xy_batch_init: phase-form work units do not match the plan");
             }
+            // two streams (XY_PHASE_STREAMS=1 keeps one): the phase samples
+            // [0, k_split) on the caller's stream, the rest on `aux`, k_split
+            // halving the work units
+            int n_streams = 2;
+            if (const char *env = std::getenv("XY_PHASE_STREAMS")) n_streams = std::atoi(env) == 1 ? 1 : 2;
+            b->phase_split = b->phase_units;
+            if (n_streams == 2 && phase.size() >= 2) {
+                std::vector<size_t> per(phase.size(), 0);
+                for (size_t a = 1; a < units.size(); a += 2) ++per[units[a].y];
+                size_t half = 0, acc = 0, k_split = 1;
+                for (size_t v : per) half += v;
+                for (size_t k = 0; k + 1 < per.size(); ++k) {
+                    acc += per[k];
+                    k_split = k + 1;
+                    if (2 * acc >= half) break;
+                }
+                for (int c = 0; c < p.Qmax; ++c) {
+                    int n1 = 0;
+                    for (int a = 0; a < b->phase_units[c]; ++a)
+                        if ((size_t)units[b->phase_unit_off[c] + 2 * a + 1].y < k_split) ++n1;
+                    b->phase_split[c] = n1;
+                }
+                hipError_t e = hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking);
+                if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+                if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
+                if (e != hipSuccess) {
+                    xy_batch_free(b);
+                    return hip_err(e, "xy_batch_init: phase stream");
+                }
+            }
             unsigned char *ph = gimg.data() + gl.phase;
             std::copy(phase.begin(), phase.end(), reinterpret_cast<int32_t *>(ph));
             std::copy(units.begin(), units.end(), reinterpret_cast<int4 *>(ph + align_up(4 * (size_t)G, 16)));
@@ -561,10 +597,20 @@ hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream
             e = launch_fix16_sweep(b->dev, grp.items, grp.n_items, grp.mode, grp.block, n_or, do_rec, grp.lds, s);
             if (e != hipSuccess) break;
         }
+        const bool fork = b->n_phase > 0 && b->aux;
+        if (e == hipSuccess && fork) e = hipEventRecord(b->ev_fork, s);
+        if (e == hipSuccess && fork) e = hipStreamWaitEvent(b->aux, b->ev_fork, 0);
         for (int sub = 0; sub <= n_or && e == hipSuccess && b->n_phase > 0; ++sub)
-            for (int c = 0; c < (int)b->phase_units.size() && e == hipSuccess; ++c)
-                e = launch_fix16_phase(b->dev, b->d_units + b->phase_unit_off[c], c, sub, sub == n_or,
-                                       b->phase_units[c], b->phase_stride, s);
+            for (int c = 0; c < (int)b->phase_units.size() && e == hipSuccess; ++c) {
+                const int n1 = b->phase_split[c];
+                const int4 *u = b->d_units + b->phase_unit_off[c];
+                e = launch_fix16_phase(b->dev, u, c, sub, sub == n_or, n1, b->phase_stride, s);
+                if (e == hipSuccess && fork)
+                    e = launch_fix16_phase(b->dev, u + 2 * (size_t)n1, c, sub, sub == n_or, b->phase_units[c] - n1,
+                                           b->phase_stride, b->aux);
+            }
+        if (e == hipSuccess && fork) e = hipEventRecord(b->ev_join, b->aux);
+        if (e == hipSuccess && fork) e = hipStreamWaitEvent(s, b->ev_join, 0);
         // the timed part: the sweep kernels (with their fused energies) and the
         // colour-phase kernels of the phase form
         if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
@@ -867,5 +913,8 @@ extern "C" void xy_batch_free(xy_batch *b)
         (void)hipEventDestroy(pr.first);
         (void)hipEventDestroy(pr.second);
     }
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+    if (b->aux) (void)hipStreamDestroy(b->aux);
     delete b;
 }
