@@ -39,9 +39,10 @@ struct xy_batch {
     // the phase launches of a sweep split by sample over the caller's stream
     // and `aux`, so that the ramp and tail of one launch overlap the other
     // stream's work; fork and join through events on the caller's stream
-    hipStream_t aux = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    std::vector<int> phase_split;             // per colour: units on the caller's stream
+    std::vector<hipStream_t> aux;             // groups 1.. (group 0 runs on the caller's stream)
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;          // per auxiliary stream
+    std::vector<int> phase_bounds;            // [colour][group + 1]: first unit of each group
     size_t item_cap = 0;
     Item *d_items = nullptr;
     int lds_limit = 0;
@@ -450,34 +451,52 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
                 delete b;
                 return set_error(XY_EUNSUP, "xy_batch_init: phase-form work units do not match the plan");
             }
-            // two streams (XY_PHASE_STREAMS=1 keeps one): the phase samples
-            // [0, k_split) on the caller's stream, the rest on `aux`, k_split
-            // halving the work units
+            // the phase samples in n_streams contiguous groups of about equal
+            // work units, group 0 on the caller's stream and the others on
+            // auxiliary streams (XY_PHASE_STREAMS=1..4, default 2)
             int n_streams = 2;
-            if (const char *env = std::getenv("XY_PHASE_STREAMS")) n_streams = std::atoi(env) == 1 ? 1 : 2;
-            b->phase_split = b->phase_units;
-            if (n_streams == 2 && phase.size() >= 2) {
+            if (const char *env = std::getenv("XY_PHASE_STREAMS")) n_streams = std::min(4, std::max(1, std::atoi(env)));
+            n_streams = std::max(1, std::min(n_streams, (int)phase.size()));
+            std::vector<size_t> first_sample(n_streams + 1, phase.size());   // group g: [first[g], first[g+1])
+            first_sample[0] = 0;
+            {
                 std::vector<size_t> per(phase.size(), 0);
                 for (size_t a = 1; a < units.size(); a += 2) ++per[units[a].y];
-                size_t half = 0, acc = 0, k_split = 1;
-                for (size_t v : per) half += v;
-                for (size_t k = 0; k + 1 < per.size(); ++k) {
+                size_t total = 0, acc = 0;
+                for (size_t v : per) total += v;
+                int g = 1;
+                for (size_t k = 0; k < per.size() && g < n_streams; ++k) {
                     acc += per[k];
-                    k_split = k + 1;
-                    if (2 * acc >= half) break;
+                    // close group g-1 after sample k once it holds its share,
+                    // leaving a sample for each later group
+                    if (acc * n_streams >= total * g && per.size() - (k + 1) >= (size_t)(n_streams - g))
+                        first_sample[g++] = k + 1;
                 }
-                for (int c = 0; c < p.Qmax; ++c) {
-                    int n1 = 0;
+                for (; g < n_streams; ++g) first_sample[g] = std::min(phase.size(), first_sample[g - 1] + 1);
+            }
+            b->phase_bounds.assign((size_t)p.Qmax * (n_streams + 1), 0);
+            for (int c = 0; c < p.Qmax; ++c) {
+                int *bd = b->phase_bounds.data() + (size_t)c * (n_streams + 1);
+                for (int g = 0; g <= n_streams; ++g) {
+                    int n = 0;   // units of colour c whose sample precedes group g
                     for (int a = 0; a < b->phase_units[c]; ++a)
-                        if ((size_t)units[b->phase_unit_off[c] + 2 * a + 1].y < k_split) ++n1;
-                    b->phase_split[c] = n1;
+                        if ((size_t)units[b->phase_unit_off[c] + 2 * a + 1].y < first_sample[g]) ++n;
+                    bd[g] = n;
                 }
-                hipError_t e = hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking);
-                if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
-                if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
+            }
+            if (n_streams > 1) {
+                hipError_t e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+                for (int g = 1; g < n_streams && e == hipSuccess; ++g) {
+                    hipStream_t st = nullptr;
+                    hipEvent_t ev = nullptr;
+                    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+                    if (e == hipSuccess) b->aux.push_back(st);
+                    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+                    if (e == hipSuccess) b->ev_join.push_back(ev);
+                }
                 if (e != hipSuccess) {
                     xy_batch_free(b);
-                    return hip_err(e, "xy_batch_init: phase stream");
+                    return hip_err(e, "xy_batch_init: phase streams");
                 }
             }
             unsigned char *ph = gimg.data() + gl.phase;
@@ -490,7 +509,7 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
                                                   align_up(4 * (size_t)G, 16));
             Item *items = reinterpret_cast<Item *>(gimg.data() + gl.items);
             if (!build_groups(b, trig, allow_unit, force_global, items)) {
-                delete b;
+                xy_batch_free(b);
                 return set_error(XY_EUNSUP, "xy_batch_init: work-item list exceeds its capacity");
             }
         }
@@ -510,7 +529,7 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
         hipError_t e;
         if ((e = hipMemcpyAsync(d_graph, gimg.data(), gimg.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
             (e = hipMemcpyAsync(d_work, wimg.data(), wimg.size(), hipMemcpyHostToDevice, s)) != hipSuccess) {
-            delete b;
+            xy_batch_free(b);
             return hip_err(e, "xy_batch_init upload");
         }
 
@@ -545,9 +564,9 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
 
         e = (precision == XY_FP64) ? launch_fp64_init(dv, p.max_n, s) : launch_fix16_init(dv, p.max_n, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);   // host images must outlive the copies
-        if (e != hipSuccess) { delete b; return hip_err(e, "xy_batch_init"); }
+        if (e != hipSuccess) { xy_batch_free(b); return hip_err(e, "xy_batch_init"); }
     } catch (const std::bad_alloc &) {
-        delete b;
+        xy_batch_free(b);
         return set_error(XY_ENOMEM, "xy_batch_init: out of memory");
     }
     *out = b;
@@ -597,20 +616,22 @@ hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream
             e = launch_fix16_sweep(b->dev, grp.items, grp.n_items, grp.mode, grp.block, n_or, do_rec, grp.lds, s);
             if (e != hipSuccess) break;
         }
-        const bool fork = b->n_phase > 0 && b->aux;
+        const int n_st = 1 + (int)b->aux.size();
+        const bool fork = b->n_phase > 0 && n_st > 1;
         if (e == hipSuccess && fork) e = hipEventRecord(b->ev_fork, s);
-        if (e == hipSuccess && fork) e = hipStreamWaitEvent(b->aux, b->ev_fork, 0);
+        for (int g = 1; g < n_st && fork && e == hipSuccess; ++g) e = hipStreamWaitEvent(b->aux[g - 1], b->ev_fork, 0);
         for (int sub = 0; sub <= n_or && e == hipSuccess && b->n_phase > 0; ++sub)
             for (int c = 0; c < (int)b->phase_units.size() && e == hipSuccess; ++c) {
-                const int n1 = b->phase_split[c];
+                const int *bd = b->phase_bounds.data() + (size_t)c * (n_st + 1);
                 const int4 *u = b->d_units + b->phase_unit_off[c];
-                e = launch_fix16_phase(b->dev, u, c, sub, sub == n_or, n1, b->phase_stride, s);
-                if (e == hipSuccess && fork)
-                    e = launch_fix16_phase(b->dev, u + 2 * (size_t)n1, c, sub, sub == n_or, b->phase_units[c] - n1,
-                                           b->phase_stride, b->aux);
+                for (int g = 0; g < n_st && e == hipSuccess; ++g)
+                    e = launch_fix16_phase(b->dev, u + 2 * (size_t)bd[g], c, sub, sub == n_or, bd[g + 1] - bd[g],
+                                           b->phase_stride, g == 0 ? s : b->aux[g - 1]);
             }
-        if (e == hipSuccess && fork) e = hipEventRecord(b->ev_join, b->aux);
-        if (e == hipSuccess && fork) e = hipStreamWaitEvent(s, b->ev_join, 0);
+        for (int g = 1; g < n_st && fork && e == hipSuccess; ++g) {
+            e = hipEventRecord(b->ev_join[g - 1], b->aux[g - 1]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, b->ev_join[g - 1], 0);
+        }
         // the timed part: the sweep kernels (with their fused energies) and the
         // colour-phase kernels of the phase form
         if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
@@ -914,7 +935,7 @@ extern "C" void xy_batch_free(xy_batch *b)
         (void)hipEventDestroy(pr.second);
     }
     if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
-    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
-    if (b->aux) (void)hipStreamDestroy(b->aux);
+    for (hipEvent_t ev : b->ev_join) (void)hipEventDestroy(ev);
+    for (hipStream_t st : b->aux) (void)hipStreamDestroy(st);
     delete b;
 }
