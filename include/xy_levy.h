@@ -168,6 +168,14 @@ xy_status xy_measure(xy_batch *b, double *d_out, void *stream);
  * current state, pair parity from the sweep counter). */
 xy_status xy_pt_swap(xy_batch *b, void *stream);
 
+/* The replica energies E = -sum over links cos(theta_i - theta_j) (Eq. HXY)
+ * that the last tempering step used, by replica slot: copies
+ * double[n_graphs][n_T slots] into caller-owned device memory d_out,
+ * asynchronously on `stream`.  Defined after a sweep with tempering or an
+ * xy_pt_swap; the fixed-point path sums them from FP32 link energies (Sec. 4,
+ * parallel tempering). */
+xy_status xy_pt_energies(xy_batch *b, double *d_out, void *stream);
+
 /* Synchronous copies of the state (checkpoint, tests).  Host layout:
  *   fp64 : double[n_graphs][n_T slots][n_i][2], lattice order
  *   fix16: uint16[n_graphs][n_T slots][n_i], lattice order

@@ -175,6 +175,14 @@ class Batch:
         self.synchronize()
         return out
 
+    def pt_energies(self):
+        """Replica energies the last tempering step used, by slot: device
+        tensor [G, n_T] (float64), complete when this returns."""
+        out = self._torch.empty((self.G, self.R), dtype=self._torch.float64, device=self.device)
+        _lib.call("xy_pt_energies", self._h, ctypes.c_void_p(out.data_ptr()), self._s())
+        self.synchronize()
+        return out
+
     def pt_swap(self):
         _lib.call("xy_pt_swap", self._h, self._s())
 

@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "XY_OK", -1: "XY_EINVAL", -2: "XY_ENOMEM", -3: "XY_EHIP", -4:
                 -5: "XY_EUNSUP", -6: "XY_ECONVERGE"}
 
 EXPORTS = ("xy_graph_levy", "xy_graph_levy_free", "xy_graph_from_edges", "xy_graph_info", "xy_graph_export", "xy_graph_free",
-           "xy_batch_sizes", "xy_batch_init", "xy_sweep", "xy_measure", "xy_pt_swap", "xy_get_state",
+           "xy_batch_sizes", "xy_batch_init", "xy_sweep", "xy_measure", "xy_pt_energies", "xy_pt_swap", "xy_get_state",
            "xy_set_state", "xy_get_counters", "xy_decision_log", "xy_batch_use_graph", "xy_batch_set_fix16_form", "xy_batch_forms", "xy_walk_bytes", "xy_random_walk", "xy_kernel_timing",
            "xy_kernel_time", "xy_last_error", "xy_batch_free")
 
@@ -58,6 +58,7 @@ _sigs = {
     "xy_batch_init": ([ctypes.POINTER(_vp), _vp, _i32, _i32, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp], _i32),
     "xy_sweep": ([_vp, _i32, _i32, _i32, _i32, _vp], _i32),
     "xy_measure": ([_vp, _vp, _vp], _i32),
+    "xy_pt_energies": ([_vp, _vp, _vp], _i32),
     "xy_pt_swap": ([_vp, _vp], _i32),
     "xy_get_state": ([_vp, _vp, _vp, ctypes.POINTER(_u32), _vp], _i32),
     "xy_set_state": ([_vp, _vp, _vp, _u32, _vp], _i32),

@@ -704,6 +704,14 @@ extern "C" xy_status xy_batch_use_graph(xy_batch *b, int chunk)
     return XY_OK;
 }
 
+extern "C" xy_status xy_pt_energies(xy_batch *b, double *d_out, void *stream)
+{
+    if (!b || !d_out) return set_error(XY_EINVAL, "xy_pt_energies: NULL argument");
+    const hipError_t e = hipMemcpyAsync(d_out, b->dev.E_slot, sizeof(double) * (size_t)b->G * b->R,
+                                        hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? XY_OK : hip_err(e, "xy_pt_energies");
+}
+
 extern "C" xy_status xy_measure(xy_batch *b, double *d_out, void *stream)
 {
     if (!b || !d_out) return set_error(XY_EINVAL, "xy_measure: bad arguments");

@@ -330,6 +330,29 @@ def test_phase_form_pt_batch_matches_fp64_gpu(monkeypatch):
     assert np.max(np.abs(np.array(zs))) < 4.0, zs
 
 
+@pytest.mark.parametrize("streams", ["1", "2", "3"])
+def test_tempering_energies_equal_state_energy(streams, monkeypatch):
+    """The replica energies the tempering step uses (summed in the last
+    sub-sweep over the links to lower colours) equal
+    -sum_links cos(theta_i - theta_j) of the state, in FP64 from the exported
+    links: phase form with its samples in one to three stream groups, and a
+    workgroup-form sample."""
+    monkeypatch.setenv("XY_PHASE_STREAMS", streams)
+    graphs = [xy.Graph.levy(128, 6, 3.5, s) for s in range(5)] + [xy.Graph.levy(32, 6, 2.5, 7)]
+    T = workloads.linear_ladder(1.0, 2.5, 8)
+    b = xy.Batch(graphs, T, precision="fix16", seeds=np.arange(6) + 40)
+    assert list(b.forms()) == [1, 1, 1, 1, 1, 0]
+    b.sweep(7, pt_every=1, meas_every=0)
+    E = b.pt_energies().cpu().numpy()
+    st, _, _ = b.get_state()
+    for k, g in enumerate(graphs):
+        e = g.export()["edges"]
+        for slot in range(len(T)):
+            th = st[k][slot].astype(np.float64) * (2 * np.pi / 65536)
+            ref = -np.cos(th[e[:, 0]] - th[e[:, 1]]).sum()
+            assert abs(E[k, slot] - ref) <= 1e-5 * abs(ref), (k, slot, E[k, slot], ref)
+
+
 def test_phase_form_state_roundtrip_and_resume(monkeypatch):
     monkeypatch.setenv("XY_FIX16_PHASE", "1")
     graphs = [xy.Graph.levy(16, 6, 3.5, 1), xy.Graph.levy(32, 6, 2.5, 2)]
