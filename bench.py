@@ -55,7 +55,8 @@ def alg_bytes_per_update(b_s, z, R):
 
 def kernel_source_digest():
     h = hashlib.sha256()
-    for f in ("kernels_phase.hip", "fix16_common.hpp", "kernels.hpp", "xy_internal.hpp"):
+    # the kernel sources and the runtime that groups its launches
+    for f in ("kernels_phase.hip", "fix16_common.hpp", "kernels.hpp", "xy_internal.hpp", "runtime.hip"):
         with open(os.path.join(ROOT, "paper_1211_3991_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -288,7 +289,8 @@ def main():
     if args.precision == "fp64":
         kname = "k_fp64_phase (the 6·Q colour-phase launches of one sweep)"
     elif uses_phase_form(wl):
-        kname = "k_fix16_phase (the 6·Q colour-phase launches of one sweep, all samples per launch)"
+        kname = ("k_fix16_phase (the colour-phase launches of one sweep: 6·Q per sample group, two groups on "
+                 "two streams; timed by HIP events on the caller's stream around the fork, the launches and the join)")
     else:
         kname = "k_fix16_sweep (one launch = one sweep of every (sample, slot))"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
