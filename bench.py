@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
+VALU_PEAK_TLANE = 78.64    # 256 CUs x 4 SIMDs x 64 lanes x 2.4 GHz / 2 cycles per wave instruction, in 1e12/s
 
 
 def traffic_file(workload):
@@ -129,7 +130,7 @@ def write_traffic(wl, paths, argv):
     CSVs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch, summed over a sweep's
     dispatches), each scaled by what the same counter reads for a plain 512 MiB
     device copy."""
-    fetch, write, cal_f, cal_w = (_pmc_rows(p) for p in paths)
+    fetch, write, cal_f, cal_w = (_pmc_rows(p) for p in paths[:4])
     pat = "k_fix16_phase<" if uses_phase_form(wl) else "k_fix16_sweep<"
 
     def per_sweep(rows, counter, n_last=4):
@@ -166,6 +167,11 @@ def write_traffic(wl, paths, argv):
            "write_kib_per_sweep": round(w_kib, 1), "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
            "bytes_per_sweep": int(bytes_sweep), "bytes_per_update": round(bytes_sweep / upd, 4),
            "updates_per_sweep": upd, "command": f"python bench.py {argv}"}
+    if len(paths) > 4:
+        # VALU wave instructions of the same dispatches; x 64 lanes
+        _, valu, _ = per_sweep(_pmc_rows(paths[4]), "SQ_INSTS_VALU")
+        out["valu_lane_instr_per_sweep"] = int(valu * 64)
+        out["valu_lane_instr_per_update"] = round(valu * 64 / upd, 2)
     with open(traffic_file(wl.name), "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
@@ -236,11 +242,14 @@ def main():
                     help="sweeps of the Metropolis-only run that splits the rate into Met and OR (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (HBM counter calibration)")
-    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH_CSV", "CAL_WRITE_CSV"),
-                    help="no GPU work: turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter CSVs of this workload "
-                         "and of --calibrate-copy 512 into profiles/traffic_<workload>.json")
+    ap.add_argument("--traffic-from", nargs="+", metavar="CSV",
+                    help="no GPU work: FETCH_CSV WRITE_CSV CAL_FETCH_CSV CAL_WRITE_CSV [SQ_CSV]: turn rocprofv3 --pmc "
+                         "FETCH_SIZE / WRITE_SIZE counter CSVs of this workload and of --calibrate-copy 512 (and "
+                         "optionally one with SQ_INSTS_VALU) into profiles/traffic_<workload>.json")
     args = ap.parse_args()
     if args.traffic_from:
+        if len(args.traffic_from) not in (4, 5):
+            ap.error("--traffic-from takes 4 or 5 CSV paths")
         write_traffic(workloads.ALL[args.workload](), args.traffic_from, " ".join(sys.argv[1:]))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -298,6 +307,17 @@ def main():
                 "kernel": kname,
                 "kernel_ms": round(k_ms, 4), "alg_bytes_per_update": round(bpu, 3),
                 "updates_per_launch": upd_per_sweep}
+    # the bound the kernel meets first: VALU issue, from the counted VALU
+    # instructions of the same launches (same digest rule as the traffic)
+    alu = None
+    if traffic is not None and tr.get("valu_lane_instr_per_sweep"):
+        lane = tr["valu_lane_instr_per_sweep"] / (k_ms * 1e-3) / 1e12
+        alu = {"bound": "alu", "achieved": round(lane, 2), "peak": VALU_PEAK_TLANE, "unit": "T VALU lane-instr/s",
+               "frac": round(lane / VALU_PEAK_TLANE, 4),
+               "lane_instr_per_update": tr["valu_lane_instr_per_update"],
+               "note": "peak: 256 CUs x 4 SIMDs x 64 lanes x 2.4 GHz / 2 cycles per wave instruction (the FP32 "
+                       "157.3 TFLOP/s counting an FMA as 2); about 17 of the instructions per update are "
+                       "transcendentals, which issue at about a third of that rate"}
 
     fp64 = None
     if args.precision == "fix16" and args.fp64_steps > 0:
@@ -345,6 +365,7 @@ def main():
                    "state": "uint16 angles, FP32 fields, FP64 accumulators" if args.precision == "fix16"
                    else "FP64 unit vectors", "parallelism": "samples x temperatures on one GPU"},
         "roofline": roofline,
+        "alu_roofline": alu,
         "fp64_plain": fp64,
         "sub_sweep_rates": split,
         "random_walk": walk,

@@ -65,8 +65,9 @@ template <> struct Trig<2> {
 
 // 2 phi in units of 2pi/2^16, rounded, for phi = atan2(hy, hx): the axis of
 // the over-relaxation reflection.  atan on [0, 1] by an odd polynomial of
-// degree 11, least-squares fitted on 4000 Chebyshev nodes (|error| < 2e-6
-// rad in FP32), then the octant is restored.
+// degree 9, least-squares fitted on 4000 Chebyshev nodes (|error| < 1.3e-5
+// rad in FP32, an eighth of the angle quantum 2pi/2^16), then the octant is
+// restored.
 // The accuracy only affects the acceptance rate of the reflection, not the
 // detailed balance (the reflection is accepted by a Metropolis test).
 __device__ __forceinline__ uint32_t field_axis2(float hx, float hy)
@@ -75,12 +76,11 @@ __device__ __forceinline__ uint32_t field_axis2(float hx, float hy)
     const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
     const float t = mx > 0.f ? mn * __builtin_amdgcn_rcpf(mx) : 0.f;
     const float t2 = t * t;
-    float p = -0.011770499870181084f;
-    p = fmaf(p, t2, 0.05282348766922951f);
-    p = fmaf(p, t2, -0.11665111780166626f);
-    p = fmaf(p, t2, 0.19367031753063202f);
-    p = fmaf(p, t2, -0.33265548944473267f);
-    p = fmaf(p, t2, 0.9999798536300659f);
+    float p = 0.02093181200325489f;
+    p = fmaf(p, t2, -0.08540830761194229f);
+    p = fmaf(p, t2, 0.1804126799106598f);
+    p = fmaf(p, t2, -0.3304055631160736f);
+    p = fmaf(p, t2, 0.9998787641525269f);
     float a = p * t;                                   // atan(t), t in [0, 1]
     a = ay > ax ? 1.5707963267948966f - a : a;
     a = hx < 0.f ? 3.141592653589793f - a : a;

@@ -1,0 +1,69 @@
+"""Accuracy of the over-relaxation axis of the fixed-point path (no GPU).
+
+The fixed-point over-relaxation reflects a 16-bit angle about the local field,
+theta' = 2 phi_q - theta, where phi_q is atan2(h_y, h_x) on the 2^16 grid
+(Sec. 3, improved equilibrium dynamics; the reflection is then accepted by a
+Metropolis test).  The device evaluates atan on [0, 1] by an odd polynomial.
+Its coefficients are read from the device source, the polynomial is evaluated
+in FP32 with one rounding per fused multiply-add, and the error must stay below
+the bound the source states (an eighth of the angle quantum), so that 2 phi_q
+is off the exact rounding by at most one grid step.
+"""
+import os
+import re
+
+import numpy as np
+
+SRC = os.path.join(os.path.dirname(__file__), "..", "paper_1211_3991_amd", "csrc", "fix16_common.hpp")
+
+
+def _coefficients():
+    body = open(SRC).read()
+    body = body[body.index("uint32_t field_axis2("):]
+    body = body[:body.index("float a = p * t;")]
+    first = re.search(r"float p = ([-0-9.e]+)f;", body).group(1)
+    rest = re.findall(r"p = fmaf\(p, t2, ([-0-9.e]+)f\);", body)
+    return [np.float32(float(v)) for v in [first] + rest]       # highest degree first
+
+
+def _fma32(a, b, c):
+    # a*b is exact in FP64 for FP32 operands; the sum is rounded to FP64 and then to FP32
+    return (a.astype(np.float64) * b.astype(np.float64) + np.float64(c)).astype(np.float32)
+
+
+def _atan01(t):
+    t = t.astype(np.float32)
+    t2 = (t * t).astype(np.float32)
+    c = _coefficients()
+    p = np.full_like(t, c[0])
+    for ck in c[1:]:
+        p = _fma32(p, t2, ck)
+    return (p * t).astype(np.float32)
+
+
+def test_polynomial_within_stated_bound():
+    t = np.linspace(0.0, 1.0, 1 << 20)
+    err = np.abs(_atan01(t).astype(np.float64) - np.arctan(t.astype(np.float32).astype(np.float64)))
+    assert len(_coefficients()) == 5                      # degree 9
+    assert err.max() < 1.3e-5, err.max()
+    assert 1.3e-5 < (2 * np.pi / 65536) / 7               # under an eighth of the quantum (with margin)
+
+
+def test_axis_within_one_grid_step():
+    """2 phi on the 2^16 grid, with the octant restored as on the device, is
+    the exact rounding or one step from it over random fields (about 15% of
+    them one step off: the reflected angle is then one quantum from the
+    exact reflection, which the Metropolis test of the move absorbs)."""
+    rng = np.random.default_rng(7)
+    hx, hy = (rng.standard_normal(200000) * 3).astype(np.float32), (rng.standard_normal(200000) * 3).astype(np.float32)
+    ax, ay = np.abs(hx), np.abs(hy)
+    mx, mn = np.maximum(ax, ay), np.minimum(ax, ay)
+    a = _atan01((mn / mx).astype(np.float32)).astype(np.float64)
+    a = np.where(ay > ax, np.pi / 2 - a, a)
+    a = np.where(hx < 0, np.pi - a, a)
+    a = np.where(hy < 0, -a, a)
+    got = np.rint(a * 65536 / np.pi).astype(np.int64) & 0xFFFF
+    exact = np.rint(np.arctan2(hy.astype(np.float64), hx.astype(np.float64)) * 65536 / np.pi).astype(np.int64) & 0xFFFF
+    d = (got - exact) & 0xFFFF
+    d = np.minimum(d, 65536 - d)
+    assert d.max() <= 1 and d.mean() < 0.25, (d.max(), d.mean())
