@@ -369,11 +369,14 @@ __global__ __launch_bounds__(kPhaseEnergyBlock) void k_fix16_phase_energy(DevBat
         for (int c = 0; c < d.Q; ++c) {
             const int nb = (d.colour_off[c + 1] - d.colour_off[c] + S - 1) / S;
             const double *src = b.epart + ((int64_t)k * kMaxColours + c) * max_blocks * R + slot;
+            // eight loads in flight, added in block order
             int blk = part;
-            for (; blk + 3 * P < nb; blk += 4 * P) {
-                const double a0 = src[(int64_t)blk * R], a1 = src[(int64_t)(blk + P) * R];
-                const double a2 = src[(int64_t)(blk + 2 * P) * R], a3 = src[(int64_t)(blk + 3 * P) * R];
-                e += a0; e += a1; e += a2; e += a3;
+            for (; blk + 7 * P < nb; blk += 8 * P) {
+                double a[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] = src[(int64_t)(blk + u * P) * R];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) e += a[u];
             }
             for (; blk < nb; blk += P) e += src[(int64_t)blk * R];
         }

@@ -192,38 +192,44 @@ __global__ __launch_bounds__(kBlock) void k_fp64_observe_final(DevBatch b, int f
 //  - parallel tempering (App. B; Hukushima-Nemoto): pairs (k, k+1) with
 //    k = sweep mod 2, +2, ...; the temperature labels of the two slots are
 //    swapped with probability min(1, exp((beta_k - beta_{k+1})(E_k - E_{k+1})));
-//  - a record of the per-slot observables, reordered by temperature;
+//    the pairs of one sweep are disjoint, so a thread takes one (sample, k)
+//  - a record of the per-slot observables, reordered by temperature, one
+//    thread per (sample, temperature) after the swaps;
 //  - sweep counter (and record counter) advance.
-__global__ __launch_bounds__(kBlock) void k_end_sweep(DevBatch b, int do_pt, int do_record, int advance)
+constexpr int kEndBlock = 1024;
+
+__global__ __launch_bounds__(kEndBlock) void k_end_sweep(DevBatch b, int do_pt, int do_record, int advance)
 {
     const uint32_t sweep = b.ctl->sweep;
     const uint32_t rec = b.ctl->n_records;
-    const int R = b.R;
-    for (int s = threadIdx.x; s < b.G; s += kBlock) {
-        const SampleDesc &d = b.desc[s];
-        int32_t *sot = b.slot_of_T + s * R;
-        int32_t *tos = b.T_of_slot + s * R;
-        if (do_pt) {
+    const int R = b.R, GR = b.G * R;
+    if (do_pt) {
+        for (int t = threadIdx.x; t < GR; t += kEndBlock) {
+            const int s = t / R, k = t - s * R;
+            if (((k ^ (int)sweep) & 1) || k + 1 >= R) continue;
+            int32_t *sot = b.slot_of_T + s * R;
+            int32_t *tos = b.T_of_slot + s * R;
             const double *beta = b.beta + s * R;
             const double *E = b.E_slot + s * R;
-            for (int k = (int)(sweep & 1u); k + 1 < R; k += 2) {
-                const int lo = sot[k], hi = sot[k + 1];
-                const double delta = (beta[k] - beta[k + 1]) * (E[lo] - E[hi]);
-                const U4 w = draw(d, (uint32_t)k, sweep, 0u, tag(kPT));
-                const bool accept = delta >= 0.0 || unit53(w.x, w.y) < exp(delta);
-                b.pt_try[s * R + k] += 1;
-                if (accept) {
-                    sot[k] = hi; sot[k + 1] = lo;
-                    tos[hi] = k; tos[lo] = k + 1;
-                    b.pt_acc[s * R + k] += 1;
-                }
+            const int lo = sot[k], hi = sot[k + 1];
+            const double delta = (beta[k] - beta[k + 1]) * (E[lo] - E[hi]);
+            const U4 w = draw(b.desc[s], (uint32_t)k, sweep, 0u, tag(kPT));
+            const bool accept = delta >= 0.0 || unit53(w.x, w.y) < exp(delta);
+            b.pt_try[t] += 1;
+            if (accept) {
+                sot[k] = hi; sot[k + 1] = lo;
+                tos[hi] = k; tos[lo] = k + 1;
+                b.pt_acc[t] += 1;
             }
         }
-        if (do_record && rec < (uint32_t)b.max_records) {
-            double *dst = b.records + (((int64_t)rec * b.G + s) * R) * XY_NOBS;
-            for (int k = 0; k < R; ++k)
-                for (int q = 0; q < XY_NOBS; ++q)
-                    dst[(int64_t)k * XY_NOBS + q] = b.obs_slot[((int64_t)s * R + sot[k]) * XY_NOBS + q];
+    }
+    __syncthreads();                                   // the swapped labels, before the record
+    if (do_record && rec < (uint32_t)b.max_records) {
+        for (int t = threadIdx.x; t < GR; t += kEndBlock) {
+            const int s = t / R;                       // t = s R + temperature index
+            const double *src = b.obs_slot + ((int64_t)s * R + b.slot_of_T[t]) * XY_NOBS;
+            double *dst = b.records + ((int64_t)rec * GR + t) * XY_NOBS;
+            for (int q = 0; q < XY_NOBS; ++q) dst[q] = src[q];
         }
     }
     __syncthreads();
@@ -265,7 +271,7 @@ hipError_t launch_fp64_observe(const DevBatch &b, int full, double *out_by_T, hi
 
 hipError_t launch_end_sweep(const DevBatch &b, int do_pt, int do_record, int advance, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_end_sweep, dim3(1), dim3(kBlock), 0, s, b, do_pt, do_record, advance);
+    hipLaunchKernelGGL(k_end_sweep, dim3(1), dim3(kEndBlock), 0, s, b, do_pt, do_record, advance);
     return hipGetLastError();
 }
 
