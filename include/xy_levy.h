@@ -207,10 +207,14 @@ xy_status xy_batch_use_graph(xy_batch *b, int chunk);
 /* Kernel timing for roofline reports: while enabled, every xy_sweep records a
  * HIP event pair on its stream around the dominant kernels of each sweep (the
  * fix16 sweep kernels and the fix16 phase-form colour-phase kernels, or the
- * colour-phase kernels of an FP64 sweep); HIP graph
- * replay is bypassed meanwhile.  xy_kernel_time synchronises the stream of the
- * last sweep, returns the summed elapsed milliseconds and the number of timed
- * sweeps since timing was enabled, and keeps timing on. */
+ * colour-phase kernels of an FP64 sweep).  When every sample is in the phase
+ * form and its samples run as two or more stream groups, the groups fork from
+ * the caller's stream once per xy_sweep call and each runs its own energies,
+ * tempering and records; the event pair then brackets the whole call, whose
+ * sweeps it counts.  HIP graph replay is bypassed meanwhile.  xy_kernel_time
+ * synchronises the stream of the last sweep, returns the summed elapsed
+ * milliseconds and the number of timed sweeps since timing was enabled, and
+ * keeps timing on. */
 xy_status xy_kernel_timing(xy_batch *b, int enable);
 xy_status xy_kernel_time(xy_batch *b, double *ms_total, int *n_timed);
 

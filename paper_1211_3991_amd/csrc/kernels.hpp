@@ -40,7 +40,9 @@ struct DevBatch {
 hipError_t launch_fp64_init(const DevBatch &b, int max_n, hipStream_t s);
 hipError_t launch_fp64_phase(const DevBatch &b, int colour, int met, int max_class, hipStream_t s);
 hipError_t launch_fp64_observe(const DevBatch &b, int full, double *out_by_T, hipStream_t s);
-hipError_t launch_end_sweep(const DevBatch &b, int do_pt, int do_record, int advance, hipStream_t s);
+// samples: the samples to temper and record (NULL: all); ctl: b.ctl[grp]
+hipError_t launch_end_sweep(const DevBatch &b, const int32_t *samples, int n_samples, int grp, int do_pt,
+                            int do_record, int advance, hipStream_t s);
 
 // fix16 path (kernels_fix16.hip).
 hipError_t launch_fix16_init(const DevBatch &b, int max_n, hipStream_t s);
@@ -52,18 +54,20 @@ hipError_t launch_fix16_observe(const DevBatch &b, double *out_by_T, hipStream_t
 size_t fix16_lds_bytes(int n_pad, int trig, int mode);
 
 // fix16 phase form (site-major state, one launch per colour phase) for the
-// samples listed in phase_samples[n_phase]; sites_per_block(R) sites per block.
+// samples listed in phase_samples; sites_per_block(R) sites per block.
 int fix16_phase_sites_per_block(int R);
-// units: the n_units (sample, phase-sample index, block, 0) work units of this colour;
-// max_blocks: stride of the energy partials (the largest block count of any
-// colour); last: fuse the energy.
+// units: the n_units work units (two int4 each, see k_fix16_phase) of this
+// colour; max_blocks: stride of the energy partials (the largest block count
+// of any colour); last: fuse the energy; grp: the control block b.ctl[grp]
+// whose sweep counter keys the random words.
 hipError_t launch_fix16_phase(const DevBatch &b, const int4 *units, int colour, int sub,
-                              int last, int n_units, int max_blocks, hipStream_t s);
-hipError_t launch_fix16_phase_energy(const DevBatch &b, const int32_t *phase_samples, int n_phase, int max_blocks,
-                                     hipStream_t s);
-// Energies (and, when full, observables) of the phase-form samples: two
-// deterministic stages through b.partial.
-hipError_t launch_fix16_observe_sm(const DevBatch &b, const int32_t *phase_samples, int n_phase, int full,
-                                   hipStream_t s);
+                              int last, int n_units, int max_blocks, int grp, hipStream_t s);
+// phase samples [k_first, k_first + n_phase) of the list
+hipError_t launch_fix16_phase_energy(const DevBatch &b, const int32_t *phase_samples, int k_first, int n_phase,
+                                     int max_blocks, hipStream_t s);
+// Energies (and, when full, observables) of phase samples [k_first,
+// k_first + n_phase): two deterministic stages through b.partial.
+hipError_t launch_fix16_observe_sm(const DevBatch &b, const int32_t *phase_samples, int k_first, int n_phase,
+                                   int full, hipStream_t s);
 
 }  // namespace xy

@@ -357,11 +357,11 @@ __global__ __launch_bounds__(kObsBlock) void k_fix16_observe(DevBatch b, double 
 constexpr int kPhaseEnergyBlock = 1024;
 
 __global__ __launch_bounds__(kPhaseEnergyBlock) void k_fix16_phase_energy(DevBatch b, const int32_t *phase_samples,
-                                                                          int max_blocks)
+                                                                          int k_first, int max_blocks)
 {
     __shared__ double red[kPhaseEnergyBlock];
     const int R = b.R, S = kPhaseBlock / (R >> 2), P = kPhaseEnergyBlock / R;   // R <= 256, so P >= 4
-    const int k = blockIdx.x, s = phase_samples[k];
+    const int k = k_first + (int)blockIdx.x, s = phase_samples[k];
     const SampleDesc &d = b.desc[s];
     const int t = threadIdx.x, part = t / R, slot = t % R;
     double e = 0.0;
@@ -399,11 +399,11 @@ constexpr int kObsBlocks = 64;
 
 template <typename Idx>
 __global__ __launch_bounds__(kObsBlock) void k_fix16_observe_sm_partial(DevBatch b, const int32_t *phase_samples,
-                                                                       int full)
+                                                                       int k_first, int full)
 {
     __shared__ double red[kObsBlock * 4];
     __shared__ double2 t64[512];          // the FP64 two-level (cos, sin) table
-    const int s = phase_samples[blockIdx.y], R = b.R, Lq = R >> 2;
+    const int kk = k_first + (int)blockIdx.y, s = phase_samples[kk], R = b.R, Lq = R >> 2;
     const SampleDesc &d = b.desc[s];
     for (int k = threadIdx.x; k < 512; k += kObsBlock) t64[k] = b.tab64[k];
     __syncthreads();
@@ -488,19 +488,19 @@ __global__ __launch_bounds__(kObsBlock) void k_fix16_observe_sm_partial(DevBatch
             const int qd = t >> 2, r = t & 3;
             double acc = 0.0;
             for (int k = 0; k < S; ++k) acc += red[(k * Lq + qd) * 4 + r];
-            b.partial[(((int64_t)blockIdx.y * kObsBlocks + blockIdx.x) * R + t) * kNRed + qq] = acc;
+            b.partial[(((int64_t)kk * kObsBlocks + blockIdx.x) * R + t) * kNRed + qq] = acc;
         }
         __syncthreads();
     }
 }
 
 __global__ __launch_bounds__(kObsBlock) void k_fix16_observe_sm_final(DevBatch b, const int32_t *phase_samples,
-                                                                     int n_phase, int full)
+                                                                     int k_first, int n_phase, int full)
 {
     const int R = b.R;
     const int64_t t = (int64_t)blockIdx.x * kObsBlock + threadIdx.x;
     if (t >= (int64_t)n_phase * R) return;
-    const int k = (int)(t / R), slot = (int)(t % R), s = phase_samples[k];
+    const int k = k_first + (int)(t / R), slot = (int)(t % R), s = phase_samples[k];
     const SampleDesc &d = b.desc[s];
     double v[kNRed];
     for (int qq = 0; qq < kNRed; ++qq) v[qq] = 0.0;
@@ -582,29 +582,31 @@ hipError_t launch_fix16_sweep(const DevBatch &b, const Item *items, int n_items,
 }
 
 
-hipError_t launch_fix16_phase_energy(const DevBatch &b, const int32_t *phase_samples, int n_phase, int max_blocks,
-                                     hipStream_t s)
+hipError_t launch_fix16_phase_energy(const DevBatch &b, const int32_t *phase_samples, int k_first, int n_phase,
+                                     int max_blocks, hipStream_t s)
 {
     if (n_phase == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fix16_phase_energy, dim3((unsigned)n_phase), dim3(kPhaseEnergyBlock), 0, s, b, phase_samples,
-                       max_blocks);
+                       k_first, max_blocks);
     return hipGetLastError();
 }
 
-hipError_t launch_fix16_observe_sm(const DevBatch &b, const int32_t *phase_samples, int n_phase, int full,
-                                   hipStream_t s)
+hipError_t launch_fix16_observe_sm(const DevBatch &b, const int32_t *phase_samples, int k_first, int n_phase,
+                                   int full, hipStream_t s)
 {
     if (n_phase == 0) return hipSuccess;
     dim3 grid(kObsBlocks, (unsigned)n_phase);
     if (b.idx16)
-        hipLaunchKernelGGL(k_fix16_observe_sm_partial<uint16_t>, grid, dim3(kObsBlock), 0, s, b, phase_samples, full);
+        hipLaunchKernelGGL(k_fix16_observe_sm_partial<uint16_t>, grid, dim3(kObsBlock), 0, s, b, phase_samples, k_first,
+                           full);
     else
-        hipLaunchKernelGGL(k_fix16_observe_sm_partial<int32_t>, grid, dim3(kObsBlock), 0, s, b, phase_samples, full);
+        hipLaunchKernelGGL(k_fix16_observe_sm_partial<int32_t>, grid, dim3(kObsBlock), 0, s, b, phase_samples, k_first,
+                           full);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t n = (int64_t)n_phase * b.R;
     hipLaunchKernelGGL(k_fix16_observe_sm_final, dim3((unsigned)((n + kObsBlock - 1) / kObsBlock)), dim3(kObsBlock),
-                       0, s, b, phase_samples, n_phase, full);
+                       0, s, b, phase_samples, k_first, n_phase, full);
     return hipGetLastError();
 }
 

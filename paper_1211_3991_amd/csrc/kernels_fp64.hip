@@ -187,8 +187,9 @@ __global__ __launch_bounds__(kBlock) void k_fp64_observe_final(DevBatch b, int f
     for (int q = 0; q < XY_NOBS; ++q) dst[q] = o[q];
 }
 
-// End of a sweep, one block for the whole batch (so the sweep counter is
-// advanced only after every sample has read it):
+// End of a sweep for a list of samples (all when NULL), one block, so that
+// the sweep counter of control block grp is advanced only after every one of
+// them has read it:
 //  - parallel tempering (App. B; Hukushima-Nemoto): pairs (k, k+1) with
 //    k = sweep mod 2, +2, ...; the temperature labels of the two slots are
 //    swapped with probability min(1, exp((beta_k - beta_{k+1})(E_k - E_{k+1})));
@@ -198,14 +199,16 @@ __global__ __launch_bounds__(kBlock) void k_fp64_observe_final(DevBatch b, int f
 //  - sweep counter (and record counter) advance.
 constexpr int kEndBlock = 1024;
 
-__global__ __launch_bounds__(kEndBlock) void k_end_sweep(DevBatch b, int do_pt, int do_record, int advance)
+__global__ __launch_bounds__(kEndBlock) void k_end_sweep(DevBatch b, const int32_t *samples, int n_samples, int grp,
+                                                        int do_pt, int do_record, int advance)
 {
-    const uint32_t sweep = b.ctl->sweep;
-    const uint32_t rec = b.ctl->n_records;
-    const int R = b.R, GR = b.G * R;
+    Ctl *ctl = b.ctl + grp;
+    const uint32_t sweep = ctl->sweep;
+    const uint32_t rec = ctl->n_records;
+    const int R = b.R, n = samples ? n_samples : b.G;
     if (do_pt) {
-        for (int t = threadIdx.x; t < GR; t += kEndBlock) {
-            const int s = t / R, k = t - s * R;
+        for (int t = threadIdx.x; t < n * R; t += kEndBlock) {
+            const int j = t / R, k = t - j * R, s = samples ? samples[j] : j;
             if (((k ^ (int)sweep) & 1) || k + 1 >= R) continue;
             int32_t *sot = b.slot_of_T + s * R;
             int32_t *tos = b.T_of_slot + s * R;
@@ -215,27 +218,27 @@ __global__ __launch_bounds__(kEndBlock) void k_end_sweep(DevBatch b, int do_pt, 
             const double delta = (beta[k] - beta[k + 1]) * (E[lo] - E[hi]);
             const U4 w = draw(b.desc[s], (uint32_t)k, sweep, 0u, tag(kPT));
             const bool accept = delta >= 0.0 || unit53(w.x, w.y) < exp(delta);
-            b.pt_try[t] += 1;
+            b.pt_try[s * R + k] += 1;
             if (accept) {
                 sot[k] = hi; sot[k + 1] = lo;
                 tos[hi] = k; tos[lo] = k + 1;
-                b.pt_acc[t] += 1;
+                b.pt_acc[s * R + k] += 1;
             }
         }
     }
     __syncthreads();                                   // the swapped labels, before the record
     if (do_record && rec < (uint32_t)b.max_records) {
-        for (int t = threadIdx.x; t < GR; t += kEndBlock) {
-            const int s = t / R;                       // t = s R + temperature index
-            const double *src = b.obs_slot + ((int64_t)s * R + b.slot_of_T[t]) * XY_NOBS;
-            double *dst = b.records + ((int64_t)rec * GR + t) * XY_NOBS;
+        for (int t = threadIdx.x; t < n * R; t += kEndBlock) {
+            const int j = t / R, k = t - j * R, s = samples ? samples[j] : j;
+            const double *src = b.obs_slot + ((int64_t)s * R + b.slot_of_T[s * R + k]) * XY_NOBS;
+            double *dst = b.records + (((int64_t)rec * b.G + s) * R + k) * XY_NOBS;
             for (int q = 0; q < XY_NOBS; ++q) dst[q] = src[q];
         }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        if (advance) b.ctl->sweep = sweep + 1;
-        if (do_record) b.ctl->n_records = rec + 1;
+        if (advance) ctl->sweep = sweep + 1;
+        if (do_record) ctl->n_records = rec + 1;
     }
 }
 
@@ -269,9 +272,11 @@ hipError_t launch_fp64_observe(const DevBatch &b, int full, double *out_by_T, hi
     return hipGetLastError();
 }
 
-hipError_t launch_end_sweep(const DevBatch &b, int do_pt, int do_record, int advance, hipStream_t s)
+hipError_t launch_end_sweep(const DevBatch &b, const int32_t *samples, int n_samples, int grp, int do_pt,
+                            int do_record, int advance, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_end_sweep, dim3(1), dim3(kEndBlock), 0, s, b, do_pt, do_record, advance);
+    hipLaunchKernelGGL(k_end_sweep, dim3(1), dim3(kEndBlock), 0, s, b, samples, n_samples, grp, do_pt, do_record,
+                       advance);
     return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ __device__ __forceinline__ int xcd_contiguous(int lin, int n)
 
 template <typename Idx, bool kLast>
 __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const int4 *units, int colour, int sub,
-                                                            int max_blocks)
+                                                            int max_blocks, int grp)
 {
     __shared__ float esum[kLast ? kPhaseBlock * 4 : 1];
     const int R = b.R, Lq = R >> 2, S = kPhaseBlock / Lq;
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
             add(word(j), j, false);
         }
     }
-    const uint32_t sweep = b.ctl->sweep;
+    const uint32_t sweep = b.ctl[grp].sweep;
     const U4 w = philox4x32_10({(uint32_t)i, sweep, (uint32_t)(4 * q), tag(sub == 0 ? kMet : kOR, (uint32_t)sub)},
                                d.seed_lo, d.seed_hi);
     const uint32_t words[4] = {w.x, w.y, w.z, w.w};
@@ -156,12 +156,12 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
 int fix16_phase_sites_per_block(int R) { return kPhaseBlock / (R / 4); }
 
 hipError_t launch_fix16_phase(const DevBatch &b, const int4 *units, int colour, int sub,
-                              int last, int n_units, int max_blocks, hipStream_t s)
+                              int last, int n_units, int max_blocks, int grp, hipStream_t s)
 {
     if (n_units == 0) return hipSuccess;
     auto k = b.idx16 ? (last ? k_fix16_phase<uint16_t, true> : k_fix16_phase<uint16_t, false>)
                      : (last ? k_fix16_phase<int32_t, true> : k_fix16_phase<int32_t, false>);
-    hipLaunchKernelGGL(k, dim3((unsigned)n_units), dim3(kPhaseBlock), 0, s, b, units, colour, sub, max_blocks);
+    hipLaunchKernelGGL(k, dim3((unsigned)n_units), dim3(kPhaseBlock), 0, s, b, units, colour, sub, max_blocks, grp);
     return hipGetLastError();
 }
 

@@ -43,6 +43,12 @@ struct xy_batch {
     hipEvent_t ev_fork = nullptr;
     std::vector<hipEvent_t> ev_join;          // per auxiliary stream
     std::vector<int> phase_bounds;            // [colour][group + 1]: first unit of each group
+    std::vector<int> group_first;             // [group + 1]: first phase sample of each group
+    // every sample in the phase form: each group also runs its own energies,
+    // tempering and records with its own control block b.ctl[g], so the
+    // groups fork once per xy_sweep call and join at its end
+    bool indep = false;
+    std::vector<int> event_sweeps;            // sweeps covered by each timing event pair
     size_t item_cap = 0;
     Item *d_items = nullptr;
     int lds_limit = 0;
@@ -177,7 +183,7 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
     WorkLayout &wl = p.wl;
     const size_t GR = (size_t)G * R;
     off = 0;
-    wl.ctl = off;       off = align_up(off + sizeof(Ctl), 256);
+    wl.ctl = off;       off = align_up(off + sizeof(Ctl) * kMaxPhaseStreams, 256);
     wl.beta = off;      off = align_up(off + 8 * GR, 256);
     wl.slot_of_T = off; off = align_up(off + 4 * GR, 256);
     wl.T_of_slot = off; off = align_up(off + 4 * GR, 256);
@@ -455,7 +461,8 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
             // work units, group 0 on the caller's stream and the others on
             // auxiliary streams (XY_PHASE_STREAMS=1..4, default 2)
             int n_streams = 2;
-            if (const char *env = std::getenv("XY_PHASE_STREAMS")) n_streams = std::min(4, std::max(1, std::atoi(env)));
+            if (const char *env = std::getenv("XY_PHASE_STREAMS"))
+                n_streams = std::min(kMaxPhaseStreams, std::max(1, std::atoi(env)));
             n_streams = std::max(1, std::min(n_streams, (int)phase.size()));
             std::vector<size_t> first_sample(n_streams + 1, phase.size());   // group g: [first[g], first[g+1])
             first_sample[0] = 0;
@@ -484,6 +491,8 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
                     bd[g] = n;
                 }
             }
+            b->group_first.assign(first_sample.begin(), first_sample.end());
+            b->indep = n_streams > 1 && (int)phase.size() == G;
             if (n_streams > 1) {
                 hipError_t e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
                 for (int g = 1; g < n_streams && e == hipSuccess; ++g) {
@@ -594,54 +603,90 @@ hipError_t next_events(xy_batch *b, hipEvent_t *start, hipEvent_t *stop)
     return hipSuccess;
 }
 
-// Enqueues one sweep with the given flags.
+// Forks the auxiliary streams of the phase form from s, and joins them back.
+hipError_t fork_groups(xy_batch *b, hipStream_t s)
+{
+    hipError_t e = hipEventRecord(b->ev_fork, s);
+    for (size_t g = 0; g < b->aux.size() && e == hipSuccess; ++g) e = hipStreamWaitEvent(b->aux[g], b->ev_fork, 0);
+    return e;
+}
+
+hipError_t join_groups(xy_batch *b, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    for (size_t g = 0; g < b->aux.size() && e == hipSuccess; ++g) {
+        e = hipEventRecord(b->ev_join[g], b->aux[g]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, b->ev_join[g], 0);
+    }
+    return e;
+}
+
+// Enqueues one sweep with the given flags.  With independent groups the
+// caller has forked them (fork_groups) and joins them after its last sweep.
 hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream_t s)
 {
     hipError_t e = hipSuccess;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (b->timing) {
+    if (b->timing && !b->indep) {
         e = next_events(b, &ev0, &ev1);
         if (e == hipSuccess) e = hipEventRecord(ev0, s);
         if (e != hipSuccess) return e;
+        b->event_sweeps.push_back(1);
         b->timed_stream = s;
     }
+    const int n_st = 1 + (int)b->aux.size();
     if (b->precision == XY_FP64) {
         for (int sub = 0; sub <= n_or && e == hipSuccess; ++sub)
             for (int c = 0; c < b->Qmax && e == hipSuccess; ++c)
                 e = launch_fp64_phase(b->dev, c, sub == 0, b->max_class[c], s);
         if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
         if (e == hipSuccess && (do_pt || do_rec)) e = launch_fp64_observe(b->dev, do_rec, nullptr, s);
+    } else if (b->indep) {
+        // each group: its colour phases, then its energies, tempering,
+        // records and sweep counter, all on its own stream
+        for (int sub = 0; sub <= n_or && e == hipSuccess; ++sub)
+            for (int c = 0; c < (int)b->phase_units.size() && e == hipSuccess; ++c) {
+                const int *bd = b->phase_bounds.data() + (size_t)c * (n_st + 1);
+                const int4 *u = b->d_units + b->phase_unit_off[c];
+                for (int g = 0; g < n_st && e == hipSuccess; ++g)
+                    e = launch_fix16_phase(b->dev, u + 2 * (size_t)bd[g], c, sub, sub == n_or, bd[g + 1] - bd[g],
+                                           b->phase_stride, g, g == 0 ? s : b->aux[g - 1]);
+            }
+        for (int g = 0; g < n_st && e == hipSuccess; ++g) {
+            hipStream_t st = g == 0 ? s : b->aux[g - 1];
+            const int k0 = b->group_first[g], nk = b->group_first[g + 1] - k0;
+            if (do_rec) e = launch_fix16_observe_sm(b->dev, b->d_phase, k0, nk, 1, st);
+            if (e == hipSuccess && do_pt) e = launch_fix16_phase_energy(b->dev, b->d_phase, k0, nk, b->phase_stride, st);
+            if (e == hipSuccess) e = launch_end_sweep(b->dev, b->d_phase + k0, nk, g, do_pt, do_rec, 1, st);
+        }
+        return e;
     } else {
         for (const auto &grp : b->groups) {
             e = launch_fix16_sweep(b->dev, grp.items, grp.n_items, grp.mode, grp.block, n_or, do_rec, grp.lds, s);
             if (e != hipSuccess) break;
         }
-        const int n_st = 1 + (int)b->aux.size();
         const bool fork = b->n_phase > 0 && n_st > 1;
-        if (e == hipSuccess && fork) e = hipEventRecord(b->ev_fork, s);
-        for (int g = 1; g < n_st && fork && e == hipSuccess; ++g) e = hipStreamWaitEvent(b->aux[g - 1], b->ev_fork, 0);
+        if (e == hipSuccess && fork) e = fork_groups(b, s);
         for (int sub = 0; sub <= n_or && e == hipSuccess && b->n_phase > 0; ++sub)
             for (int c = 0; c < (int)b->phase_units.size() && e == hipSuccess; ++c) {
                 const int *bd = b->phase_bounds.data() + (size_t)c * (n_st + 1);
                 const int4 *u = b->d_units + b->phase_unit_off[c];
                 for (int g = 0; g < n_st && e == hipSuccess; ++g)
                     e = launch_fix16_phase(b->dev, u + 2 * (size_t)bd[g], c, sub, sub == n_or, bd[g + 1] - bd[g],
-                                           b->phase_stride, g == 0 ? s : b->aux[g - 1]);
+                                           b->phase_stride, 0, g == 0 ? s : b->aux[g - 1]);
             }
-        for (int g = 1; g < n_st && fork && e == hipSuccess; ++g) {
-            e = hipEventRecord(b->ev_join[g - 1], b->aux[g - 1]);
-            if (e == hipSuccess) e = hipStreamWaitEvent(s, b->ev_join[g - 1], 0);
-        }
+        if (e == hipSuccess && fork) e = join_groups(b, s);
         // the timed part: the sweep kernels (with their fused energies) and the
         // colour-phase kernels of the phase form
         if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
         if (e == hipSuccess && b->n_phase > 0) {
-            if (do_rec) e = launch_fix16_observe_sm(b->dev, b->d_phase, b->n_phase, 1, s);
+            if (do_rec) e = launch_fix16_observe_sm(b->dev, b->d_phase, 0, b->n_phase, 1, s);
             // E_slot for tempering: the FP32-form energies fused in the last sub-sweep
-            if (e == hipSuccess && do_pt) e = launch_fix16_phase_energy(b->dev, b->d_phase, b->n_phase, b->phase_stride, s);
+            if (e == hipSuccess && do_pt)
+                e = launch_fix16_phase_energy(b->dev, b->d_phase, 0, b->n_phase, b->phase_stride, s);
         }
     }
-    if (e == hipSuccess) e = launch_end_sweep(b->dev, do_pt, do_rec, 1, s);
+    if (e == hipSuccess) e = launch_end_sweep(b->dev, nullptr, 0, 0, do_pt, do_rec, 1, s);
     return e;
 }
 
@@ -671,8 +716,10 @@ extern "C" xy_status xy_sweep(xy_batch *b, int n_sweeps, int n_or, int pt_every,
                 hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
                 if (e != hipSuccess) return hip_err(e, "xy_sweep capture");
                 uint32_t sw = b->host_sweep;
+                if (b->indep) e = fork_groups(b, s);
                 for (int k = 0; k < b->chunk && e == hipSuccess; ++k, ++sw)
                     e = enqueue_sweep(b, n_or, flag_at(sw, pt_every), flag_at(sw, meas_every), s);
+                if (b->indep && e == hipSuccess) e = join_groups(b, s);
                 hipError_t e2 = hipStreamEndCapture(s, &graph);
                 if (e == hipSuccess) e = e2;
                 if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
@@ -687,13 +734,32 @@ extern "C" xy_status xy_sweep(xy_batch *b, int n_sweeps, int n_or, int pt_every,
             done += b->chunk;
         }
     }
-    for (; done < n_sweeps; ++done) {
-        const uint32_t sw = b->host_sweep;
-        const hipError_t e = enqueue_sweep(b, n_or, flag_at(sw, pt_every), flag_at(sw, meas_every), s);
+    if (done == n_sweeps) return XY_OK;
+    // independent groups: one fork and one join for the remaining sweeps,
+    // timed as a whole (the colour phases and the per-group tails)
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipError_t e = hipSuccess;
+    if (b->indep) {
+        if (b->timing) {
+            e = next_events(b, &ev0, &ev1);
+            if (e == hipSuccess) e = hipEventRecord(ev0, s);
+            b->event_sweeps.push_back(n_sweeps - done);
+            b->timed_stream = s;
+        }
+        if (e == hipSuccess) e = fork_groups(b, s);
         if (e != hipSuccess) return hip_err(e, "xy_sweep");
-        b->host_sweep++;
     }
-    return XY_OK;
+    for (; done < n_sweeps && e == hipSuccess; ++done) {
+        const uint32_t sw = b->host_sweep;
+        e = enqueue_sweep(b, n_or, flag_at(sw, pt_every), flag_at(sw, meas_every), s);
+        if (e == hipSuccess) b->host_sweep++;
+    }
+    if (b->indep) {
+        const hipError_t e2 = join_groups(b, s);   // also after a failed launch: leave no stream forked
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
+    }
+    return e == hipSuccess ? XY_OK : hip_err(e, "xy_sweep");
 }
 
 extern "C" xy_status xy_batch_use_graph(xy_batch *b, int chunk)
@@ -727,7 +793,7 @@ extern "C" xy_status xy_pt_swap(xy_batch *b, void *stream)
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = (b->precision == XY_FP64) ? launch_fp64_observe(b->dev, 0, nullptr, s)
                                              : launch_fix16_observe(b->dev, nullptr, s);
-    if (e == hipSuccess) e = launch_end_sweep(b->dev, 1, 0, 0, s);
+    if (e == hipSuccess) e = launch_end_sweep(b->dev, nullptr, 0, 0, 1, 0, 0, s);
     return e == hipSuccess ? XY_OK : hip_err(e, "xy_pt_swap");
 }
 
@@ -833,7 +899,8 @@ extern "C" xy_status xy_set_state(xy_batch *b, const void *h_state, const int32_
             e = hipMemcpyAsync(b->dev.slot_of_T, sot.data(), sot.size() * 4, hipMemcpyHostToDevice, s);
             if (e == hipSuccess) e = hipMemcpyAsync(b->dev.T_of_slot, tos.data(), tos.size() * 4, hipMemcpyHostToDevice, s);
         }
-        if (e == hipSuccess) e = hipMemcpyAsync(&b->dev.ctl->sweep, &sweep, 4, hipMemcpyHostToDevice, s);
+        for (int g = 0; g < kMaxPhaseStreams && e == hipSuccess; ++g)
+            e = hipMemcpyAsync(&b->dev.ctl[g].sweep, &sweep, 4, hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_err(e, "xy_set_state");
         b->host_sweep = sweep;
@@ -884,6 +951,7 @@ extern "C" xy_status xy_kernel_timing(xy_batch *b, int enable)
     }
     b->timing = enable != 0;
     b->events_used = 0;
+    b->event_sweeps.clear();
     return XY_OK;
 }
 
@@ -900,8 +968,10 @@ extern "C" xy_status xy_kernel_time(xy_batch *b, double *ms_total, int *n_timed)
         }
         if (e != hipSuccess) return hip_err(e, "xy_kernel_time");
     }
+    int n = 0;
+    for (size_t k = 0; k < b->events_used && k < b->event_sweeps.size(); ++k) n += b->event_sweeps[k];
     if (ms_total) *ms_total = total;
-    if (n_timed) *n_timed = (int)b->events_used;
+    if (n_timed) *n_timed = n;
     return XY_OK;
 }
 

@@ -84,6 +84,7 @@ struct xy_graph {
 namespace xy {
 
 constexpr int kMaxColours = 31;
+constexpr int kMaxPhaseStreams = 4;   // stream groups of the phase form, each with its own control block
 constexpr int kMaxT = 256;
 
 xy_status set_error(xy_status code, const std::string &msg);

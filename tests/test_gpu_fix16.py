@@ -353,6 +353,36 @@ def test_tempering_energies_equal_state_energy(streams, monkeypatch):
             assert abs(E[k, slot] - ref) <= 1e-5 * abs(ref), (k, slot, E[k, slot], ref)
 
 
+def test_stream_groups_give_identical_trajectories(monkeypatch):
+    """The phase form in one, two or three stream groups (with two or more,
+    and every sample in the phase form, each group runs its own energies,
+    tempering, records and sweep counter; once also replayed from a captured
+    HIP graph) updates every site in the same order with the same random
+    words: states, temperature labels, records and tempering counters are
+    identical."""
+    graphs = [xy.Graph.levy(128, 6, 3.5, s) for s in range(5)]
+    T = workloads.linear_ladder(1.0, 2.5, 8)
+    runs = []
+    for streams, chunk in (("1", 0), ("2", 0), ("3", 0), ("2", 4)):
+        monkeypatch.setenv("XY_PHASE_STREAMS", streams)
+        b = xy.Batch(graphs, T, precision="fix16", seeds=np.arange(5) + 60, max_records=8, stream=torch.cuda.Stream())
+        assert b.forms().all()
+        if chunk:
+            b.use_graph(chunk)
+        b.sweep(12, pt_every=1, meas_every=4)
+        b.synchronize()
+        st, sot, sw = b.get_state()
+        nrec, acc, tries = b.counters()
+        runs.append((st, sot, sw, b.records().cpu().numpy(), acc, tries, nrec, b.pt_energies().cpu().numpy()))
+        b.close()
+    ref = runs[0]
+    assert ref[2] == 12 and ref[6] == 3 and ref[5].sum() > 0
+    for r in runs[1:]:
+        assert all(np.array_equal(x, y) for x, y in zip(r[0], ref[0]))
+        for k in range(1, 8):
+            assert np.array_equal(r[k], ref[k]), k
+
+
 def test_phase_form_state_roundtrip_and_resume(monkeypatch):
     monkeypatch.setenv("XY_FIX16_PHASE", "1")
     graphs = [xy.Graph.levy(16, 6, 3.5, 1), xy.Graph.levy(32, 6, 2.5, 2)]
