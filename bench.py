@@ -135,9 +135,11 @@ def write_traffic(wl, paths, argv):
 
     def per_sweep(rows, counter, n_last=4):
         # counter summed over the dominant kernel's dispatches of each sweep
-        # (k_end_sweep ends one); the mean of the last n_last sweeps, which
-        # all ran the tuned form
-        sums, cur, names, n_disp = [], 0.0, set(), 0
+        # (a k_end_sweep after them ends one; with independent stream groups
+        # every group ends its sweep with its own k_end_sweep, and the
+        # dispatches are in enqueue order, so the later ones close nothing);
+        # the mean of the last n_last sweeps, which all ran the tuned form
+        sums, cur, names, n_disp, n_cur = [], 0.0, set(), 0, 0
         for r in rows:
             if r["Counter_Name"] != counter:
                 continue
@@ -145,9 +147,10 @@ def write_traffic(wl, paths, argv):
                 cur += float(r["Counter_Value"])
                 names.add(r["Kernel_Name"])
                 n_disp += 1
-            elif "k_end_sweep" in r["Kernel_Name"]:
+                n_cur += 1
+            elif "k_end_sweep" in r["Kernel_Name"] and n_cur:
                 sums.append(cur)
-                cur = 0.0
+                cur, n_cur = 0.0, 0
         last = sums[-n_last:]
         return sorted(names), sum(last) / len(last), n_disp / max(len(sums), 1)
 
@@ -299,7 +302,8 @@ def main():
         kname = "k_fp64_phase (the 6·Q colour-phase launches of one sweep)"
     elif uses_phase_form(wl):
         kname = ("k_fix16_phase (the colour-phase launches of one sweep: 6·Q per sample group, two groups on "
-                 "two streams; timed by HIP events on the caller's stream around the fork, the launches and the join)")
+                 "two streams, each group also running its own energies and tempering; timed by HIP events on the "
+                 "caller's stream around the fork, all sweeps of the call and the join, per sweep)")
     else:
         kname = "k_fix16_sweep (one launch = one sweep of every (sample, slot))"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
