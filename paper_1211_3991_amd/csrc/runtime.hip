@@ -661,12 +661,14 @@ hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream
         }
         return e;
     } else {
-        for (const auto &grp : b->groups) {
-            e = launch_fix16_sweep(b->dev, grp.items, grp.n_items, grp.mode, grp.block, n_or, do_rec, grp.lds, s);
-            if (e != hipSuccess) break;
-        }
+        // the workgroup-form samples on the caller's stream, after the fork,
+        // so that the other groups' colour phases overlap them
         const bool fork = b->n_phase > 0 && n_st > 1;
         if (e == hipSuccess && fork) e = fork_groups(b, s);
+        for (const auto &grp : b->groups) {
+            if (e != hipSuccess) break;
+            e = launch_fix16_sweep(b->dev, grp.items, grp.n_items, grp.mode, grp.block, n_or, do_rec, grp.lds, s);
+        }
         for (int sub = 0; sub <= n_or && e == hipSuccess && b->n_phase > 0; ++sub)
             for (int c = 0; c < (int)b->phase_units.size() && e == hipSuccess; ++c) {
                 const int *bd = b->phase_bounds.data() + (size_t)c * (n_st + 1);

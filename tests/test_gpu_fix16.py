@@ -353,20 +353,25 @@ def test_tempering_energies_equal_state_energy(streams, monkeypatch):
             assert abs(E[k, slot] - ref) <= 1e-5 * abs(ref), (k, slot, E[k, slot], ref)
 
 
-def test_stream_groups_give_identical_trajectories(monkeypatch):
-    """The phase form in one, two or three stream groups (with two or more,
-    and every sample in the phase form, each group runs its own energies,
-    tempering, records and sweep counter; once also replayed from a captured
-    HIP graph) updates every site in the same order with the same random
-    words: states, temperature labels, records and tempering counters are
-    identical."""
+@pytest.mark.parametrize("mixed", [False, True])
+def test_stream_groups_give_identical_trajectories(mixed, monkeypatch):
+    """The phase form in one, two or three stream groups updates every site in
+    the same order with the same random words: states, temperature labels,
+    records and tempering counters are identical.  With every sample in the
+    phase form and two or more groups, each group runs its own energies,
+    tempering, records and sweep counter (once also replayed from a captured
+    HIP graph); in a batch that also holds workgroup-form samples the groups
+    join every sweep."""
     graphs = [xy.Graph.levy(128, 6, 3.5, s) for s in range(5)]
+    if mixed:
+        graphs += [xy.Graph.levy(32, 6, 2.5, 11), xy.Graph.levy(16, 6, 3.5, 12)]
+    G = len(graphs)
     T = workloads.linear_ladder(1.0, 2.5, 8)
     runs = []
     for streams, chunk in (("1", 0), ("2", 0), ("3", 0), ("2", 4)):
         monkeypatch.setenv("XY_PHASE_STREAMS", streams)
-        b = xy.Batch(graphs, T, precision="fix16", seeds=np.arange(5) + 60, max_records=8, stream=torch.cuda.Stream())
-        assert b.forms().all()
+        b = xy.Batch(graphs, T, precision="fix16", seeds=np.arange(G) + 60, max_records=8, stream=torch.cuda.Stream())
+        assert list(b.forms()) == [1] * 5 + [0] * (G - 5)
         if chunk:
             b.use_graph(chunk)
         b.sweep(12, pt_every=1, meas_every=4)
