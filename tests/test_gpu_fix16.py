@@ -330,16 +330,17 @@ def test_phase_form_pt_batch_matches_fp64_gpu(monkeypatch):
     assert np.max(np.abs(np.array(zs))) < 4.0, zs
 
 
-@pytest.mark.parametrize("streams", ["1", "2", "3"])
-def test_tempering_energies_equal_state_energy(streams, monkeypatch):
+@pytest.mark.parametrize("streams,n_T", [("1", 8), ("2", 8), ("3", 8), ("2", 4), ("2", 12), ("2", 24)])
+def test_tempering_energies_equal_state_energy(streams, n_T, monkeypatch):
     """The replica energies the tempering step uses (summed in the last
     sub-sweep over the links to lower colours) equal
     -sum_links cos(theta_i - theta_j) of the state, in FP64 from the exported
     links: phase form with its samples in one to three stream groups, and a
-    workgroup-form sample."""
+    workgroup-form sample.  4, 8 and 12 temperatures put more than 64 sites in
+    a block (blocks spanning three to five chunks); 24 is the headline's."""
     monkeypatch.setenv("XY_PHASE_STREAMS", streams)
     graphs = [xy.Graph.levy(128, 6, 3.5, s) for s in range(5)] + [xy.Graph.levy(32, 6, 2.5, 7)]
-    T = workloads.linear_ladder(1.0, 2.5, 8)
+    T = workloads.linear_ladder(1.0, 2.5, n_T)
     b = xy.Batch(graphs, T, precision="fix16", seeds=np.arange(6) + 40)
     assert list(b.forms()) == [1, 1, 1, 1, 1, 0]
     b.sweep(7, pt_every=1, meas_every=0)
