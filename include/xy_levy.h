@@ -218,6 +218,18 @@ xy_status xy_batch_use_graph(xy_batch *b, int chunk);
 xy_status xy_kernel_timing(xy_batch *b, int enable);
 xy_status xy_kernel_time(xy_batch *b, double *ms_total, int *n_timed);
 
+/* Stream groups of the phase form (fix16 batches; used by the autotuner):
+ * the phase-form samples are split into n_streams (1..4) contiguous groups of
+ * about equal work, group 0 launched on the caller's stream and the others on
+ * streams the library owns.  Every group updates its samples exactly as one
+ * group would, so the trajectory does not depend on the choice; only the
+ * overlap of the launches does (App. B's colour phases, here per group).
+ * Initial value 2 (the environment variable XY_PHASE_STREAMS overrides it at
+ * xy_batch_init).  Synchronises `stream` and the library's streams; no effect
+ * on batches without phase-form samples.  XY_EINVAL outside [1, 4]. */
+xy_status xy_batch_set_phase_streams(xy_batch *b, int n_streams, void *stream);
+xy_status xy_batch_phase_streams(const xy_batch *b, int *n_streams);
+
 /* Fixed-point sweep configuration (fix16 batches; used by the autotuner).
  *   trig        : (cos, sin) of a 16-bit angle: 0 two-level LDS table, 1 2048-entry
  *                 LDS table with a small-angle rotation, 2 hardware sine/cosine

@@ -143,6 +143,16 @@ class Batch:
         _lib.call("xy_batch_set_fix16_form", self._h, int(trig), int(bool(allow_unit)), int(bool(force_global)),
                   self._s())
 
+    def set_phase_streams(self, n):
+        """Number of stream groups of the phase-form samples (1..4); the
+        trajectory does not depend on it."""
+        _lib.call("xy_batch_set_phase_streams", self._h, int(n), self._s())
+
+    def phase_streams(self):
+        n = ctypes.c_int()
+        _lib.call("xy_batch_phase_streams", self._h, ctypes.byref(n))
+        return n.value
+
     def forms(self):
         """Storage form per sample: 1 site-major phase form, 0 workgroup per replica."""
         out = np.zeros(self.G, np.int32)

@@ -1,13 +1,15 @@
 """Autotuner of the fixed-point sweep configuration.
 
-The candidates are the (cos, sin) form (hardware sine/cosine, 2048-entry LDS
-table, two-level LDS table) times the storage form (unit vectors in LDS where a
-replica fits, or angles).  Each candidate is timed on the live batch with HIP
-events around the sweep kernel (``xy_kernel_timing``).  Trial sweeps run
-without tempering or records, and the spins, permutations and sweep counter are
-restored afterwards, so tuning does not change the trajectory's inputs.  The
-choice is cached in a JSON file keyed by the GPU architecture and the batch
-shape (the multiset of graph sizes and the number of temperatures).
+For workgroup-form samples the candidates are the (cos, sin) form (hardware
+sine/cosine, 2048-entry LDS table, two-level LDS table) times the storage form
+(unit vectors in LDS where a replica fits, or angles).  For phase-form samples
+the candidate is the number of stream groups (1 to 3), which changes only how
+the colour-phase launches overlap.  Each candidate is timed on the live batch
+with HIP events (``xy_kernel_timing``).  Trial sweeps run without tempering or
+records, and the spins, permutations and sweep counter are restored
+afterwards, so tuning does not change the trajectory's inputs.  The choice is
+cached in a JSON file keyed by the GPU architecture and the batch shape (the
+multiset of graph sizes and the number of temperatures).
 """
 import json
 import os
@@ -38,36 +40,69 @@ def _load(path):
         return {}
 
 
+def _time(batch, sweeps, n_or, saved):
+    batch.sweep(1, n_or=n_or, pt_every=0, meas_every=0)           # first launch of a kernel variant
+    batch.kernel_timing(True)
+    batch.sweep(sweeps, n_or=n_or, pt_every=0, meas_every=0)
+    ms, n = batch.kernel_time()
+    batch.kernel_timing(False)
+    batch.set_state(*saved)
+    return ms / max(n, 1)
+
+
 def autotune(batch, sweeps=3, n_or=5, use_cache=True):
-    """Picks and applies the fastest (trig, allow_unit); returns a report dict."""
+    """Picks and applies the fastest (trig, allow_unit) and stream-group count;
+    returns a report dict."""
     if batch.precision != "fix16":
         return {"tuned": False, "reason": "fp64 batch"}
-    if batch.forms().all():
-        return {"tuned": False, "reason": "every sample is in the phase form, which these choices do not affect"}
+    forms = batch.forms()
+    n_phase = int(forms.sum())
     key = signature(batch)
     path = cache_path()
     cache = _load(path) if use_cache else {}
-    if key in cache:
-        trig, unit = cache[key]["trig"], cache[key]["allow_unit"]
-        batch.set_fix16_form(trig, unit)
-        return {"tuned": True, "cached": True, "trig": trig, "allow_unit": unit, "key": key}
+    if key in cache and "phase_streams" in cache[key]:
+        c = cache[key]
+        if not forms.all():
+            batch.set_fix16_form(c["trig"], c["allow_unit"])
+        batch.set_phase_streams(c["phase_streams"])
+        return {"tuned": True, "cached": True, "trig": c.get("trig"), "allow_unit": c.get("allow_unit"),
+                "phase_streams": c["phase_streams"], "key": key}
     saved = batch.get_state()
-    times = {}
-    for trig, unit in CANDIDATES:
+    rep = {"tuned": True, "cached": False, "key": key}
+    entry = {}
+    if not forms.all():
+        times = {}
+        for trig, unit in CANDIDATES:
+            batch.set_fix16_form(trig, unit)
+            times[(trig, unit)] = _time(batch, sweeps, n_or, saved)
+        (trig, unit), _ = min(times.items(), key=lambda kv: kv[1])
         batch.set_fix16_form(trig, unit)
-        batch.sweep(1, n_or=n_or, pt_every=0, meas_every=0)       # first launch of a kernel variant
-        batch.kernel_timing(True)
-        batch.sweep(sweeps, n_or=n_or, pt_every=0, meas_every=0)
-        ms, n = batch.kernel_time()
-        batch.kernel_timing(False)
-        times[(trig, unit)] = ms / max(n, 1)
-        batch.set_state(*saved)
-    (trig, unit), best = min(times.items(), key=lambda kv: kv[1])
-    batch.set_fix16_form(trig, unit)
-    rep = {"tuned": True, "cached": False, "trig": trig, "allow_unit": unit, "key": key,
-           "ms_per_sweep": {f"trig{t}_unit{u}": round(v, 4) for (t, u), v in times.items()}}
+        rep.update(trig=trig, allow_unit=unit,
+                   ms_per_sweep={f"trig{t}_unit{u}": round(v, 4) for (t, u), v in times.items()})
+        entry.update(trig=trig, allow_unit=unit, ms_per_sweep=rep["ms_per_sweep"])
+    n_best = batch.phase_streams()
+    if n_phase >= 2:
+        # the group counts differ by a few percent: each trial runs about
+        # 40 ms of sweeps (at least 2 x sweeps), twice, keeping the faster
+        probe = _time(batch, sweeps, n_or, saved)
+        n_sw = int(min(256, max(2 * sweeps, 40.0 / max(probe, 1e-3))))
+        # (trials run without tempering, whose per-group tails favour fewer
+        # groups, and the caller's stream plus three others fill the four
+        # hardware queues a process gets by default: one to three groups, and
+        # the fewest within 2% of the fastest)
+        st = {}
+        for n in range(1, min(3, n_phase) + 1):
+            batch.set_phase_streams(n)
+            st[n] = min(_time(batch, n_sw, n_or, saved) for _ in range(2))
+        fastest = min(st.values())
+        n_best = min(n for n, v in st.items() if v <= 1.02 * fastest)
+        rep["phase_streams_ms_per_sweep"] = {str(n): round(v, 4) for n, v in st.items()}
+        entry["phase_streams_ms_per_sweep"] = rep["phase_streams_ms_per_sweep"]
+    batch.set_phase_streams(n_best)
+    rep["phase_streams"] = n_best
+    entry["phase_streams"] = n_best
     if use_cache:
-        cache[key] = {"trig": trig, "allow_unit": unit, "ms_per_sweep": rep["ms_per_sweep"]}
+        cache[key] = entry
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)
             with open(path + ".tmp", "w") as fh:

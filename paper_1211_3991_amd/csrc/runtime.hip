@@ -44,6 +44,7 @@ struct xy_batch {
     std::vector<hipEvent_t> ev_join;          // per auxiliary stream
     std::vector<int> phase_bounds;            // [colour][group + 1]: first unit of each group
     std::vector<int> group_first;             // [group + 1]: first phase sample of each group
+    std::vector<int32_t> unit_k;              // phase index of each work unit, in d_units order
     // every sample in the phase form: each group also runs its own energies,
     // tempering and records with its own control block b.ctl[g], so the
     // groups fork once per xy_sweep call and join at its end
@@ -80,6 +81,61 @@ constexpr int kGroupBlock[kGroups] = {256, 1024, 1024, 512};
 xy_status hip_err(hipError_t e, const char *where)
 {
     return set_error(XY_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Splits the phase samples into n_streams contiguous groups of about equal
+// work units, group 0 on the caller's stream and the others on auxiliary
+// streams created here (the previous ones are released); no work may be in
+// flight on them.
+hipError_t setup_phase_groups(xy_batch *b, int n_streams)
+{
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    for (hipEvent_t ev : b->ev_join) (void)hipEventDestroy(ev);
+    for (hipStream_t st : b->aux) (void)hipStreamDestroy(st);
+    b->ev_fork = nullptr;
+    b->ev_join.clear();
+    b->aux.clear();
+    const int n_ph = b->n_phase, Q = (int)b->phase_units.size();
+    n_streams = std::max(1, std::min({n_streams, kMaxPhaseStreams, std::max(n_ph, 1)}));
+    std::vector<int> first(n_streams + 1, n_ph);   // group g: phase samples [first[g], first[g+1])
+    first[0] = 0;
+    std::vector<size_t> per(std::max(n_ph, 1), 0);
+    for (int32_t k : b->unit_k) ++per[k];
+    size_t total = 0, acc = 0;
+    for (size_t v : per) total += v;
+    int g = 1;
+    for (int k = 0; k < n_ph && g < n_streams; ++k) {
+        acc += per[k];
+        // close group g-1 after sample k once it holds its share, leaving a
+        // sample for each later group
+        if (acc * n_streams >= total * g && n_ph - (k + 1) >= n_streams - g) first[g++] = k + 1;
+    }
+    for (; g < n_streams; ++g) first[g] = std::min(n_ph, first[g - 1] + 1);
+    b->phase_bounds.assign((size_t)Q * (n_streams + 1), 0);
+    for (int c = 0; c < Q; ++c) {
+        int *bd = b->phase_bounds.data() + (size_t)c * (n_streams + 1);
+        const int32_t *uk = b->unit_k.data() + b->phase_unit_off[c] / 2;
+        for (int h = 0; h <= n_streams; ++h) {
+            int n = 0;   // units of colour c whose sample precedes group h
+            for (int a = 0; a < b->phase_units[c]; ++a) n += uk[a] < first[h];
+            bd[h] = n;
+        }
+    }
+    b->group_first = first;
+    b->indep = n_streams > 1 && n_ph == b->G;
+    hipError_t e = hipSuccess;
+    if (n_streams > 1) {
+        e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+        for (int h = 1; h < n_streams && e == hipSuccess; ++h) {
+            hipStream_t st = nullptr;
+            hipEvent_t ev = nullptr;
+            e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+            if (e == hipSuccess) b->aux.push_back(st);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e == hipSuccess) b->ev_join.push_back(ev);
+        }
+    }
+    return e;
 }
 
 struct Plan {
@@ -457,61 +513,20 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
                 delete b;
                 return set_error(XY_EUNSUP, "xy_batch_init: phase-form work units do not match the plan");
             }
-            // the phase samples in n_streams contiguous groups of about equal
-            // work units, group 0 on the caller's stream and the others on
-            // auxiliary streams (XY_PHASE_STREAMS=1..4, default 2)
-            int n_streams = 2;
-            if (const char *env = std::getenv("XY_PHASE_STREAMS"))
-                n_streams = std::min(kMaxPhaseStreams, std::max(1, std::atoi(env)));
-            n_streams = std::max(1, std::min(n_streams, (int)phase.size()));
-            std::vector<size_t> first_sample(n_streams + 1, phase.size());   // group g: [first[g], first[g+1])
-            first_sample[0] = 0;
-            {
-                std::vector<size_t> per(phase.size(), 0);
-                for (size_t a = 1; a < units.size(); a += 2) ++per[units[a].y];
-                size_t total = 0, acc = 0;
-                for (size_t v : per) total += v;
-                int g = 1;
-                for (size_t k = 0; k < per.size() && g < n_streams; ++k) {
-                    acc += per[k];
-                    // close group g-1 after sample k once it holds its share,
-                    // leaving a sample for each later group
-                    if (acc * n_streams >= total * g && per.size() - (k + 1) >= (size_t)(n_streams - g))
-                        first_sample[g++] = k + 1;
-                }
-                for (; g < n_streams; ++g) first_sample[g] = std::min(phase.size(), first_sample[g - 1] + 1);
-            }
-            b->phase_bounds.assign((size_t)p.Qmax * (n_streams + 1), 0);
-            for (int c = 0; c < p.Qmax; ++c) {
-                int *bd = b->phase_bounds.data() + (size_t)c * (n_streams + 1);
-                for (int g = 0; g <= n_streams; ++g) {
-                    int n = 0;   // units of colour c whose sample precedes group g
-                    for (int a = 0; a < b->phase_units[c]; ++a)
-                        if ((size_t)units[b->phase_unit_off[c] + 2 * a + 1].y < first_sample[g]) ++n;
-                    bd[g] = n;
-                }
-            }
-            b->group_first.assign(first_sample.begin(), first_sample.end());
-            b->indep = n_streams > 1 && (int)phase.size() == G;
-            if (n_streams > 1) {
-                hipError_t e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
-                for (int g = 1; g < n_streams && e == hipSuccess; ++g) {
-                    hipStream_t st = nullptr;
-                    hipEvent_t ev = nullptr;
-                    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-                    if (e == hipSuccess) b->aux.push_back(st);
-                    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-                    if (e == hipSuccess) b->ev_join.push_back(ev);
-                }
-                if (e != hipSuccess) {
-                    xy_batch_free(b);
-                    return hip_err(e, "xy_batch_init: phase streams");
-                }
+            // phase index of every work unit, for regrouping
+            b->unit_k.resize(units.size() / 2);
+            for (size_t a = 0; a < b->unit_k.size(); ++a) b->unit_k[a] = units[2 * a + 1].y;
+            b->n_phase = (int)phase.size();
+            int n_streams = 2;   // XY_PHASE_STREAMS=1..4 overrides
+            if (const char *env = std::getenv("XY_PHASE_STREAMS")) n_streams = std::atoi(env);
+            const hipError_t e = setup_phase_groups(b, n_streams);
+            if (e != hipSuccess) {
+                xy_batch_free(b);
+                return hip_err(e, "xy_batch_init: phase streams");
             }
             unsigned char *ph = gimg.data() + gl.phase;
             std::copy(phase.begin(), phase.end(), reinterpret_cast<int32_t *>(ph));
             std::copy(units.begin(), units.end(), reinterpret_cast<int4 *>(ph + align_up(4 * (size_t)G, 16)));
-            b->n_phase = (int)phase.size();
             b->phase_stride = p.phase_blocks;
             b->d_phase = reinterpret_cast<int32_t *>(static_cast<unsigned char *>(d_graph) + gl.phase);
             b->d_units = reinterpret_cast<int4 *>(static_cast<unsigned char *>(d_graph) + gl.phase +
@@ -974,6 +989,30 @@ extern "C" xy_status xy_kernel_time(xy_batch *b, double *ms_total, int *n_timed)
     for (size_t k = 0; k < b->events_used && k < b->event_sweeps.size(); ++k) n += b->event_sweeps[k];
     if (ms_total) *ms_total = total;
     if (n_timed) *n_timed = n;
+    return XY_OK;
+}
+
+extern "C" xy_status xy_batch_set_phase_streams(xy_batch *b, int n_streams, void *stream)
+{
+    if (!b || n_streams < 1 || n_streams > kMaxPhaseStreams)
+        return set_error(XY_EINVAL, "xy_batch_set_phase_streams: n_streams must be in [1, 4]");
+    if (b->precision != XY_FIX16 || b->n_phase == 0) return XY_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamSynchronize(s);
+    for (size_t g = 0; g < b->aux.size() && e == hipSuccess; ++g) e = hipStreamSynchronize(b->aux[g]);
+    if (e == hipSuccess) e = setup_phase_groups(b, n_streams);
+    // every group's control block continues from group 0's (equal after a sweep call)
+    for (int g = 1; g < kMaxPhaseStreams && e == hipSuccess; ++g)
+        e = hipMemcpyAsync(b->dev.ctl + g, b->dev.ctl, sizeof(Ctl), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+    return e == hipSuccess ? XY_OK : hip_err(e, "xy_batch_set_phase_streams");
+}
+
+extern "C" xy_status xy_batch_phase_streams(const xy_batch *b, int *n_streams)
+{
+    if (!b || !n_streams) return set_error(XY_EINVAL, "xy_batch_phase_streams: NULL argument");
+    *n_streams = 1 + (int)b->aux.size();
     return XY_OK;
 }
 

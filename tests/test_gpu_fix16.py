@@ -260,6 +260,25 @@ def test_graph_replay_equals_direct_launches():
     assert all(np.array_equal(x, y) for x, y in zip(eager.get_state()[0], graph.get_state()[0]))
 
 
+def test_autotune_phase_streams_restores_state(tmp_path, monkeypatch):
+    """Every sample in the phase form: the tuner times one to three stream
+    groups, applies the fastest (the fewest within 2%), and restores the
+    state."""
+    monkeypatch.setenv("XY_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    g = [xy.Graph.levy(128, 6, 3.5, s) for s in range(4)]
+    b = xy.Batch(g, workloads.linear_ladder(1.0, 2.5, 8), precision="fix16", max_records=4)
+    b.sweep(5, pt_every=1, meas_every=0)
+    before = b.get_state()
+    rep = b.autotune(sweeps=2)
+    assert rep["tuned"] and set(rep["phase_streams_ms_per_sweep"]) == {"1", "2", "3"}
+    assert b.phase_streams() == rep["phase_streams"]
+    after = b.get_state()
+    assert after[2] == before[2] == 5 and np.array_equal(after[1], before[1])
+    assert all(np.array_equal(x, y) for x, y in zip(after[0], before[0]))
+    again = xy.Batch(g, workloads.linear_ladder(1.0, 2.5, 8), precision="fix16", max_records=4).autotune()
+    assert again["cached"] and again["phase_streams"] == rep["phase_streams"]
+
+
 def test_autotune_restores_state_and_applies_choice(tmp_path, monkeypatch):
     monkeypatch.setenv("XY_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
     g = [xy.Graph.levy(32, 6, 3.5, s) for s in range(8)] + [xy.Graph.levy(128, 6, 3.5, 9)]
@@ -361,21 +380,28 @@ def test_stream_groups_give_identical_trajectories(mixed, monkeypatch):
     records and tempering counters are identical.  With every sample in the
     phase form and two or more groups, each group runs its own energies,
     tempering, records and sweep counter (once also replayed from a captured
-    HIP graph); in a batch that also holds workgroup-form samples the groups
-    join every sweep."""
+    HIP graph, once regrouped from two to four groups half way); in a batch
+    that also holds workgroup-form samples the groups join every sweep."""
     graphs = [xy.Graph.levy(128, 6, 3.5, s) for s in range(5)]
     if mixed:
         graphs += [xy.Graph.levy(32, 6, 2.5, 11), xy.Graph.levy(16, 6, 3.5, 12)]
     G = len(graphs)
     T = workloads.linear_ladder(1.0, 2.5, 8)
     runs = []
-    for streams, chunk in (("1", 0), ("2", 0), ("3", 0), ("2", 4)):
-        monkeypatch.setenv("XY_PHASE_STREAMS", streams)
+    for streams, chunk in (("1", 0), ("2", 0), ("3", 0), ("2", 4), ("2>4", 0)):
+        monkeypatch.setenv("XY_PHASE_STREAMS", streams[0])
         b = xy.Batch(graphs, T, precision="fix16", seeds=np.arange(G) + 60, max_records=8, stream=torch.cuda.Stream())
         assert list(b.forms()) == [1] * 5 + [0] * (G - 5)
+        assert b.phase_streams() == int(streams[0])
         if chunk:
             b.use_graph(chunk)
-        b.sweep(12, pt_every=1, meas_every=4)
+        if ">" in streams:                       # regrouped half way (xy_batch_set_phase_streams)
+            b.sweep(6, pt_every=1, meas_every=4)
+            b.set_phase_streams(int(streams[2]))
+            assert b.phase_streams() == int(streams[2])
+            b.sweep(6, pt_every=1, meas_every=4)
+        else:
+            b.sweep(12, pt_every=1, meas_every=4)
         b.synchronize()
         st, sot, sw = b.get_state()
         nrec, acc, tries = b.counters()
