@@ -63,9 +63,10 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def time_gpu(wl, precision, steps, warmup, graphs, torch, xy, n_or=None, form=None):
+def time_gpu(wl, precision, steps, warmup, graphs, torch, xy, n_or=None, form=None, phase_streams=0):
     """Times `steps` sweeps.  fix16: autotunes first, or takes `form` =
-    (trig, allow_unit) from an earlier tuning."""
+    (trig, allow_unit) from an earlier tuning; phase_streams > 0 then fixes the
+    stream-group count of the phase-form samples."""
     n_or = wl.n_or if n_or is None else n_or
     stream = torch.cuda.Stream()
     b = xy.Batch(graphs, wl.T, precision=precision, seeds=[s.seed for s in wl.samples],
@@ -76,6 +77,8 @@ def time_gpu(wl, precision, steps, warmup, graphs, torch, xy, n_or=None, form=No
             tune = b.autotune(n_or=n_or, use_cache=False)
         else:
             b.set_fix16_form(trig=form[0], allow_unit=form[1])
+        if phase_streams:
+            b.set_phase_streams(phase_streams)
     b.sweep(warmup, n_or=n_or, pt_every=wl.pt_every, meas_every=wl.meas_every)
     b.synchronize()
     b.kernel_timing(True)
@@ -91,8 +94,9 @@ def time_gpu(wl, precision, steps, warmup, graphs, torch, xy, n_or=None, form=No
     b.kernel_timing(False)
     nrec, acc, tries = b.counters()
     rec = b.records().cpu().numpy()
+    n_groups = b.phase_streams() if precision == "fix16" else 1
     b.close()
-    return {"ms": ms, "kernel_ms": k_ms / max(k_n, 1), "kernel_n": k_n, "records": rec,
+    return {"ms": ms, "kernel_ms": k_ms / max(k_n, 1), "kernel_n": k_n, "records": rec, "phase_streams": n_groups,
             "pt_rate": float(acc.sum()) / max(float(tries.sum()), 1.0), "autotune": tune}
 
 
@@ -125,7 +129,7 @@ def _pmc_rows(path):
     return sorted(rows, key=lambda r: int(r["Dispatch_Id"]))
 
 
-def write_traffic(wl, paths, argv):
+def write_traffic(wl, paths, argv, phase_streams):
     """HBM bytes per sweep of the dominant fix16 kernel from rocprofv3 counter
     CSVs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch, summed over a sweep's
     dispatches), each scaled by what the same counter reads for a plain 512 MiB
@@ -139,20 +143,20 @@ def write_traffic(wl, paths, argv):
         # every group ends its sweep with its own k_end_sweep, and the
         # dispatches are in enqueue order, so the later ones close nothing);
         # the mean of the last n_last sweeps, which all ran the tuned form
-        sums, cur, names, n_disp, n_cur = [], 0.0, set(), 0, 0
+        sums, counts, cur, names, n_cur = [], [], 0.0, set(), 0
         for r in rows:
             if r["Counter_Name"] != counter:
                 continue
             if pat in r["Kernel_Name"]:
                 cur += float(r["Counter_Value"])
                 names.add(r["Kernel_Name"])
-                n_disp += 1
                 n_cur += 1
             elif "k_end_sweep" in r["Kernel_Name"] and n_cur:
                 sums.append(cur)
+                counts.append(n_cur)
                 cur, n_cur = 0.0, 0
         last = sums[-n_last:]
-        return sorted(names), sum(last) / len(last), n_disp / max(len(sums), 1)
+        return sorted(names), sum(last) / len(last), sum(counts[-n_last:]) / len(last)
 
     def copy_kib(rows, counter):
         v = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == counter]
@@ -169,7 +173,7 @@ def write_traffic(wl, paths, argv):
            "dispatches_per_sweep": round(n_per_sweep, 2), "fetch_kib_per_sweep": round(f_kib, 1),
            "write_kib_per_sweep": round(w_kib, 1), "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
            "bytes_per_sweep": int(bytes_sweep), "bytes_per_update": round(bytes_sweep / upd, 4),
-           "updates_per_sweep": upd, "command": f"python bench.py {argv}"}
+           "updates_per_sweep": upd, "phase_streams": phase_streams, "command": f"python bench.py {argv}"}
     if len(paths) > 4:
         # VALU wave instructions of the same dispatches; x 64 lanes
         _, valu, _ = per_sweep(_pmc_rows(paths[4]), "SQ_INSTS_VALU")
@@ -245,6 +249,9 @@ def main():
                     help="sweeps of the Metropolis-only run that splits the rate into Met and OR (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (HBM counter calibration)")
+    ap.add_argument("--phase-streams", type=int, default=0,
+                    help="stream groups of the phase-form samples (default: the autotuner's choice); with "
+                         "--traffic-from, the count the counters were taken with")
     ap.add_argument("--traffic-from", nargs="+", metavar="CSV",
                     help="no GPU work: FETCH_CSV WRITE_CSV CAL_FETCH_CSV CAL_WRITE_CSV [SQ_CSV]: turn rocprofv3 --pmc "
                          "FETCH_SIZE / WRITE_SIZE counter CSVs of this workload and of --calibrate-copy 512 (and "
@@ -253,7 +260,9 @@ def main():
     if args.traffic_from:
         if len(args.traffic_from) not in (4, 5):
             ap.error("--traffic-from takes 4 or 5 CSV paths")
-        write_traffic(workloads.ALL[args.workload](), args.traffic_from, " ".join(sys.argv[1:]))
+        if not args.phase_streams:
+            ap.error("--traffic-from needs --phase-streams: the group count the counters were taken with")
+        write_traffic(workloads.ALL[args.workload](), args.traffic_from, " ".join(sys.argv[1:]), args.phase_streams)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the samples are independent and a multi-GPU "
@@ -282,7 +291,8 @@ def main():
           f"{sorted(set(g.n_colours for g in graphs))}", file=sys.stderr, flush=True)
 
     upd_per_sweep = wl.updates_per_sweep()
-    main_run = time_gpu(wl, args.precision, args.steps, args.warmup, graphs, torch, xy)
+    main_run = time_gpu(wl, args.precision, args.steps, args.warmup, graphs, torch, xy,
+                        phase_streams=args.phase_streams)
     value = upd_per_sweep * args.steps / (main_run["ms"] * 1e6)
     print(f"# {args.precision}: {main_run['ms'] / args.steps:.3f} ms/sweep, {value:.1f} updates/ns",
           file=sys.stderr, flush=True)
@@ -296,7 +306,9 @@ def main():
     if args.precision == "fix16" and os.path.exists(traffic_file(wl.name)):
         with open(traffic_file(wl.name)) as fh:
             tr = json.load(fh)
-        if tr.get("kernel_digest") == kernel_source_digest() and tr.get("workload") == wl.name:
+        # the counters hold for this source and for the stream-group count they were taken with
+        if (tr.get("kernel_digest") == kernel_source_digest() and tr.get("workload") == wl.name
+                and tr.get("phase_streams") == main_run["phase_streams"]):
             traffic = tr["bytes_per_sweep"]
     if args.precision == "fp64":
         kname = "k_fp64_phase (the 6·Q colour-phase launches of one sweep)"
@@ -339,7 +351,8 @@ def main():
         # are outside the kernel time)
         tuned = main_run["autotune"]
         form = (tuned["trig"], tuned["allow_unit"]) if tuned and "trig" in tuned else None
-        met = time_gpu(wl, args.precision, args.split_steps, 2, graphs, torch, xy, n_or=0, form=form)
+        met = time_gpu(wl, args.precision, args.split_steps, 2, graphs, torch, xy, n_or=0, form=form,
+                       phase_streams=main_run["phase_streams"])
         n_upd = upd_per_sweep // (1 + wl.n_or)
         or_ms = k_ms - met["kernel_ms"]
         split = {"met_only": round(n_upd / (met["kernel_ms"] * 1e6), 2),
