@@ -137,8 +137,9 @@ xy_status xy_batch_sizes(const xy_graph *const *g, int n_graphs, int n_T, int pr
  *   seeds : uint64[n_graphs] Philox keys of the samples' dynamics
  * The graphs may be freed after this call returns.
  * fix16 storage per sample: graphs of at least 16384 sites, when n_T is a
- * multiple of 4, are stored site-major and swept one colour phase of all such
- * samples per launch (the phase form); smaller graphs, or any n_T, get one
+ * multiple of 4, are stored site-major and swept one colour phase of many such
+ * samples per launch (the phase form; the samples form stream groups, see
+ * xy_batch_set_phase_streams); smaller graphs, or any n_T, get one
  * workgroup per replica with the replica in LDS when it fits (else in global
  * memory).  The environment variables XY_FIX16_PHASE_MIN (the site threshold)
  * and XY_FIX16_PHASE (1: every sample, 0: none) override the rule; they are

@@ -1,7 +1,7 @@
 // Fixed-point path, phase form (graphs from 16384 sites when the temperature
 // count is a multiple of 4): the state of a sample is site-major, [site][slot],
-// and one launch updates one colour class of all phase-form samples (App. B's
-// colour phases as launches over the whole batch).
+// and one launch updates one colour class of the phase-form samples of one
+// stream group (App. B's colour phases as launches over many samples).
 #include <hip/hip_runtime.h>
 
 #include "fix16_common.hpp"
