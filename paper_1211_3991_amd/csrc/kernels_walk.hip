@@ -85,11 +85,13 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkDesc *desc, const
             const uint32_t r = (t & 3) == 0 ? x[a].x : (t & 3) == 1 ? x[a].y : (t & 3) == 2 ? x[a].z : x[a].w;
             if (e[a].y > 0) cur[a] = nbr[e[a].x + (int)(((uint64_t)r * (uint32_t)e[a].y) >> 32)];
         }
+        // walkers at their start: counted per wave (one atomic per wave and
+        // step instead of one per walker, which all hit the same bin)
+        uint32_t n_at = 0;
 #pragma unroll
-        for (int a = 0; a < kW; ++a) {
-            if (live[a] && cur[a] == s0[a]) {
-                if constexpr (kLds) atomicAdd(&lds[t + 1], 1u); else atomicAdd(&h[t + 1], 1ull);
-            }
+        for (int a = 0; a < kW; ++a) n_at += (uint32_t)__popcll(__ballot(live[a] && cur[a] == s0[a]));
+        if (n_at && __lane_id() == 0) {
+            if constexpr (kLds) atomicAdd(&lds[t + 1], n_at); else atomicAdd(&h[t + 1], (unsigned long long)n_at);
         }
     }
     if constexpr (kLds) {
