@@ -1,8 +1,10 @@
 // Random walks on the graphs (Sec. 2, spectral dimension; App. A): the
 // histogram of the times at which a walker is back at its starting site
-// estimates P(tau) ~ tau^(-dbar/2).  One thread per walker, all graphs in one
-// launch.  A step is two dependent loads: the site's (first neighbour, degree)
-// record, then the chosen neighbour; one Philox4x32-10 call serves four steps.
+// estimates P(tau) ~ tau^(-dbar/2).  All graphs in one launch.  A step loads
+// the site's 16-byte record (degree, first two neighbours, offset of the
+// others), and a second, dependent load only when the chosen neighbour is past
+// the second (one scattered line per step instead of two for most of them);
+// one Philox4x32-10 call serves four steps.
 // The per-block histogram lives in LDS (walks up to 8191 steps; longer ones
 // count in global memory) and is added to the caller's histogram with 64-bit
 // integer atomics, so the result does not depend on the order in which
@@ -19,7 +21,7 @@ namespace xy {
 namespace {
 
 struct WalkDesc {
-    int64_t od;        // int2 pool: (first neighbour, degree) per site
+    int64_t od;        // int4 pool per site: degree, neighbours 0 and 1, nbr offset of neighbour 2
     int64_t nbr;       // int32 pool: neighbours, ascending lattice index per site
     int64_t elig;      // int32 pool: sites of degree > 2, ascending
     int32_t n, n_elig, centre, pad_;
@@ -41,7 +43,7 @@ __device__ __forceinline__ int xcd_run(int lin, int n)
 
 // One thread runs kW walkers in lock step (their loads overlap).
 template <bool kLds, int kW>
-__global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkDesc *desc, const int2 *od_pool, const int32_t *i32,
+__global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkDesc *desc, const int4 *od_pool, const int32_t *i32,
                                                     int n_walkers, int n_steps, int start_mode, int blocks_per_graph,
                                                     unsigned long long *hist)
 {
@@ -54,7 +56,7 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkDesc *desc, const
         for (int t = threadIdx.x; t <= n_steps; t += kWalkBlock) lds[t] = 0u;
         __syncthreads();
     }
-    const int2 *od = od_pool + d.od;
+    const int4 *od = od_pool + d.od;
     const int32_t *nbr = i32 + d.nbr;
     int w[kW], s0[kW], cur[kW];
     bool live[kW];
@@ -77,13 +79,14 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkDesc *desc, const
                 x[a] = philox4x32_10({(uint32_t)w[a], (uint32_t)(t >> 2), 0u, (uint32_t)kWalk << 24}, d.seed_lo,
                                      d.seed_hi);
         }
-        int2 e[kW];
+        int4 e[kW];
 #pragma unroll
         for (int a = 0; a < kW; ++a) e[a] = od[cur[a]];
 #pragma unroll
         for (int a = 0; a < kW; ++a) {
             const uint32_t r = (t & 3) == 0 ? x[a].x : (t & 3) == 1 ? x[a].y : (t & 3) == 2 ? x[a].z : x[a].w;
-            if (e[a].y > 0) cur[a] = nbr[e[a].x + (int)(((uint64_t)r * (uint32_t)e[a].y) >> 32)];
+            const int j = (int)(((uint64_t)r * (uint32_t)e[a].x) >> 32);   // neighbour number, < degree
+            if (e[a].x > 0) cur[a] = j == 0 ? e[a].y : j == 1 ? e[a].z : nbr[e[a].w + j - 2];
         }
         // walkers at their start: counted per wave (one atomic per wave and
         // step instead of one per walker, which all hit the same bin)
@@ -131,7 +134,7 @@ xy_status plan_walk(const xy_graph *const *g, int G, WalkPlan &p)
     }
     p.off_desc = 0;
     p.off_od = align256(sizeof(WalkDesc) * G);
-    p.off_i32 = align256(p.off_od + 8 * p.n_od);
+    p.off_i32 = align256(p.off_od + 16 * p.n_od);
     p.total = align256(p.off_i32 + 4 * p.n_i32);
     return XY_OK;
 }
@@ -166,7 +169,7 @@ extern "C" xy_status xy_random_walk(const xy_graph *const *g, int n_graphs, int 
         if (st != XY_OK) return st;
         if (graph_bytes < p.total) return set_error(XY_EINVAL, "xy_random_walk: d_graph smaller than xy_walk_bytes");
         std::vector<unsigned char> img(p.total, 0);
-        int2 *od = reinterpret_cast<int2 *>(img.data() + p.off_od);
+        int4 *od = reinterpret_cast<int4 *>(img.data() + p.off_od);
         int32_t *i32 = reinterpret_cast<int32_t *>(img.data() + p.off_i32);
         std::vector<int32_t> deg, fill;
         for (int k = 0; k < n_graphs; ++k) {
@@ -175,16 +178,23 @@ extern "C" xy_status xy_random_walk(const xy_graph *const *g, int n_graphs, int 
             const int n = gr.n;
             deg.assign(n, 0);
             for (int e = 0; e < gr.m; ++e) { ++deg[gr.edges[2 * e]]; ++deg[gr.edges[2 * e + 1]]; }
+            std::vector<int32_t> first(n);
             int32_t acc = 0;
-            for (int i = 0; i < n; ++i) { od[d.od + i] = make_int2(acc, deg[i]); acc += deg[i]; }
+            for (int i = 0; i < n; ++i) { first[i] = acc; acc += deg[i]; }
             int32_t *nb = i32 + d.nbr;
             fill.assign(n, 0);
             for (int e = 0; e < gr.m; ++e) {
                 const int a = gr.edges[2 * e], b = gr.edges[2 * e + 1];
-                nb[od[d.od + a].x + fill[a]++] = b;
-                nb[od[d.od + b].x + fill[b]++] = a;
+                nb[first[a] + fill[a]++] = b;
+                nb[first[b] + fill[b]++] = a;
             }
-            for (int i = 0; i < n; ++i) std::sort(nb + od[d.od + i].x, nb + od[d.od + i].x + deg[i]);
+            // record: degree, the first two neighbours (ascending lattice index),
+            // and the offset of the third in nb (neighbour j >= 2 is nb[w + j - 2])
+            for (int i = 0; i < n; ++i) {
+                std::sort(nb + first[i], nb + first[i] + deg[i]);
+                od[d.od + i] = make_int4(deg[i], deg[i] > 0 ? nb[first[i]] : 0, deg[i] > 1 ? nb[first[i] + 1] : 0,
+                                         first[i] + 2);
+            }
             int n_elig = 0;
             for (int i = 0; i < n; ++i)
                 if (deg[i] > 2) i32[d.elig + n_elig++] = i;
@@ -219,7 +229,7 @@ extern "C" xy_status xy_random_walk(const xy_graph *const *g, int n_graphs, int 
         if (e == hipSuccess && n_walkers > 0) {
             unsigned char *base = static_cast<unsigned char *>(d_graph);
             const auto *dd = reinterpret_cast<const WalkDesc *>(base + p.off_desc);
-            const auto *dod = reinterpret_cast<const int2 *>(base + p.off_od);
+            const auto *dod = reinterpret_cast<const int4 *>(base + p.off_od);
             const auto *di = reinterpret_cast<const int32_t *>(base + p.off_i32);
             // kWalkers walkers per thread; one flat grid of (graph, block) units
             const int64_t per = (n_walkers + kWalkBlock * kWalkers - 1) / (kWalkBlock * kWalkers);
