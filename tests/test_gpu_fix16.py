@@ -302,8 +302,8 @@ def test_full_headline_shape_sampled():
     """64 x L=256 x 24 T, the benchmark's launch configuration (autotuned form):
     after 6 sweeps with PT the fused record of the last sweep equals a
     standalone measurement of the same state, samples 0 and 37 of it equal the
-    oracle's measurement of that state, and every PT pair was attempted on its
-    parity's sweeps."""
+    oracle's measurement of that state, their tempering energies equal the
+    state's energy, and every PT pair was attempted on its parity's sweeps."""
     wl = workloads.headline_l256()
     graphs = [xy.Graph.levy(s.L, s.z, s.rho, s.seed) for s in wl.samples]
     b = xy.Batch(graphs, wl.T, precision="fix16", seeds=[s.seed for s in wl.samples], max_records=4)
@@ -316,6 +316,7 @@ def test_full_headline_shape_sampled():
     assert np.allclose(rec[-1], o, rtol=1e-12, atol=1e-9)
     st, sot, sw = b.get_state()
     assert sw == 6
+    E_pt = b.pt_energies().cpu().numpy()
     for k in (0, 37):
         s = wl.samples[k]
         e, _ = oracle.levy_graph(s.L, s.z, s.rho, s.seed)
@@ -324,6 +325,11 @@ def test_full_headline_shape_sampled():
         sim.set_state(_unit(st[k]), sot[k], sw)
         ref = sim.measure()
         assert np.allclose(o[k, :, :7], ref[:, :7], rtol=1e-10, atol=1e-8), k
+        edges = graphs[k].export()["edges"]
+        for slot in range(wl.n_T):
+            th = st[k][slot].astype(np.float64) * (2 * np.pi / 65536)
+            e_ref = -np.cos(th[edges[:, 0]] - th[edges[:, 1]]).sum()
+            assert abs(E_pt[k, slot] - e_ref) <= 1e-5 * abs(e_ref), (k, slot)
     # pairs (k, k+1) with k even are tried on even sweeps (0, 2, 4), odd k on odd sweeps
     R = wl.n_T
     expect = np.array([3 if k % 2 == 0 else 3 for k in range(R - 1)] + [0])
