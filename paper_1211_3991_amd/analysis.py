@@ -305,3 +305,46 @@ def gamma_over_nu_bar(T, N, records, T_ref, discard=0.5):
         return np.polyfit(np.log(Ns), ln_chi, 1)[0]
 
     return _jackknife_sizes(est, per_size)
+
+
+def _eta_curve(T, L, m2_means, r):
+    """eta at every ladder temperature from the per-size mean |m|^2 curves."""
+    Ls = np.asarray(L, dtype=np.float64)
+    x = np.log(Ls)
+    y = np.stack([np.log(l * l * m2) + 2.0 * r * np.log(np.log(l)) for l, m2 in zip(Ls, m2_means)])
+    slope = np.polyfit(x, y, 1)[0]                 # one slope per temperature
+    return 2.0 - slope
+
+
+def eta_of_T(T, L, records, r=1.0 / 16, discard=0.5):
+    """eta(T) on a square L x L lattice (Sec. 5, the square-lattice limit,
+    Eq. chi_SR): chi = N <|m|^2> ~ L^(2 - eta) (ln L)^(-2r) at each ladder
+    temperature, fitted over the sizes (least squares of ln chi + 2r ln ln L
+    against ln L; r = 1/16).  records: one [n_rec, G, n_T, 8] array per size
+    in L.  Returns eta per temperature (sample means of <|m|^2>)."""
+    m2 = []
+    for rec in records:
+        rec = np.asarray(rec, dtype=np.float64)
+        rec = rec[int(rec.shape[0] * discard):]
+        m2.append(rec.mean(axis=(0, 1))[:, M2])
+    return _eta_curve(T, L, m2, r)
+
+
+def t_eta(T, L, records, eta_target=0.25, r=1.0 / 16, discard=0.5):
+    """The temperature where eta(T) of eta_of_T reaches eta_target (the KT
+    value 1/4 locates T_c, Sec. 5), by linear interpolation along the ladder,
+    with a jackknife error over the samples of each size.  Returns (T, error);
+    T is None when eta does not cross the target on the ladder."""
+    T = np.asarray(T, dtype=np.float64)
+    per_size = []
+    for rec in records:
+        rec = np.asarray(rec, dtype=np.float64)
+        rec = rec[int(rec.shape[0] * discard):]
+        per_size.append((rec.mean(axis=0)[:, :, M2],))
+
+    def est(means):
+        eta = _eta_curve(T, L, [m2 for (m2,) in means], r)
+        return crossing(T, eta, np.full_like(eta, eta_target))
+
+    t, err = _jackknife_sizes(est, per_size)
+    return t, err

@@ -156,3 +156,32 @@ def test_u4_slope_at():
     t, s = analysis.u4_slope_at(T, np.array([0.9, 0.5, 0.1]), 0.6)
     assert abs(t - 1.75) < 1e-12 and abs(s + 0.4) < 1e-12
     assert analysis.u4_slope_at(T, np.array([0.9, 0.8, 0.7]), 0.1) is None
+
+
+def test_eta_and_kt_temperature_from_exact_scaling():
+    """chi = L^(2 - eta(T)) (ln L)^(-1/8) c(T) with eta(T) = 1/4 + 1.5 (T - 0.894)
+    (the square-lattice form of Sec. 5, Eq. chi_SR): eta_of_T returns eta(T)
+    and t_eta the temperature where eta = 1/4, exactly; with per-sample noise
+    the jackknife error is finite and covers it.  A dropped log correction
+    (r = 0) moves the answer, so the correction is pinned too."""
+    T = np.linspace(0.80, 1.00, 11)
+    L = [16, 32, 64, 128]
+    eta = 0.25 + 1.5 * (T - 0.894)
+
+    def recs(G, rng=None):
+        out = []
+        for l in L:
+            m2 = l ** (-eta) * np.log(l) ** (-1.0 / 8) * (1.2 - 0.1 * T)
+            out.append(_scaling_records(T, l * l, G, lambda t: np.zeros_like(t), lambda t, m2=m2: m2, rng))
+            if rng is not None:
+                out[-1][:, :, :, 1] *= 1.0 + 0.002 * rng.normal(size=(1, G, 1))
+        return out
+
+    r = recs(4)
+    assert np.allclose(analysis.eta_of_T(T, L, r, discard=0.0), eta, atol=1e-12)
+    t, err = analysis.t_eta(T, L, r, discard=0.0)
+    assert abs(t - 0.894) < 1e-12 and err < 1e-12
+    t0, _ = analysis.t_eta(T, L, r, r=0.0, discard=0.0)
+    assert abs(t0 - 0.894) > 0.005
+    t, err = analysis.t_eta(T, L, recs(24, np.random.default_rng(5)), discard=0.0)
+    assert 0 < err < 0.01 and abs(t - 0.894) < 5 * err
