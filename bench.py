@@ -326,7 +326,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kname,
                 "kernel_ms": round(k_ms, 4), "alg_bytes_per_update": round(bpu, 3),
-                "updates_per_launch": upd_per_sweep}
+                "updates_per_sweep": upd_per_sweep}
     # the bound the kernel meets first: VALU issue, from the counted VALU
     # instructions of the same launches (same digest rule as the traffic)
     alu = None
