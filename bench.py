@@ -113,17 +113,17 @@ def time_walk(xy):
     steps = G * W * T
     d, err = analysis.spectral_dimension(hist.cpu().numpy().sum(axis=0), 32, 1024)
     # the 16-byte site record every step, and a 4-byte neighbour index on the
-    # steps past the second neighbour: a fraction sum_i max(0, d_i - 2) / 2M
-    # of them for a walker in its stationary law (0.516 on these graphs)
-    bps = 16 + 4 * 0.516
+    # steps past the third neighbour: a fraction sum_i max(0, d_i - 3) / 2M
+    # of them for a walker in its stationary law (0.312 on these graphs)
+    bps = 16 + 4 * 0.312
     gbs = bps * steps / (ms * 1e6)
     return {"value": round(steps / (ms * 1e6), 2), "unit": "walker steps/ns", "kernel_ms": round(ms, 3),
             "workload": f"{G} graphs of L={L} (rho={rho}, z=4), {W} walkers each from sites of degree > 2, {T} steps",
             "dbar": round(d, 3), "dbar_err": round(err, 3), "dbar_formula": round(2 * 2 / (rho - 2), 3),
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes_per_step": bps,
-                         "note": "one scattered record load per step, a second dependent one on about half of "
-                                 "the steps; the graphs (about 24 MB) stay in L2/MALL, "
+                         "note": "one scattered record load per step, a second dependent one on about a third "
+                                 "of the steps; the graphs (about 24 MB) stay in L2/MALL, "
                                  "so latency, not HBM bandwidth, binds"}}
 
 

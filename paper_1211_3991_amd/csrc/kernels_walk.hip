@@ -1,10 +1,12 @@
 // Random walks on the graphs (Sec. 2, spectral dimension; App. A): the
 // histogram of the times at which a walker is back at its starting site
 // estimates P(tau) ~ tau^(-dbar/2).  All graphs in one launch.  A step loads
-// the site's 16-byte record (degree, first two neighbours, offset of the
-// others), and a second, dependent load only when the chosen neighbour is past
-// the second (one scattered line per step instead of two for most of them);
-// one Philox4x32-10 call serves four steps.
+// the site's 16-byte record and a second, dependent neighbour index only when
+// the chosen neighbour is not in the record (one scattered line per step
+// instead of two for most steps): degree and the offset of the rest packed in
+// one word with the first three neighbours when every graph has fewer than
+// 2^24 - 3 neighbour entries, else degree, first two neighbours and offset.
+// One Philox4x32-10 call serves four steps.
 // The per-block histogram lives in LDS (walks up to 8191 steps; longer ones
 // count in global memory) and is added to the caller's histogram with 64-bit
 // integer atomics, so the result does not depend on the order in which
@@ -12,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -21,7 +24,7 @@ namespace xy {
 namespace {
 
 struct WalkDesc {
-    int64_t od;        // int4 pool per site: degree, neighbours 0 and 1, nbr offset of neighbour 2
+    int64_t od;        // int4 pool per site: the record (see k_walk)
     int64_t nbr;       // int32 pool: neighbours, ascending lattice index per site
     int64_t elig;      // int32 pool: sites of degree > 2, ascending
     int32_t n, n_elig, centre, pad_;
@@ -41,8 +44,10 @@ __device__ __forceinline__ int xcd_run(int lin, int n)
     return x * per + min(x, rem) + k;
 }
 
-// One thread runs kW walkers in lock step (their loads overlap).
-template <bool kLds, int kW>
+// One thread runs kW walkers in lock step (their loads overlap).  Record of a
+// site: kPacked: (degree | offset of neighbour 3 << 8, n0, n1, n2); else
+// (degree, n0, n1, offset of neighbour 2).
+template <bool kLds, int kW, bool kPacked>
 __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkDesc *desc, const int4 *od_pool, const int32_t *i32,
                                                     int n_walkers, int n_steps, int start_mode, int blocks_per_graph,
                                                     unsigned long long *hist)
@@ -85,8 +90,15 @@ __global__ __launch_bounds__(kWalkBlock) void k_walk(const WalkDesc *desc, const
 #pragma unroll
         for (int a = 0; a < kW; ++a) {
             const uint32_t r = (t & 3) == 0 ? x[a].x : (t & 3) == 1 ? x[a].y : (t & 3) == 2 ? x[a].z : x[a].w;
-            const int j = (int)(((uint64_t)r * (uint32_t)e[a].x) >> 32);   // neighbour number, < degree
-            if (e[a].x > 0) cur[a] = j == 0 ? e[a].y : j == 1 ? e[a].z : nbr[e[a].w + j - 2];
+            const uint32_t dg = kPacked ? ((uint32_t)e[a].x & 255u) : (uint32_t)e[a].x;
+            const int j = (int)(((uint64_t)r * dg) >> 32);               // neighbour number, < degree
+            if (dg > 0) {
+                if constexpr (kPacked)
+                    cur[a] = j == 0 ? e[a].y : j == 1 ? e[a].z : j == 2 ? e[a].w
+                                                                         : nbr[((uint32_t)e[a].x >> 8) + j - 3];
+                else
+                    cur[a] = j == 0 ? e[a].y : j == 1 ? e[a].z : nbr[e[a].w + j - 2];
+            }
         }
         // walkers at their start: counted per wave (one atomic per wave and
         // step instead of one per walker, which all hit the same bin)
@@ -172,6 +184,12 @@ extern "C" xy_status xy_random_walk(const xy_graph *const *g, int n_graphs, int 
         int4 *od = reinterpret_cast<int4 *>(img.data() + p.off_od);
         int32_t *i32 = reinterpret_cast<int32_t *>(img.data() + p.off_i32);
         std::vector<int32_t> deg, fill;
+        // packed records when every graph's neighbour list (offset of neighbour 3 included) fits 24 bits;
+        // degrees are below 256 for every graph the library builds
+        // (XY_WALK_PACKED=0 forces the other form; tests compare both)
+        bool packed = true;
+        if (const char *env = std::getenv("XY_WALK_PACKED")) packed = std::atoi(env) != 0;
+        for (int k = 0; k < n_graphs; ++k) packed = packed && 2 * (int64_t)g[k]->m + 3 < (int64_t)1 << 24;
         for (int k = 0; k < n_graphs; ++k) {
             const xy_graph &gr = *g[k];
             WalkDesc &d = p.desc[k];
@@ -188,12 +206,16 @@ extern "C" xy_status xy_random_walk(const xy_graph *const *g, int n_graphs, int 
                 nb[first[a] + fill[a]++] = b;
                 nb[first[b] + fill[b]++] = a;
             }
-            // record: degree, the first two neighbours (ascending lattice index),
-            // and the offset of the third in nb (neighbour j >= 2 is nb[w + j - 2])
+            // neighbours in ascending lattice index; the record holds the first
+            // ones and the offset in nb of the rest
             for (int i = 0; i < n; ++i) {
                 std::sort(nb + first[i], nb + first[i] + deg[i]);
-                od[d.od + i] = make_int4(deg[i], deg[i] > 0 ? nb[first[i]] : 0, deg[i] > 1 ? nb[first[i] + 1] : 0,
-                                         first[i] + 2);
+                const int32_t *f = nb + first[i];
+                if (packed)
+                    od[d.od + i] = make_int4((int32_t)((uint32_t)deg[i] | ((uint32_t)(first[i] + 3) << 8)),
+                                             deg[i] > 0 ? f[0] : 0, deg[i] > 1 ? f[1] : 0, deg[i] > 2 ? f[2] : 0);
+                else
+                    od[d.od + i] = make_int4(deg[i], deg[i] > 0 ? f[0] : 0, deg[i] > 1 ? f[1] : 0, first[i] + 2);
             }
             int n_elig = 0;
             for (int i = 0; i < n; ++i)
@@ -235,13 +257,12 @@ extern "C" xy_status xy_random_walk(const xy_graph *const *g, int n_graphs, int 
             const int64_t per = (n_walkers + kWalkBlock * kWalkers - 1) / (kWalkBlock * kWalkers);
             const int64_t units = per * n_graphs;
             if (units > 0x7fffffff) return set_error(XY_EINVAL, "xy_random_walk: too many walkers");
-            if (n_steps + 1 <= kWalkLdsBins)
-                hipLaunchKernelGGL((k_walk<true, kWalkers>), dim3((unsigned)units), dim3(kWalkBlock),
-                                   4 * (size_t)(n_steps + 1), s, dd, dod, di, n_walkers, n_steps, start_mode, (int)per,
-                                   h);
-            else
-                hipLaunchKernelGGL((k_walk<false, kWalkers>), dim3((unsigned)units), dim3(kWalkBlock), 0, s, dd, dod,
-                                   di, n_walkers, n_steps, start_mode, (int)per, h);
+            const bool lds = n_steps + 1 <= kWalkLdsBins;
+            const size_t lds_bytes = lds ? 4 * (size_t)(n_steps + 1) : 0;
+            auto kern = lds ? (packed ? k_walk<true, kWalkers, true> : k_walk<true, kWalkers, false>)
+                            : (packed ? k_walk<false, kWalkers, true> : k_walk<false, kWalkers, false>);
+            hipLaunchKernelGGL(kern, dim3((unsigned)units), dim3(kWalkBlock), lds_bytes, s, dd, dod, di, n_walkers,
+                               n_steps, start_mode, (int)per, h);
             e = hipGetLastError();
         }
         if (e == hipSuccess && kernel_ms) {

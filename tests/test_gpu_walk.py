@@ -26,9 +26,13 @@ def _oracle_hist(L, z, rho, gseed, n_walkers, n_steps, wseed, mode):
     return oracle.random_walk(L * L, e, L, n_walkers, n_steps, wseed, start_mode=mode)
 
 
+@pytest.mark.parametrize("packed", ["1", "0"])
 @pytest.mark.parametrize("start,mode", [("degree3", 1), ("centre", 0)])
 @pytest.mark.parametrize("n_walkers,n_steps", [(3000, 300), (1, 40), (257, 1000), (300, 9000)])
-def test_histograms_equal_oracle(start, mode, n_walkers, n_steps):
+def test_histograms_equal_oracle(start, mode, n_walkers, n_steps, packed, monkeypatch):
+    """Both site-record forms (three neighbours packed with degree and offset,
+    or two with separate degree and offset)."""
+    monkeypatch.setenv("XY_WALK_PACKED", packed)
     specs = [(32, 6, 3.5, 1), (32, 4, 2.5, 2), (16, 6, 4.5, 3)]
     graphs = [xy.Graph.levy(L, z, rho, s) for L, z, rho, s in specs]
     seeds = np.array([11, 12, 13], dtype=np.uint64)
