@@ -32,7 +32,7 @@ struct WalkDesc {
 };
 
 constexpr int kWalkBlock = 256;
-constexpr int kWalkers = 2;             // walkers per thread
+constexpr int kWalkers = 1;             // walkers per thread
 constexpr int kWalkLdsBins = 8192;      // steps + 1 up to this: LDS histogram (dynamic, 4 B a bin)
 
 // Each XCD takes one contiguous run of the (graph, block) units (the
