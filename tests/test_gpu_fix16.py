@@ -355,14 +355,15 @@ def test_phase_form_pt_batch_matches_fp64_gpu(monkeypatch):
     assert np.max(np.abs(np.array(zs))) < 4.0, zs
 
 
-@pytest.mark.parametrize("streams,n_T", [("1", 8), ("2", 8), ("3", 8), ("2", 4), ("2", 12), ("2", 24)])
+@pytest.mark.parametrize("streams,n_T", [("1", 8), ("2", 8), ("3", 8), ("2", 4), ("2", 12), ("2", 24), ("2", 256)])
 def test_tempering_energies_equal_state_energy(streams, n_T, monkeypatch):
     """The replica energies the tempering step uses (summed in the last
     sub-sweep over the links to lower colours) equal
     -sum_links cos(theta_i - theta_j) of the state, in FP64 from the exported
     links: phase form with its samples in one to three stream groups, and a
     workgroup-form sample.  4, 8 and 12 temperatures put more than 64 sites in
-    a block (blocks spanning three to five chunks); 24 is the headline's."""
+    a block (blocks spanning three to five chunks); 24 is the headline's; 256,
+    the most a batch takes, puts four sites in a block."""
     monkeypatch.setenv("XY_PHASE_STREAMS", streams)
     graphs = [xy.Graph.levy(128, 6, 3.5, s) for s in range(5)] + [xy.Graph.levy(32, 6, 2.5, 7)]
     T = workloads.linear_ladder(1.0, 2.5, n_T)
