@@ -277,6 +277,10 @@ def test_autotune_phase_streams_restores_state(tmp_path, monkeypatch):
     assert all(np.array_equal(x, y) for x, y in zip(after[0], before[0]))
     again = xy.Batch(g, workloads.linear_ladder(1.0, 2.5, 8), precision="fix16", max_records=4).autotune()
     assert again["cached"] and again["phase_streams"] == rep["phase_streams"]
+    for bad in (0, 5):
+        with pytest.raises(xy.XYError):
+            b.set_phase_streams(bad)
+    assert b.phase_streams() == rep["phase_streams"]
 
 
 def test_autotune_restores_state_and_applies_choice(tmp_path, monkeypatch):
