@@ -127,6 +127,25 @@ def time_walk(xy):
                                  "so latency, not HBM bandwidth, binds"}}
 
 
+def copy_bandwidth(torch, mib=1024, reps=10):
+    """Achievable HBM rate of a plain device copy (bytes read + written per
+    second), for context beside the published peak."""
+    n = mib << 20
+    src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * n * reps / (t0.elapsed_time(t1) * 1e6)
+    del src, dst
+    return round(gbs, 1)
+
+
 def _pmc_rows(path):
     with open(path, newline="") as fh:
         rows = list(csv.DictReader(fh))
@@ -324,6 +343,7 @@ def main():
         kname = "k_fix16_sweep (one launch = one sweep of every (sample, slot))"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "achievable_copy_gbs": copy_bandwidth(torch),
                 "kernel": kname,
                 "kernel_ms": round(k_ms, 4), "alg_bytes_per_update": round(bpu, 3),
                 "updates_per_sweep": upd_per_sweep}
