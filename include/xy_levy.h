@@ -156,8 +156,15 @@ xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int n_graphs, 
  * 2, sweep mod 2 + 2, ...; then, when meas_every > 0 and
  * (sweep+1) % meas_every == 0, a record [n_graphs][n_T][XY_NOBS] is appended
  * to the observation buffer (ignored once max_records are stored).
- * n_sweeps >= 0, 0 <= n_or <= 255. */
-xy_status xy_sweep(xy_batch *b, int n_sweeps, int n_or, int pt_every, int meas_every, void *stream);
+ *   T : NULL keeps the ladder; else double[n_graphs * n_T], the new
+ *       temperature of every (sample, temperature index) from this call on
+ *       (finite, > 0).  The labels stay: the replica that holds index k
+ *       continues at the new T_k.  The host array may be reused when the call
+ *       returns (the batch uploads a copy of 1/T on `stream`).
+ * n_sweeps >= 0, 0 <= n_or <= 255.  Errors: XY_EINVAL (bad argument; no
+ * effect), XY_EHIP. */
+xy_status xy_sweep(xy_batch *b, const double *T, int n_sweeps, int n_or, int pt_every, int meas_every,
+                   void *stream);
 
 /* Observables of the current state, by temperature, into caller-owned device
  * memory d_out: double[n_graphs][n_T][XY_NOBS] (E, |m|^2, |m|^4, F_x, F_y,
@@ -165,16 +172,17 @@ xy_status xy_sweep(xy_batch *b, int n_sweeps, int n_or, int pt_every, int meas_e
  * F_a = |sum_j S_j exp(2 pi i a_j / L)|^2 / N (Sec. 3). */
 xy_status xy_measure(xy_batch *b, double *d_out, void *stream);
 
-/* Enqueues one parallel-tempering step now (energies recomputed from the
- * current state, pair parity from the sweep counter). */
+/* Enqueues one parallel-tempering step now (App. B, parallel tempering:
+ * exchanges of the temperatures of neighbouring replicas with the
+ * Hukushima-Nemoto probability), with the replica energies recomputed from
+ * the current state and the pair parity from the sweep counter. */
 xy_status xy_pt_swap(xy_batch *b, void *stream);
 
-/* The replica energies E = -sum over links cos(theta_i - theta_j) (Eq. HXY)
- * that the last tempering step used, by replica slot: copies
- * double[n_graphs][n_T slots] into caller-owned device memory d_out,
+/* The replica energies E = -sum over links cos(theta_i - theta_j) (Sec. 2,
+ * Eq. HXY) that the last tempering step (App. B) used, by replica slot:
+ * copies double[n_graphs][n_T slots] into caller-owned device memory d_out,
  * asynchronously on `stream`.  Defined after a sweep with tempering or an
- * xy_pt_swap; the fixed-point path sums them from FP32 link energies (Sec. 4,
- * parallel tempering). */
+ * xy_pt_swap; the fixed-point path sums them from FP32 link energies in FP64. */
 xy_status xy_pt_energies(xy_batch *b, double *d_out, void *stream);
 
 /* Synchronous copies of the state (checkpoint, tests).  Host layout:
@@ -200,9 +208,16 @@ xy_status xy_get_counters(xy_batch *b, int *n_records, uint64_t *pt_accepted,
  * Sweeps are counted from the enabling call.  d_log = NULL disables. */
 xy_status xy_decision_log(xy_batch *b, uint8_t *d_log, int max_sweeps);
 
-/* Captures `chunk` sweeps of the given shape into a HIP graph that later
- * xy_sweep calls replay (chunk = 0 turns it off).  chunk must be a multiple of
- * meas_every and of 2 (PT parity) when those are used. */
+/* HIP-graph replay: xy_sweep captures `chunk` sweeps of its shape (n_or,
+ * pt_every, meas_every, stream) into a HIP graph on first use and replays it
+ * for every whole chunk of later calls of the same shape (chunk = 0 turns it
+ * off; a non-null stream is then required).  The captured tempering and
+ * record flags repeat with P = lcm(pt_every, meas_every) (0 counting as 1):
+ * a replay starts only at a sweep index congruent modulo P to the one it was
+ * captured at, and direct launches reach that index first (chunk a multiple
+ * of P keeps every later chunk aligned).  Replays and direct launches give
+ * identical trajectories.  A ladder change (xy_sweep's T) needs no new
+ * capture: the kernels read 1/T from device memory. */
 xy_status xy_batch_use_graph(xy_batch *b, int chunk);
 
 /* Kernel timing for roofline reports: while enabled, every xy_sweep records a
@@ -210,12 +225,12 @@ xy_status xy_batch_use_graph(xy_batch *b, int chunk);
  * fix16 sweep kernels and the fix16 phase-form colour-phase kernels, or the
  * colour-phase kernels of an FP64 sweep).  When every sample is in the phase
  * form and its samples run as two or more stream groups, the groups fork from
- * the caller's stream once per xy_sweep call and each runs its own energies,
- * tempering and records; the event pair then brackets the whole call, whose
- * sweeps it counts.  HIP graph replay is bypassed meanwhile.  xy_kernel_time
- * synchronises the stream of the last sweep, returns the summed elapsed
- * milliseconds and the number of timed sweeps since timing was enabled, and
- * keeps timing on. */
+ * the caller's stream once per run of direct launches and each runs its own
+ * energies, tempering and records; the event pair then brackets that whole
+ * run, whose sweeps it counts.  A HIP-graph replay is bracketed as a whole
+ * (all kernels of its chunk of sweeps).  xy_kernel_time synchronises the
+ * stream of the last sweep, returns the summed elapsed milliseconds and the
+ * number of timed sweeps since timing was enabled, and keeps timing on. */
 xy_status xy_kernel_timing(xy_batch *b, int enable);
 xy_status xy_kernel_time(xy_batch *b, double *ms_total, int *n_timed);
 

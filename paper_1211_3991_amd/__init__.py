@@ -132,8 +132,21 @@ class Batch:
         st = self._stream if self._stream is not None else self._torch.cuda.current_stream(self.device)
         return ctypes.c_void_p(st.cuda_stream)
 
-    def sweep(self, n_sweeps, n_or=5, pt_every=1, meas_every=32):
-        _lib.call("xy_sweep", self._h, int(n_sweeps), int(n_or), int(pt_every), int(meas_every), self._s())
+    def sweep(self, n_sweeps, n_or=5, pt_every=1, meas_every=32, T=None):
+        """n_sweeps sweeps; T (per-sample ladders [G, n_T] or one ladder [n_T])
+        replaces the temperature of every index from this call on."""
+        t = None
+        if T is not None:
+            t = np.asarray(T, dtype=np.float64)
+            if t.ndim == 1:
+                t = np.tile(t, (self.G, 1))
+            if t.shape != (self.G, self.R):
+                raise ValueError("T must be [n_T] or [n_graphs, n_T]")
+            t = np.ascontiguousarray(t)
+        _lib.call("xy_sweep", self._h, _ptr(t), int(n_sweeps), int(n_or), int(pt_every), int(meas_every),
+                  self._s())
+        if t is not None:
+            self.T = t
 
     def use_graph(self, chunk):
         _lib.call("xy_batch_use_graph", self._h, int(chunk))

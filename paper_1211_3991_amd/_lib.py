@@ -56,7 +56,7 @@ _sigs = {
     "xy_graph_free": ([_vp], None),
     "xy_batch_sizes": ([_vp, _i32, _i32, _i32, _i32, ctypes.POINTER(Sizes)], _i32),
     "xy_batch_init": ([ctypes.POINTER(_vp), _vp, _i32, _i32, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp], _i32),
-    "xy_sweep": ([_vp, _i32, _i32, _i32, _i32, _vp], _i32),
+    "xy_sweep": ([_vp, _vp, _i32, _i32, _i32, _i32, _vp], _i32),
     "xy_measure": ([_vp, _vp, _vp], _i32),
     "xy_pt_energies": ([_vp, _vp, _vp], _i32),
     "xy_pt_swap": ([_vp, _vp], _i32),

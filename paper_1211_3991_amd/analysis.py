@@ -147,7 +147,7 @@ def u4_crossing(T, rec_small, rec_large, discard=0.5):
     """Crossing temperature of the disorder-averaged U4 (Sec. 3, ratio of
     disorder averages) of two sizes, with a jackknife error over the samples
     of both sizes (independent sets: the leave-one-out variances add).
-    Sec. 5 estimates T_c from the crossing of U4(T, N) with U4(T, N/4)."""
+    Sec. 4 estimates T_c from the crossing of U4(T, N) with U4(T, N/4)."""
     a4, a2 = u4_samples(rec_small, discard)
     b4, b2 = u4_samples(rec_large, discard)
 
@@ -175,7 +175,7 @@ def u4_crossing(T, rec_small, rec_large, discard=0.5):
 
 def fss_tc(N, T_cross, nu_bar):
     """T_c from crossing temperatures T(N) under T(N) = C N^(-1/nu_bar) + T_c
-    (Sec. 5): least squares in (N^(-1/nu_bar), T).  Returns (T_c, C)."""
+    (Sec. 4): least squares in (N^(-1/nu_bar), T).  Returns (T_c, C)."""
     x = np.asarray(N, dtype=np.float64) ** (-1.0 / nu_bar)
     A = np.stack([np.ones_like(x), x], axis=1)
     (tc, c), *_ = np.linalg.lstsq(A, np.asarray(T_cross, dtype=np.float64), rcond=None)
@@ -268,7 +268,7 @@ def _jackknife_sizes(est, per_size):
 
 
 def nu_bar_from_u4(T, N, records, u_target, discard=0.5):
-    """nu_bar from dU4/dT at fixed U4 (Sec. 5, Eq. U4dot): |dU4/dT| at the
+    """nu_bar from dU4/dT at fixed U4 (Sec. 4, Eq. U4dot): |dU4/dT| at the
     temperature where U4(T, N) = u_target grows as N^(1/nu_bar).  records:
     one [n_rec, G, n_T, 8] array per size N.  Returns (nu_bar, error), the
     error a jackknife over the samples of every size."""
@@ -289,7 +289,7 @@ def nu_bar_from_u4(T, N, records, u_target, discard=0.5):
 
 
 def gamma_over_nu_bar(T, N, records, T_ref, discard=0.5):
-    """gamma / nu_bar from chi = N <|m|^2> at T_ref (Sec. 3, Eq. chi; Sec. 5):
+    """gamma / nu_bar from chi = N <|m|^2> at T_ref (Sec. 3, Eq. chi; Sec. 4):
     chi(T_ref, N) ~ N^(gamma/nu_bar), chi linearly interpolated along the
     ladder.  Returns (gamma/nu_bar, jackknife error over samples)."""
     T = np.asarray(T, dtype=np.float64)
@@ -317,7 +317,7 @@ def _eta_curve(T, L, m2_means, r):
 
 
 def eta_of_T(T, L, records, r=1.0 / 16, discard=0.5):
-    """eta(T) on a square L x L lattice (Sec. 5, the square-lattice limit,
+    """eta(T) on a square L x L lattice (Sec. 4, the square-lattice limit,
     Eq. chi_SR): chi = N <|m|^2> ~ L^(2 - eta) (ln L)^(-2r) at each ladder
     temperature, fitted over the sizes (least squares of ln chi + 2r ln ln L
     against ln L; r = 1/16).  records: one [n_rec, G, n_T, 8] array per size
@@ -332,7 +332,7 @@ def eta_of_T(T, L, records, r=1.0 / 16, discard=0.5):
 
 def t_eta(T, L, records, eta_target=0.25, r=1.0 / 16, discard=0.5):
     """The temperature where eta(T) of eta_of_T reaches eta_target (the KT
-    value 1/4 locates T_c, Sec. 5), by linear interpolation along the ladder,
+    value 1/4 locates T_c, Sec. 4), by linear interpolation along the ladder,
     with a jackknife error over the samples of each size.  Returns (T, error);
     T is None when eta does not cross the target on the ladder."""
     T = np.asarray(T, dtype=np.float64)

@@ -59,7 +59,12 @@ struct xy_batch {
     hipGraphExec_t gexec = nullptr;
     hipStream_t gstream = nullptr;
     int g_n_or = -1, g_pt = -1, g_meas = -1;
-    uint32_t g_phase = 0;   // host_sweep modulo the pattern period at capture time
+    uint64_t g_phase = 0;   // host_sweep modulo the pattern period at capture time
+    uint64_t g_period = 0;  // period of the tempering / record pattern of the captured chunk
+    // temperature ladder by temperature index: host copy of the last upload
+    double *d_beta = nullptr;
+    std::vector<double> beta_host;
+    hipEvent_t ev_beta = nullptr;   // the last ladder upload (the host copy may be reused after it)
     // kernel timing (event pairs around the dominant kernel of each sweep)
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -549,6 +554,8 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
             sot[k] = k % R;
             tos[k] = k % R;
         }
+        b->beta_host.assign(beta, beta + (size_t)G * R);
+        b->d_beta = reinterpret_cast<double *>(static_cast<unsigned char *>(d_work) + wl.beta);
 
         hipError_t e;
         if ((e = hipMemcpyAsync(d_graph, gimg.data(), gimg.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
@@ -709,64 +716,42 @@ hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream
 
 bool flag_at(uint32_t sweep, int every) { return every > 0 && (sweep + 1) % (uint32_t)every == 0; }
 
-}  // namespace
-
-extern "C" xy_status xy_sweep(xy_batch *b, int n_sweeps, int n_or, int pt_every, int meas_every, void *stream)
+uint64_t gcd_u64(uint64_t a, uint64_t c)
 {
-    if (!b) return set_error(XY_EINVAL, "xy_sweep: batch is NULL");
-    if (n_sweeps < 0 || n_or < 0 || n_or > 255 || pt_every < 0 || meas_every < 0)
-        return set_error(XY_EINVAL, "xy_sweep: bad arguments");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    int done = 0;
-    // HIP graph replay: the captured chunk starts at a sweep index congruent
-    // to the one it was captured at, modulo the PT/measurement period.
-    if (b->chunk > 0 && !b->timing) {
-        if (!s) return set_error(XY_EINVAL, "xy_sweep: HIP graph capture needs a non-null stream");
-        const uint32_t period = (uint32_t)std::max({2, pt_every, meas_every});
-        while (n_sweeps - done >= b->chunk) {
-            const bool shape_ok = b->gexec && b->g_n_or == n_or && b->g_pt == pt_every && b->g_meas == meas_every &&
-                                  b->gstream == s && (b->host_sweep % period) == b->g_phase;
-            if (!shape_ok) {
-                if ((b->host_sweep % period) != 0) break;   // align by direct launches first
-                if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
-                hipGraph_t graph = nullptr;
-                hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-                if (e != hipSuccess) return hip_err(e, "xy_sweep capture");
-                uint32_t sw = b->host_sweep;
-                if (b->indep) e = fork_groups(b, s);
-                for (int k = 0; k < b->chunk && e == hipSuccess; ++k, ++sw)
-                    e = enqueue_sweep(b, n_or, flag_at(sw, pt_every), flag_at(sw, meas_every), s);
-                if (b->indep && e == hipSuccess) e = join_groups(b, s);
-                hipError_t e2 = hipStreamEndCapture(s, &graph);
-                if (e == hipSuccess) e = e2;
-                if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
-                if (graph) (void)hipGraphDestroy(graph);
-                if (e != hipSuccess) { b->gexec = nullptr; return hip_err(e, "xy_sweep graph"); }
-                b->g_n_or = n_or; b->g_pt = pt_every; b->g_meas = meas_every; b->gstream = s;
-                b->g_phase = b->host_sweep % period;
-            }
-            const hipError_t e = hipGraphLaunch(b->gexec, s);
-            if (e != hipSuccess) return hip_err(e, "xy_sweep graph launch");
-            b->host_sweep += (uint32_t)b->chunk;
-            done += b->chunk;
-        }
-    }
-    if (done == n_sweeps) return XY_OK;
-    // independent groups: one fork and one join for the remaining sweeps,
-    // timed as a whole (the colour phases and the per-group tails)
+    while (c) { const uint64_t t = a % c; a = c; c = t; }
+    return a;
+}
+
+// Period of the per-sweep pattern a captured chunk bakes in: tempering after
+// sweeps with (sweep + 1) % pt_every == 0 and records after sweeps with
+// (sweep + 1) % meas_every == 0 repeat with lcm(pt_every, meas_every).  (The
+// pair parity of a tempering step is read from the device's sweep counter,
+// so it is not baked in.)
+uint64_t pattern_period(int pt_every, int meas_every)
+{
+    const uint64_t a = pt_every > 0 ? (uint64_t)pt_every : 1u, c = meas_every > 0 ? (uint64_t)meas_every : 1u;
+    return a / gcd_u64(a, c) * c;
+}
+
+// n sweeps by direct launches.  With independent stream groups: one fork and
+// one join around them, and with timing one event pair around the whole.
+hipError_t run_direct(xy_batch *b, int n, int n_or, int pt_every, int meas_every, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipError_t e = hipSuccess;
     if (b->indep) {
         if (b->timing) {
             e = next_events(b, &ev0, &ev1);
             if (e == hipSuccess) e = hipEventRecord(ev0, s);
-            b->event_sweeps.push_back(n_sweeps - done);
+            if (e != hipSuccess) return e;
+            b->event_sweeps.push_back(n);
             b->timed_stream = s;
         }
-        if (e == hipSuccess) e = fork_groups(b, s);
-        if (e != hipSuccess) return hip_err(e, "xy_sweep");
+        e = fork_groups(b, s);
+        if (e != hipSuccess) return e;
     }
-    for (; done < n_sweeps && e == hipSuccess; ++done) {
+    for (int k = 0; k < n && e == hipSuccess; ++k) {
         const uint32_t sw = b->host_sweep;
         e = enqueue_sweep(b, n_or, flag_at(sw, pt_every), flag_at(sw, meas_every), s);
         if (e == hipSuccess) b->host_sweep++;
@@ -776,6 +761,108 @@ extern "C" xy_status xy_sweep(xy_batch *b, int n_sweeps, int n_or, int pt_every,
         if (e == hipSuccess) e = e2;
         if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
     }
+    return e;
+}
+
+// Captures b->chunk sweeps starting at the current sweep into b->gexec.  The
+// graph holds no timing events: a replay is timed as a whole.
+hipError_t capture_chunk(xy_batch *b, int n_or, int pt_every, int meas_every, uint64_t period, hipStream_t s)
+{
+    if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+    const bool timing = b->timing;
+    b->timing = false;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        uint32_t sw = b->host_sweep;
+        if (b->indep) e = fork_groups(b, s);
+        for (int k = 0; k < b->chunk && e == hipSuccess; ++k, ++sw)
+            e = enqueue_sweep(b, n_or, flag_at(sw, pt_every), flag_at(sw, meas_every), s);
+        if (b->indep && e == hipSuccess) e = join_groups(b, s);
+        const hipError_t e2 = hipStreamEndCapture(s, &graph);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+    b->timing = timing;
+    if (e != hipSuccess) { b->gexec = nullptr; return e; }
+    b->g_n_or = n_or; b->g_pt = pt_every; b->g_meas = meas_every; b->gstream = s;
+    b->g_period = period;
+    b->g_phase = b->host_sweep % period;
+    return hipSuccess;
+}
+
+// New temperature ladder by temperature index (the slot labels are kept):
+// beta is uploaded on s from a host copy that the batch keeps until the
+// upload has been read (an event waits for the previous one first).
+xy_status set_ladder(xy_batch *b, const double *T, hipStream_t s)
+{
+    const size_t GR = (size_t)b->G * b->R;
+    for (size_t k = 0; k < GR; ++k)
+        if (!(T[k] > 0.0) || !std::isfinite(T[k])) return set_error(XY_EINVAL, "xy_sweep: temperatures must be finite and > 0");
+    hipError_t e = hipSuccess;
+    if (!b->ev_beta) e = hipEventCreateWithFlags(&b->ev_beta, hipEventDisableTiming);
+    else e = hipEventSynchronize(b->ev_beta);
+    if (e != hipSuccess) return hip_err(e, "xy_sweep ladder");
+    for (size_t k = 0; k < GR; ++k) b->beta_host[k] = 1.0 / T[k];
+    e = hipMemcpyAsync(b->d_beta, b->beta_host.data(), 8 * GR, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(b->ev_beta, s);
+    return e == hipSuccess ? XY_OK : hip_err(e, "xy_sweep ladder");
+}
+
+}  // namespace
+
+extern "C" xy_status xy_sweep(xy_batch *b, const double *T, int n_sweeps, int n_or, int pt_every, int meas_every,
+                              void *stream)
+{
+    if (!b) return set_error(XY_EINVAL, "xy_sweep: batch is NULL");
+    if (n_sweeps < 0 || n_or < 0 || n_or > 255 || pt_every < 0 || meas_every < 0)
+        return set_error(XY_EINVAL, "xy_sweep: bad arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (b->chunk > 0 && !s) return set_error(XY_EINVAL, "xy_sweep: HIP graph capture needs a non-null stream");
+    if (T) {
+        const xy_status st = set_ladder(b, T, s);
+        if (st != XY_OK) return st;
+    }
+    int done = 0;
+    hipError_t e = hipSuccess;
+    // HIP graph replay: a captured chunk is valid where the sweep index is
+    // congruent to the one it was captured at, modulo the period of its
+    // tempering / record pattern; in between, direct launches realign it.
+    if (b->chunk > 0) {
+        const uint64_t period = pattern_period(pt_every, meas_every);
+        while (e == hipSuccess && n_sweeps - done >= b->chunk) {
+            const bool same = b->gexec && b->g_n_or == n_or && b->g_pt == pt_every && b->g_meas == meas_every &&
+                              b->gstream == s && b->g_period == period;
+            if (same) {
+                const uint64_t ph = b->host_sweep % period;
+                if (ph != b->g_phase) {
+                    const uint64_t k = (b->g_phase + period - ph) % period;   // sweeps to the captured phase
+                    if (k > (uint64_t)(n_sweeps - done - b->chunk)) break;
+                    e = run_direct(b, (int)k, n_or, pt_every, meas_every, s);
+                    done += (int)k;
+                    continue;
+                }
+            } else {
+                e = capture_chunk(b, n_or, pt_every, meas_every, period, s);
+                if (e != hipSuccess) return hip_err(e, "xy_sweep graph capture");
+            }
+            hipEvent_t ev0 = nullptr, ev1 = nullptr;
+            if (b->timing) {
+                e = next_events(b, &ev0, &ev1);
+                if (e == hipSuccess) e = hipEventRecord(ev0, s);
+                if (e != hipSuccess) break;
+                b->event_sweeps.push_back(b->chunk);
+                b->timed_stream = s;
+            }
+            e = hipGraphLaunch(b->gexec, s);
+            if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
+            if (e != hipSuccess) break;
+            b->host_sweep += (uint32_t)b->chunk;
+            done += b->chunk;
+        }
+    }
+    if (e == hipSuccess) e = run_direct(b, n_sweeps - done, n_or, pt_every, meas_every, s);
     return e == hipSuccess ? XY_OK : hip_err(e, "xy_sweep");
 }
 
@@ -1056,5 +1143,9 @@ extern "C" void xy_batch_free(xy_batch *b)
     if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     for (hipEvent_t ev : b->ev_join) (void)hipEventDestroy(ev);
     for (hipStream_t st : b->aux) (void)hipStreamDestroy(st);
+    if (b->ev_beta) {
+        (void)hipEventSynchronize(b->ev_beta);   // the host copy of the ladder is read until then
+        (void)hipEventDestroy(b->ev_beta);
+    }
     delete b;
 }

@@ -1,5 +1,5 @@
 """Finite-size-scaling run of the paper's method on one family of graphs
-(Sec. 4 and Sec. 5): equilibrium sweeps with parallel tempering on the GPU
+(Sec. 4 and App. C): equilibrium sweeps with parallel tempering on the GPU
 path for several sizes, then the critical temperature from the crossings of
 U4(T, N) with U4(T, N/4) extrapolated with T(N) = C N^(-1/nu_bar) + T_c, nu_bar
 from dU4/dT at fixed U4 (Eq. U4dot), and gamma/nu_bar from chi at a

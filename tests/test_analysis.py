@@ -91,7 +91,7 @@ def test_bethe_tc():
     # I1/I0 at beta = 1 and 0.1 (tabulated Bessel ratios) give T = 1 and 10
     assert abs(analysis.bethe_tc(1.0 / 0.446389965896535) - 1.0) < 1e-10
     assert abs(analysis.bethe_tc(1.0 / 0.049937603987939) - 10.0) < 1e-8
-    # the analytic value for the Erdos-Renyi graph of mean degree 4 (Sec. 5)
+    # the analytic value for the Erdos-Renyi graph of mean degree 4 (Sec. 4)
     assert abs(analysis.bethe_tc(4.0) - 1.9361) < 1e-4
 
 
@@ -160,7 +160,7 @@ def test_u4_slope_at():
 
 def test_eta_and_kt_temperature_from_exact_scaling():
     """chi = L^(2 - eta(T)) (ln L)^(-1/8) c(T) with eta(T) = 1/4 + 1.5 (T - 0.894)
-    (the square-lattice form of Sec. 5, Eq. chi_SR): eta_of_T returns eta(T)
+    (the square-lattice form of Sec. 4, Eq. chi_SR): eta_of_T returns eta(T)
     and t_eta the temperature where eta = 1/4, exactly; with per-sample noise
     the jackknife error is finite and covers it.  A dropped log correction
     (r = 0) moves the answer, so the correction is pinned too."""

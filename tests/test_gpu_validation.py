@@ -1,5 +1,5 @@
 """Validation of the GPU path against the paper's critical temperature in the
-Erdos-Renyi limit (Sec. 5, subsection on the Erdos-Renyi limit; Table 2,
+Erdos-Renyi limit (Sec. 4, subsection on the Erdos-Renyi limit; Table 2,
 column rho = 0).
 
 A Levy graph with rho = 0 and z = 4 is an Erdos-Renyi graph of mean degree 4
@@ -48,7 +48,7 @@ def test_erdos_renyi_z4_critical_temperature_and_exponents():
 
 
 def test_free_boundary_rho_10_3_critical_temperature():
-    """Free boundaries at rho = 10/3, z = 4 (Sec. 5, the non-mean-field regime;
+    """Free boundaries at rho = 10/3, z = 4 (Sec. 4, the non-mean-field regime;
     the inset with free boundaries gives T_c = 1.53(2) and nu_bar = 2.24(4)):
     the crossings of L = 16 ... 128, extrapolated with the paper's nu_bar, give
     T_c within three standard errors plus the paper's 0.02."""

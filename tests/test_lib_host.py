@@ -124,7 +124,7 @@ def test_batch_argument_errors_without_device():
     st = raw.xy_batch_init(ctypes.byref(h), garr, 1, 4, T.ctypes.data_as(ctypes.c_void_p), 1,
                            seeds.ctypes.data_as(ctypes.c_void_p), 0, None, None, None, None, None)
     assert st == _lib.XY_EINVAL and b"NULL device buffer" in raw.xy_last_error()
-    assert raw.xy_sweep(None, 1, 5, 1, 1, None) == _lib.XY_EINVAL
+    assert raw.xy_sweep(None, None, 1, 5, 1, 1, None) == _lib.XY_EINVAL
     assert raw.xy_measure(None, None, None) == _lib.XY_EINVAL
 
 

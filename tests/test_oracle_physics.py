@@ -264,3 +264,44 @@ def test_infinite_temperature_moments():
     assert abs(F - 1) < 4.5 * eF
     U4, eU = jackknife_fn(lambda a, b: b / (a * a) - 1, [rec[:, 0, 1], rec[:, 0, 2]])
     assert abs(U4 - (1 - 1 / n)) < 4.5 * eU
+
+
+# ------------------------------------------------------- initial state (pinned)
+def test_initial_directions_uniform_and_independent():
+    """The random start (the workloads' "spins initialised uniform in
+    [0, 2 pi)") is an independent uniform direction per (seed, slot, site):
+    unit norm; the angle's Fourier moments <cos k theta>, <sin k theta> vanish
+    for k = 1..8 (a point drawn in the square instead of the disk leaves
+    <cos 4 theta> = 3 - pi = -0.14); the angle passes a Kolmogorov-Smirnov
+    test against U[0, 2 pi); and angles of lattice neighbours, of two slots of
+    one site and of two seeds are uncorrelated (a shared or reused stream
+    would correlate them)."""
+    from scipy import stats
+    L, n_T = 64, 8
+    n = L * L
+    e = np.array([(i, (i + 1) % n) for i in range(0, n, 2)], np.int32)   # any graph: the start ignores links
+    col = np.zeros(n, np.int32)
+    col[1::2] = 1
+    T = np.linspace(1.0, 2.0, n_T)
+    angles = []
+    for seed in (3, 4):
+        sim = oracle.Sim(n, e, col, L, T, seed)
+        sim.init_random()
+        xy_, _, sw = sim.get_state()
+        assert sw == 0
+        assert np.allclose(np.hypot(xy_[..., 0], xy_[..., 1]), 1.0, rtol=0, atol=4e-16)
+        angles.append(np.arctan2(xy_[..., 1], xy_[..., 0]) % (2 * np.pi))   # [slot, site]
+    th = np.concatenate([a.ravel() for a in angles])
+    se = 1.0 / np.sqrt(2 * th.size)             # std of <cos k theta> for uniform theta
+    for k in range(1, 9):
+        assert abs(np.cos(k * th).mean()) < 4.5 * se, k
+        assert abs(np.sin(k * th).mean()) < 4.5 * se, k
+    assert stats.kstest(th / (2 * np.pi), "uniform").pvalue > 1e-4
+    a = angles[0]
+    grid = a.reshape(n_T, L, L)
+    pairs = {"x neighbours": (grid[:, :, :-1], grid[:, :, 1:]), "y neighbours": (grid[:, :-1, :], grid[:, 1:, :]),
+             "slots 0/1": (a[0], a[1]), "seeds 3/4": (angles[0], angles[1])}
+    for name, (u, v) in pairs.items():
+        c = np.cos(u - v).ravel()                # uniform and independent: <cos(u - v)> = 0
+        assert abs(c.mean()) < 4.5 / np.sqrt(2 * c.size), name
+        assert not np.array_equal(u, v), name
