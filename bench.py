@@ -63,14 +63,27 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def time_gpu(wl, precision, steps, warmup, graphs, torch, xy, n_or=None, form=None, phase_streams=0):
-    """Times `steps` sweeps.  fix16: autotunes first, or takes `form` =
-    (trig, allow_unit) from an earlier tuning; phase_streams > 0 then fixes the
-    stream-group count of the phase-form samples."""
+def time_gpu(wl, precision, steps, warmup, graphs, torch, xy, n_or=None, form=None, phase_streams=0, replay=True,
+             direct=True):
+    """Times `steps` sweeps (fix16: autotunes first, or takes `form` =
+    (trig, allow_unit) from an earlier tuning; phase_streams > 0 then fixes
+    the stream-group count of the phase-form samples).
+
+    The timed window of `steps` sweeps is placed so that it ends on a
+    measurement sweep (it starts at a sweep index congruent to -steps modulo
+    meas_every, after at least `warmup` sweeps), so it always holds the
+    records of its share of the run.  With replay, the window is one replay
+    of a HIP graph of `steps` sweeps captured (and run once) during the
+    warm-up at the same phase; with direct, the same window is then timed
+    again by direct launches at the same phase."""
     n_or = wl.n_or if n_or is None else n_or
+    period = wl.meas_every if wl.meas_every > 0 else 1
+    phase = (-steps) % period
+    w0 = warmup + (phase - warmup) % period                    # >= warmup, congruent to phase
+    n_total = w0 + 3 * steps + 2 * phase + period
     stream = torch.cuda.Stream()
     b = xy.Batch(graphs, wl.T, precision=precision, seeds=[s.seed for s in wl.samples],
-                 max_records=max(1, (steps + warmup) // wl.meas_every + 1), stream=stream)
+                 max_records=n_total // max(wl.meas_every, 1) + 2, stream=stream)
     tune = None
     if precision == "fix16":
         if form is None:
@@ -79,25 +92,44 @@ def time_gpu(wl, precision, steps, warmup, graphs, torch, xy, n_or=None, form=No
             b.set_fix16_form(trig=form[0], allow_unit=form[1])
         if phase_streams:
             b.set_phase_streams(phase_streams)
-    b.sweep(warmup, n_or=n_or, pt_every=wl.pt_every, meas_every=wl.meas_every)
-    b.synchronize()
-    b.kernel_timing(True)
-    with torch.cuda.stream(stream):
-        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t0.record(stream)
-        b.sweep(steps, n_or=n_or, pt_every=wl.pt_every, meas_every=wl.meas_every)
-        t1.record(stream)
-        torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1)
-    k_ms, k_n = b.kernel_time()
-    b.kernel_timing(False)
+    kw = dict(n_or=n_or, pt_every=wl.pt_every, meas_every=wl.meas_every)
+    b.sweep(w0, **kw)                                          # direct warm-up, ends at the window's phase
+
+    def timed():
+        b.synchronize()
+        b.kernel_timing(True)
+        with torch.cuda.stream(stream):
+            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t0.record(stream)
+            b.sweep(steps, **kw)
+            t1.record(stream)
+            torch.cuda.synchronize()
+        k_ms, k_n = b.kernel_time()
+        b.kernel_timing(False)
+        return t0.elapsed_time(t1), k_ms / max(k_n, 1), k_n
+
+    out = {}
+    if replay:
+        b.use_graph(steps)
+        b.sweep(steps, **kw)                                   # capture at the window's phase, run once
+        b.sweep(phase, **kw)                                   # direct, back to that phase
+        ms, k_ms, k_n = timed()                                # one replay
+        out.update(ms=ms, kernel_ms=k_ms, kernel_n=k_n, launch="HIP graph replay")
+        b.use_graph(0)
+        b.sweep(phase, **kw)
+    if direct:
+        ms_d, k_ms_d, k_n_d = timed()
+        if not replay:
+            out.update(ms=ms_d, kernel_ms=k_ms_d, kernel_n=k_n_d, launch="direct")
+        out["direct_ms"] = ms_d
+        out["direct_kernel_ms"] = k_ms_d
     nrec, acc, tries = b.counters()
-    rec = b.records().cpu().numpy()
     n_groups = b.phase_streams() if precision == "fix16" else 1
     b.close()
-    return {"ms": ms, "kernel_ms": k_ms / max(k_n, 1), "kernel_n": k_n, "records": rec, "phase_streams": n_groups,
-            "pt_rate": float(acc.sum()) / max(float(tries.sum()), 1.0), "autotune": tune}
+    out.update(window=[w0 + (steps + phase if replay else 0), steps], records=nrec, phase_streams=n_groups,
+               pt_rate=float(acc.sum()) / max(float(tries.sum()), 1.0), autotune=tune)
+    return out
 
 
 def time_walk(xy):
@@ -207,6 +239,41 @@ def write_traffic(wl, paths, argv, phase_streams):
     print(json.dumps(out))
 
 
+def host_cpu():
+    """The host's core count (this process's affinity) and CPU model."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "model": model}
+
+
+def cpu_single_thread(wl_small, wl_large, large_sweeps=10):
+    """The oracle on one core: the whole plain L=16 workload (one sample, 4 T,
+    no tempering, measurement every sweep), and a slice of `large_sweeps`
+    sweeps of one sample of the large workload with tempering."""
+    import oracle
+    out = {}
+    for key, wl, n_sw in (("plain_l16", wl_small, wl_small.n_sweeps), ("slice", wl_large, large_sweeps)):
+        s = wl.samples[0]
+        e, _ = oracle.levy_graph(s.L, s.z, s.rho, s.seed)
+        col, _ = oracle.slo_colour(s.L * s.L, e)
+        sim = oracle.Sim(s.L * s.L, e, col, s.L, wl.T, s.seed)
+        sim.init_random()
+        t = time.perf_counter()
+        sim.run(n_sw, n_or=wl.n_or, pt_every=wl.pt_every, meas_every=wl.meas_every if key == "plain_l16" else 0)
+        dt = time.perf_counter() - t
+        upd = s.L * s.L * wl.n_T * (1 + wl.n_or) * n_sw
+        out[key] = {"value": round(upd / (dt * 1e9), 4), "unit": "spin updates/ns", "cores": 1,
+                    "sample": f"{wl.name}: sample 0, {n_sw} sweeps, {upd} updates in {dt:.1f} s"}
+    return out
+
+
 def cpu_baseline(wl, seconds, workers):
     """The oracle (sequential FP64 C) on the host cores: `workers` threads,
     each sweeping its own sample of the workload (all temperatures, PT every
@@ -263,10 +330,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--workload", default="headline_l256", choices=sorted(workloads.ALL))
     ap.add_argument("--precision", default="fix16", choices=["fix16", "fp64"])
-    ap.add_argument("--fp64-steps", type=int, default=8, help="sweeps of the FP64 plain comparison (0 = skip)")
+    ap.add_argument("--fp64-steps", type=int, default=32, help="sweeps of the FP64 plain comparison (0 = skip)")
+    ap.add_argument("--parity-sweeps", type=int, default=1024,
+                    help="sweeps of the fix16-vs-FP64 statistical comparison on the workload (0 = skip)")
+    ap.add_argument("--direct", action="store_true", help="time direct launches instead of HIP-graph replay")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle time budget (0 = skip)")
-    ap.add_argument("--cpu-workers", type=int, default=min(16, len(os.sched_getaffinity(0))),
-                    help="oracle threads, one sample each (default: the host cores, at most 16)")
+    ap.add_argument("--cpu-workers", type=int, default=len(os.sched_getaffinity(0)),
+                    help="oracle threads, one sample each (default: every host core this process may use)")
     ap.add_argument("--no-walk", action="store_true", help="skip the random-walk workload (App. A)")
     ap.add_argument("--split-steps", type=int, default=8,
                     help="sweeps of the Metropolis-only run that splits the rate into Met and OR (0 = skip)")
@@ -308,16 +378,18 @@ def main():
 
     wl = workloads.ALL[args.workload]()
     t = time.perf_counter()
-    graphs = [xy.Graph.levy(s.L, s.z, s.rho, s.seed) for s in wl.samples]
+    from paper_1211_3991_amd import parity as par
+    graphs = par.build_graphs(wl.samples)
     setup_s = time.perf_counter() - t
     print(f"# graphs built in {setup_s:.1f} s; colours per sample: "
           f"{sorted(set(g.n_colours for g in graphs))}", file=sys.stderr, flush=True)
 
     upd_per_sweep = wl.updates_per_sweep()
     main_run = time_gpu(wl, args.precision, args.steps, args.warmup, graphs, torch, xy,
-                        phase_streams=args.phase_streams)
+                        phase_streams=args.phase_streams, replay=not args.direct)
     value = upd_per_sweep * args.steps / (main_run["ms"] * 1e6)
-    print(f"# {args.precision}: {main_run['ms'] / args.steps:.3f} ms/sweep, {value:.1f} updates/ns",
+    print(f"# {args.precision}: {main_run['ms'] / args.steps:.3f} ms/sweep ({main_run['launch']}), "
+          f"{value:.1f} updates/ns; direct launches {main_run['direct_ms'] / args.steps:.3f} ms/sweep",
           file=sys.stderr, flush=True)
 
     z = wl.samples[0].z
@@ -325,7 +397,7 @@ def main():
     bpu = alg_bytes_per_update(b_s, z, wl.n_T)
     k_ms = main_run["kernel_ms"]
     achieved = bpu * upd_per_sweep / (k_ms * 1e6)   # GB/s over the sweep's launches of the dominant kernel
-    traffic = None
+    traffic, tr = None, {}
     if args.precision == "fix16" and os.path.exists(traffic_file(wl.name)):
         with open(traffic_file(wl.name)) as fh:
             tr = json.load(fh)
@@ -333,12 +405,14 @@ def main():
         if (tr.get("kernel_digest") == kernel_source_digest() and tr.get("workload") == wl.name
                 and tr.get("phase_streams") == main_run["phase_streams"]):
             traffic = tr["bytes_per_sweep"]
+        else:
+            tr = {}
     if args.precision == "fp64":
         kname = "k_fp64_phase (the 6·Q colour-phase launches of one sweep)"
     elif uses_phase_form(wl):
-        kname = ("k_fix16_phase (the colour-phase launches of one sweep: 6·Q per sample group, two groups on "
-                 "two streams, each group also running its own energies and tempering; timed by HIP events on the "
-                 "caller's stream around the fork, all sweeps of the call and the join, per sweep)")
+        kname = ("k_fix16_phase (the colour-phase launches of one sweep, 6·Q per sample group on its own stream, "
+                 "each group also running its own energies, tempering and records; timed by HIP events on the "
+                 "caller's stream around each replay of the captured window, per sweep)")
     else:
         kname = "k_fix16_sweep (one launch = one sweep of every (sample, slot))"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -347,10 +421,18 @@ def main():
                 "kernel": kname,
                 "kernel_ms": round(k_ms, 4), "alg_bytes_per_update": round(bpu, 3),
                 "updates_per_sweep": upd_per_sweep}
-    # the bound the kernel meets first: VALU issue, from the counted VALU
-    # instructions of the same launches (same digest rule as the traffic)
+    if traffic is not None:
+        meas = traffic / (k_ms * 1e6)
+        roofline.update(measured_gbs=round(meas, 1), measured_frac=round(meas / HBM_PEAK_GBS, 4),
+                        measured_bytes_per_update=tr["bytes_per_update"])
+        if tr.get("l2_read_bytes_per_sweep"):
+            roofline["l2_read_gbs"] = round(tr["l2_read_bytes_per_sweep"] / (k_ms * 1e6), 1)
+        if tr.get("l2_hit_rate") is not None:
+            roofline["l2_hit_rate"] = tr["l2_hit_rate"]
+    # VALU issue, from the counted VALU instructions of the same launches
+    # (same digest rule as the traffic)
     alu = None
-    if traffic is not None and tr.get("valu_lane_instr_per_sweep"):
+    if tr.get("valu_lane_instr_per_sweep"):
         lane = tr["valu_lane_instr_per_sweep"] / (k_ms * 1e-3) / 1e12
         alu = {"bound": "alu", "achieved": round(lane, 2), "peak": VALU_PEAK_TLANE, "unit": "T VALU lane-instr/s",
                "frac": round(lane / VALU_PEAK_TLANE, 4),
@@ -358,32 +440,62 @@ def main():
                "note": "peak: 256 CUs x 4 SIMDs x 64 lanes x 2.4 GHz / 2 cycles per wave instruction (the FP32 "
                        "157.3 TFLOP/s counting an FMA as 2); about 17 of the instructions per update are "
                        "transcendentals, which issue at about a third of that rate"}
+        if "trans_lane_instr_per_update" in tr:
+            # transcendentals occupy the SIMD about 3.4 times as long as an FMA
+            w = tr["valu_lane_instr_per_update"] + 2.4 * tr["trans_lane_instr_per_update"]
+            alu["weighted_frac"] = round(alu["frac"] * w / tr["valu_lane_instr_per_update"], 4)
+    # what binds: the larger of the measured HBM and VALU-issue utilisations
+    if traffic is not None and alu is not None:
+        u_hbm, u_alu = roofline["measured_frac"], alu.get("weighted_frac", alu["frac"])
+        roofline["binding"] = {"resource": "alu" if u_alu > u_hbm else "hbm", "hbm_measured_frac": u_hbm,
+                               "valu_frac": alu["frac"], "valu_weighted_frac": alu.get("weighted_frac"),
+                               "note": "neither is saturated: the rest of the time is the latency of the dependent "
+                                       "gathers (wave cycles waiting) and the launch ramp and tail"}
 
     fp64 = None
     if args.precision == "fix16" and args.fp64_steps > 0:
-        r = time_gpu(wl, "fp64", args.fp64_steps, 2, graphs, torch, xy)
+        r = time_gpu(wl, "fp64", args.fp64_steps, 2, graphs, torch, xy, replay=False)
         v64 = upd_per_sweep * args.fp64_steps / (r["ms"] * 1e6)
         fp64 = {"value": round(v64, 2), "unit": "spin updates/ns", "ms_per_step": round(r["ms"] / args.fp64_steps, 3),
-                "state": "FP64 unit vectors", "speedup_fix16_over_fp64": round(value / v64, 2)}
+                "state": "FP64 unit vectors", "speedup_fix16_over_fp64": round(value / v64, 2),
+                "window": r["window"], "launch": r["launch"]}
         print(f"# fp64 plain: {r['ms'] / args.fp64_steps:.3f} ms/sweep, {v64:.2f} updates/ns",
+              file=sys.stderr, flush=True)
+
+    parity = None
+    if args.precision == "fix16" and args.parity_sweeps > 0:
+        from paper_1211_3991_amd import parity as par
+        pr, _, _ = par.fix16_vs_fp64(wl, args.parity_sweeps, meas_every=4, n_bins=20, graphs=graphs)
+        parity = {k: pr[k] for k in ("sweeps", "meas_every", "keep", "records", "n_bins")}
+        for k in ("per_sample", "disorder", "drift"):
+            parity[k] = {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in pr[k].items()
+                         if kk != "outliers"}
+            parity[k]["outliers"] = pr[k]["outliers"][:8]
+        parity["max_rel_dev_disorder"] = {k: float(f"{v:.3g}") for k, v in pr["max_rel_dev_disorder"].items()}
+        parity["rel_err_disorder"] = {k: float(f"{v:.3g}") for k, v in pr["rel_err_disorder"].items()}
+        parity["r22_ok"] = par.r22_ok(pr)
+        parity["note"] = ("fix16 against the FP64 sweep (bit-tied to the oracle) from independent random starts: "
+                          "per (sample, T, observable) with jackknife errors over 20 time bins, and disorder-paired "
+                          "per (T, observable); the deviations are relative to the FP64 disorder average")
+        print(f"# parity: per-sample frac>3 {parity['per_sample']['frac_gt']}, chi2 {parity['per_sample']['chi2_dof']}; "
+              f"disorder frac>3 {parity['disorder']['frac_gt']}, chi2 {parity['disorder']['chi2_dof']}",
               file=sys.stderr, flush=True)
 
     split = None
     if args.split_steps > 0 and wl.n_or > 0:
         # Metropolis-only sweeps on the same batch shape and form; the OR rate
-        # follows from the difference of the kernel times (PT and measurement
-        # are outside the kernel time)
+        # follows from the difference of the kernel times
         tuned = main_run["autotune"]
         form = (tuned["trig"], tuned["allow_unit"]) if tuned and "trig" in tuned else None
         met = time_gpu(wl, args.precision, args.split_steps, 2, graphs, torch, xy, n_or=0, form=form,
-                       phase_streams=main_run["phase_streams"])
+                       phase_streams=main_run["phase_streams"], replay=not args.direct, direct=False)
         n_upd = upd_per_sweep // (1 + wl.n_or)
         or_ms = k_ms - met["kernel_ms"]
         split = {"met_only": round(n_upd / (met["kernel_ms"] * 1e6), 2),
                  "or_only": round(wl.n_or * n_upd / (or_ms * 1e6), 2) if or_ms > 0 else None,
                  "unit": "spin updates/ns (kernel time)", "met_kernel_ms": round(met["kernel_ms"], 4),
                  "note": "Metropolis-only sweeps (n_or=0, whose one sub-sweep also sums the energy for tempering) "
-                         "timed separately; OR from the difference"}
+                         "timed the same way; OR from the difference"}
         print(f"# split: Met {split['met_only']} / OR {split['or_only']} updates/ns", file=sys.stderr, flush=True)
 
     walk = None
@@ -392,7 +504,11 @@ def main():
         print(f"# random walk: {walk['value']} walker steps/ns, dbar {walk['dbar']} (formula {walk['dbar_formula']})",
               file=sys.stderr, flush=True)
 
-    cpu = cpu_baseline(wl, args.cpu_seconds, args.cpu_workers) if args.cpu_seconds > 0 else None
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = cpu_baseline(wl, args.cpu_seconds, args.cpu_workers)
+        cpu["host"] = host_cpu()
+        cpu["single_thread"] = cpu_single_thread(workloads.plain_fp64_l16(), wl)
     s0 = wl.samples[0]
     out = {
         "metric": "spin updates/ns at L=256 rho=3.5 (fixed-point batched vs FP64 plain), %HBM roof",
@@ -404,10 +520,15 @@ def main():
                    "n_T": wl.n_T, "T": [float(wl.T[0]), float(wl.T[-1])], "sweep": f"1 Metropolis + {wl.n_or} OR",
                    "pt_every": wl.pt_every, "meas_every": wl.meas_every,
                    "state": "uint16 angles, FP32 fields, FP64 accumulators" if args.precision == "fix16"
-                   else "FP64 unit vectors", "parallelism": "samples x temperatures on one GPU"},
+                   else "FP64 unit vectors", "parallelism": "samples x temperatures on one GPU",
+                   "launch": main_run["launch"], "timed_window": main_run["window"],
+                   "records_in_window": -(-args.steps // wl.meas_every) if wl.meas_every else 0},
+        "direct_launch": {"ms_per_step": round(main_run["direct_ms"] / args.steps, 4),
+                          "value": round(upd_per_sweep * args.steps / (main_run["direct_ms"] * 1e6), 2)},
         "roofline": roofline,
         "alu_roofline": alu,
         "fp64_plain": fp64,
+        "fix16_vs_fp64": parity,
         "sub_sweep_rates": split,
         "random_walk": walk,
         "cpu_baseline": cpu,

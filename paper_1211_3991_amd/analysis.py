@@ -348,3 +348,214 @@ def t_eta(T, L, records, eta_target=0.25, r=1.0 / 16, discard=0.5):
 
     t, err = _jackknife_sizes(est, per_size)
     return t, err
+
+
+def compare_chains(a, b, n_bins=20, z_bar=3.0):
+    """Statistical comparison of two independent sets of Markov chains on the
+    same graphs and ladder (e.g. the fixed-point and the FP64 sweep), as the
+    thermal averages of Sec. 3 would be compared:
+
+      a, b : kept records [n_rec, G, n_T, n_obs] (the equilibration cut
+             already applied), chain (s, k) of a and of b independent.
+
+    Per (sample, temperature, observable): the difference of the two thermal
+    averages over its error sigma = sqrt(sigma_a^2 + sigma_b^2), each sigma
+    the jackknife (for a mean: batch-means) error over n_bins contiguous time
+    bins.  Per (temperature, observable): the disorder-paired difference,
+    d_s = <O>_a,s - <O>_b,s averaged over the samples, over its standard
+    error from the sample-to-sample spread of d_s (valid whatever the
+    autocorrelation inside a chain, since the samples are independent).
+    Also the drift of each chain: first against second half of its kept
+    records, in units of its error.
+
+    Returns a dict with, for "per_sample", "disorder" and "drift", the number
+    of comparisons, the fraction with |z| > z_bar, chi^2/dof = mean(z^2),
+    max |z| and the outliers (index tuples and z)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if a.shape != b.shape or a.ndim != 4:
+        raise ValueError("a and b must both be [n_rec, G, n_T, n_obs]")
+    ba, bb = bin_means(a, n_bins), bin_means(b, n_bins)
+    ma, mb = ba.mean(axis=0), bb.mean(axis=0)
+    ea = ba.std(axis=0, ddof=1) / np.sqrt(n_bins)
+    eb = bb.std(axis=0, ddof=1) / np.sqrt(n_bins)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        z_ps = (ma - mb) / np.hypot(ea, eb)
+        d = ma - mb                                  # [G, n_T, n_obs]
+        G = d.shape[0]
+        z_dis = d.mean(axis=0) / (d.std(axis=0, ddof=1) / np.sqrt(G))
+        h = a.shape[0] // 2
+        drift = []
+        for x in (a, b):
+            q1, q2 = bin_means(x[:h], n_bins // 2), bin_means(x[h:2 * h], n_bins // 2)
+            e1 = q1.std(axis=0, ddof=1) / np.sqrt(q1.shape[0])
+            e2 = q2.std(axis=0, ddof=1) / np.sqrt(q2.shape[0])
+            drift.append((q2.mean(axis=0) - q1.mean(axis=0)) / np.hypot(e1, e2))
+        z_drift = np.stack(drift)                    # [2, G, n_T, n_obs]
+
+    def summary(z, max_list=50):
+        z = np.asarray(z)
+        ok = np.isfinite(z)
+        zf = z[ok]
+        out_idx = np.argwhere(ok & (np.abs(np.where(ok, z, 0.0)) > z_bar))
+        order = np.argsort(-np.abs(z[tuple(out_idx.T)])) if out_idx.size else []
+        outliers = [(tuple(int(v) for v in out_idx[k]), float(z[tuple(out_idx[k])])) for k in order[:max_list]]
+        return {"n": int(zf.size), "n_undefined": int((~ok).sum()),
+                "frac_gt": float(np.mean(np.abs(zf) > z_bar)) if zf.size else 0.0,
+                "chi2_dof": float(np.mean(zf ** 2)) if zf.size else 0.0,
+                "max_abs": float(np.max(np.abs(zf))) if zf.size else 0.0,
+                "mean": float(np.mean(zf)) if zf.size else 0.0, "outliers": outliers}
+
+    return {"per_sample": summary(z_ps), "disorder": summary(z_dis), "drift": summary(z_drift),
+            "z_bar": z_bar, "n_bins": n_bins, "records": int(a.shape[0]),
+            "z_per_sample": z_ps, "z_disorder": z_dis, "abs_diff_disorder": np.abs(d.mean(axis=0)),
+            "mean_a": ma, "mean_b": mb}
+
+
+# ---------------------------------------------------------------------------
+# App. C: joint finite-size-scaling fits
+# ---------------------------------------------------------------------------
+def _u4_target_temps(T, means, u_targets):
+    """T_f(U4_j, N) and dU4/dT there for every size (rows) and target
+    (columns) from per-size mean curves ((m4, m2sq) pairs); None if a curve
+    misses a target."""
+    tf = np.empty((len(means), len(u_targets)))
+    sl = np.empty_like(tf)
+    for a, (m4, m2sq) in enumerate(means):
+        U = m4 / m2sq - 1.0
+        for j, u in enumerate(u_targets):
+            hit = u4_slope_at(T, U, u)
+            if hit is None:
+                return None, None
+            tf[a, j], sl[a, j] = hit
+    return tf, sl
+
+
+def tf_joint_fit(Tf, N, common_x=True, x_fixed=None):
+    """Simultaneous fit of T_f(U4_j, N) = T_c + A_j N^(-x_j) (App. C, Eq.
+    Tfsscaling) over n_d data sets j (columns of Tf, rows = sizes N): common
+    T_c, set-dependent amplitudes A_j, and exponents x_j common to all sets
+    (common_x, the paper's choice for rho < 3.75) or one per set; x_fixed
+    fixes a common exponent (the fit is then linear).  Returns dict(T_c, A,
+    x)."""
+    from scipy.optimize import least_squares
+    Tf = np.asarray(Tf, dtype=np.float64)
+    lnN = np.log(np.asarray(N, dtype=np.float64))
+    n_sz, n_d = Tf.shape
+
+    def design(x):
+        # columns: T_c, then one amplitude per set
+        A = np.zeros((n_sz * n_d, 1 + n_d))
+        A[:, 0] = 1.0
+        for j in range(n_d):
+            A[j::n_d, 1 + j] = np.exp(-np.broadcast_to(x, (n_d,))[j] * lnN)
+        return A
+
+    y = Tf.ravel()                                   # size-major: row a, set j -> a * n_d + j
+    if x_fixed is not None:
+        coef = np.linalg.lstsq(design(float(x_fixed)), y, rcond=None)[0]
+        return {"T_c": float(coef[0]), "A": coef[1:].tolist(), "x": [float(x_fixed)] * n_d}
+    n_x = 1 if common_x else n_d
+
+    def resid(p):
+        x = np.full(n_d, p[0]) if common_x else p[:n_d]
+        coef = np.linalg.lstsq(design(x), y, rcond=None)[0]   # T_c and A_j are linear given x
+        return design(x) @ coef - y
+
+    fit = least_squares(resid, np.full(n_x, 0.5), bounds=(1e-3, 10.0), xtol=1e-14, ftol=1e-14, gtol=1e-14)
+    x = np.full(n_d, fit.x[0]) if common_x else fit.x
+    coef = np.linalg.lstsq(design(x), y, rcond=None)[0]
+    return {"T_c": float(coef[0]), "A": coef[1:].tolist(), "x": [float(v) for v in x]}
+
+
+def tc_from_u4_sets(T, N, records, u_targets, common_x=True, x_fixed=None, discard=0.5):
+    """T_c by the joint fit of Eq. Tfsscaling (App. C) on the temperatures
+    where the disorder-averaged U4 (ratio of averages) of each size reaches
+    each value of u_targets; records: one [n_rec, G, n_T, 8] array per size
+    N.  Returns dict(T_c, T_c_error, x, x_error, T_f), errors by a jackknife
+    over the samples of every size."""
+    per_size = [u4_samples(r, discard) for r in records]
+
+    def fit(means):
+        tf, _ = _u4_target_temps(T, means, u_targets)
+        return None if tf is None else tf_joint_fit(tf, N, common_x, x_fixed)
+
+    full = fit([(a.mean(0), b.mean(0)) for a, b in per_size])
+    if full is None:
+        raise ValueError("a U4 target lies outside some size's curve on the ladder")
+    tc, tc_err = _jackknife_sizes(lambda m: (lambda f: None if f is None else f["T_c"])(fit(m)), per_size)
+    x_err = None
+    if x_fixed is None and common_x:
+        _, x_err = _jackknife_sizes(lambda m: (lambda f: None if f is None else f["x"][0])(fit(m)), per_size)
+    tf, _ = _u4_target_temps(T, [(a.mean(0), b.mean(0)) for a, b in per_size], u_targets)
+    return {"T_c": full["T_c"], "T_c_error": tc_err, "x": full["x"], "x_error": x_err, "A": full["A"],
+            "T_f": tf.tolist(), "u_targets": list(map(float, u_targets))}
+
+
+def nu_bar_joint(T, N, records, u_targets, discard=0.5):
+    """nu_bar from ln dU4/dT at fixed U4 = c_j + (1/nu_bar) ln N (App. C, Eq.
+    scaling_lndotU4), fitted simultaneously over the sets U4_j with one
+    intercept per set and a common slope.  Returns (nu_bar, jackknife error
+    over the samples of every size)."""
+    per_size = [u4_samples(r, discard) for r in records]
+    lnN = np.log(np.asarray(N, dtype=np.float64))
+    n_d = len(u_targets)
+
+    def est(means):
+        _, sl = _u4_target_temps(T, means, u_targets)
+        if sl is None:
+            return None
+        y = np.log(np.abs(sl)).ravel()               # size-major
+        A = np.zeros((y.size, 1 + n_d))
+        A[:, 0] = np.repeat(lnN, n_d)
+        for j in range(n_d):
+            A[j::n_d, 1 + j] = 1.0
+        inv_nu = np.linalg.lstsq(A, y, rcond=None)[0][0]
+        return 1.0 / inv_nu
+
+    return _jackknife_sizes(est, per_size)
+
+
+def size_exponent_curve(T, N, records, kind, discard=0.5):
+    """x(T) at every ladder temperature from the sizes' disorder-averaged
+    <|m|^2>: kind "chi": ln chi = cte + x ln N with chi = N <|m|^2> (App. C,
+    Eq. chiscaling; x(T_c) = gamma/nu_bar); kind "m": (1/2) ln <|m|^2> =
+    cte - x ln N (Eq. mscaling; x(T_c) = beta/nu_bar).  Returns (x, error),
+    arrays over the ladder, errors by a jackknife over the samples."""
+    if kind not in ("chi", "m"):
+        raise ValueError("kind is 'chi' or 'm'")
+    Ns = np.asarray(N, dtype=np.float64)
+    per_size = []
+    for r in records:
+        rec = np.asarray(r, dtype=np.float64)
+        rec = rec[int(rec.shape[0] * discard):]
+        per_size.append((rec.mean(axis=0)[:, :, M2],))
+
+    def curve(means):
+        if kind == "chi":
+            y = np.stack([np.log(n * m2) for n, (m2,) in zip(Ns, means)])
+            return np.polyfit(np.log(Ns), y, 1)[0]
+        y = np.stack([0.5 * np.log(m2) for (m2,) in means])
+        return -np.polyfit(np.log(Ns), y, 1)[0]
+
+    x = curve([(m2.mean(0),) for (m2,) in per_size])
+    err = np.array([_jackknife_sizes(lambda m, k=k: curve(m)[k], per_size)[1] for k in range(len(T))])
+    return x, err
+
+
+def beta_over_nu_bar(T, N, records, T_ref, discard=0.5):
+    """beta / nu_bar = x(T_ref) of Eq. mscaling (App. C), x linearly
+    interpolated along the ladder.  Returns (value, jackknife error)."""
+    T = np.asarray(T, dtype=np.float64)
+    Ns = np.asarray(N, dtype=np.float64)
+    per_size = []
+    for r in records:
+        rec = np.asarray(r, dtype=np.float64)
+        rec = rec[int(rec.shape[0] * discard):]
+        per_size.append((rec.mean(axis=0)[:, :, M2],))
+
+    def est(means):
+        y = [0.5 * np.log(np.interp(T_ref, T, m2)) for (m2,) in means]
+        return -np.polyfit(np.log(Ns), y, 1)[0]
+
+    return _jackknife_sizes(est, per_size)

@@ -3,7 +3,9 @@
 path for several sizes, then the critical temperature from the crossings of
 U4(T, N) with U4(T, N/4) extrapolated with T(N) = C N^(-1/nu_bar) + T_c, nu_bar
 from dU4/dT at fixed U4 (Eq. U4dot), and gamma/nu_bar from chi at a
-reference temperature.
+reference temperature; then the joint fits of App. C (T_c from Eq.
+Tfsscaling over several U4 values, nu_bar from Eq. scaling_lndotU4 with a
+common slope, beta/nu_bar from Eq. mscaling).
 
     python -m paper_1211_3991_amd.fss --rho 0 --z 4            # one JSON line
 """
@@ -57,13 +59,56 @@ def run(rho, z=4, sizes=(16, 32, 64, 128), samples=64, T=(1.7, 2.2, 16), sweeps=
     Ns = [L * L for L in sizes]
     nu, nu_err = analysis.nu_bar_from_u4(ladder, Ns, [rec[L] for L in sizes], u_star)
     t_ref = tc if T_ref is None else T_ref
-    g, g_err = analysis.gamma_over_nu_bar(ladder, Ns, [rec[L] for L in sizes], t_ref)
-    return {"rho": rho, "z": z, "boundary": boundary, "sizes": list(sizes), "samples": samples,
-            "crossings": [float(v) for v in Tx], "crossing_errors": [float(v) for v in err],
-            "T_c": float(tc), "T_c_error": tc_err, "C": float(c), "nu_bar_assumed": nu_bar,
-            "U4_star": u_star, "nu_bar": float(nu), "nu_bar_error": float(nu_err),
-            "T_ref": float(t_ref), "gamma_over_nu_bar": float(g), "gamma_over_nu_bar_error": float(g_err),
-            "records": rec}
+    recs = [rec[L] for L in sizes]
+    g, g_err = analysis.gamma_over_nu_bar(ladder, Ns, recs, t_ref)
+    out = {"rho": rho, "z": z, "boundary": boundary, "sizes": list(sizes), "samples": samples,
+           "crossings": [float(v) for v in Tx], "crossing_errors": [float(v) for v in err],
+           "T_c": float(tc), "T_c_error": tc_err, "C": float(c), "nu_bar_assumed": nu_bar,
+           "U4_star": u_star, "nu_bar": float(nu), "nu_bar_error": float(nu_err),
+           "T_ref": float(t_ref), "gamma_over_nu_bar": float(g), "gamma_over_nu_bar_error": float(g_err)}
+    out.update(app_c_fits(ladder, Ns, recs, u_star, rho, t_ref))
+    out["records"] = rec
+    return out
+
+
+def u4_targets(T, records, u_center, n_d=3, span=0.6):
+    """n_d values of U4 around u_center inside the range every size's
+    disorder-averaged U4 curve covers on the ladder (the middle `span` of the
+    common range, shifted to contain u_center when it can)."""
+    lo, hi = -np.inf, np.inf
+    for r in records:
+        m4, m2sq = analysis.u4_samples(r)
+        U = m4.mean(0) / m2sq.mean(0) - 1.0
+        lo, hi = max(lo, U.min()), min(hi, U.max())
+    if not hi > lo:
+        return []
+    half = 0.5 * span * (hi - lo)
+    c = min(max(u_center, lo + half), hi - half)
+    return list(np.linspace(c - half, c + half, n_d))
+
+
+def app_c_fits(T, N, records, u_star, rho, T_ref):
+    """The joint fits of App. C on the records of every size: T_c from Eq.
+    Tfsscaling over three U4 sets (exponent common to the sets for
+    rho < 3.75, one per set above), nu_bar from Eq. scaling_lndotU4 with a
+    common slope, and beta/nu_bar = x(T_ref) of Eq. mscaling (with
+    gamma/nu_bar, the Rushbrooke-Widom sum gamma/nu_bar + 2 beta/nu_bar)."""
+    out = {}
+    targets = u4_targets(T, records, u_star)
+    if targets:
+        try:
+            r = analysis.tc_from_u4_sets(T, N, records, targets, common_x=rho < 3.75)
+            out.update(T_c_joint=r["T_c"], T_c_joint_error=r["T_c_error"], x_joint=r["x"],
+                       x_joint_error=r["x_error"], u4_sets=r["u_targets"])
+            nj, nj_err = analysis.nu_bar_joint(T, N, records, targets)
+            out.update(nu_bar_joint=float(nj), nu_bar_joint_error=float(nj_err))
+        except ValueError:
+            pass
+    b, b_err = analysis.beta_over_nu_bar(T, N, records, T_ref)
+    g, _ = analysis.gamma_over_nu_bar(T, N, records, T_ref)
+    out.update(beta_over_nu_bar=float(b), beta_over_nu_bar_error=float(b_err),
+               rushbrooke_widom=float(g + 2 * b))
+    return out
 
 
 def main():

@@ -1,6 +1,17 @@
-"""Small statistics helpers for the tests (batch means and jackknife over
-batches).  Test code only; the product's own analysis lives in the package."""
+"""Small statistics helpers for the tests (batch means, jackknife over
+batches, and the bars the statistical GPU tests apply).  Test code only; the
+product's own analysis lives in the package.
+
+Bars:
+* many comparisons (hundreds or more): at most 1% of |z| beyond 3 and
+  chi^2/dof = mean(z^2) at most 1.5, every outlier listed (assert_r22);
+* few comparisons (pooled means, disorder averages): the largest |z| below
+  the quantile a family of that size exceeds with probability 1e-3 under the
+  null (Bonferroni, Student t with the errors' degrees of freedom), and
+  chi^2/dof at most 1.5 when there are at least 20 (assert_familywise).
+"""
 import numpy as np
+from scipy import stats
 
 
 def batch_mean_err(x, n_batches=50):
@@ -9,6 +20,14 @@ def batch_mean_err(x, n_batches=50):
     nb = len(x) // n_batches
     b = x[: nb * n_batches].reshape(n_batches, nb).mean(axis=1)
     return b.mean(), b.std(ddof=1) / np.sqrt(n_batches)
+
+
+def batch_means_err_axis0(x, n_batches=50):
+    """Means and standard errors along axis 0 from n_batches contiguous batches."""
+    x = np.asarray(x, dtype=np.float64)
+    nb = x.shape[0] // n_batches
+    b = x[: nb * n_batches].reshape((n_batches, nb) + x.shape[1:]).mean(axis=1)
+    return b.mean(axis=0), b.std(axis=0, ddof=1) / np.sqrt(n_batches)
 
 
 def jackknife_fn(fn, series, n_batches=50):
@@ -22,3 +41,43 @@ def jackknife_fn(fn, series, n_batches=50):
     loo = np.array([fn(*[(b.sum() - b[i]) / (n_batches - 1) for b in bm]) for i in range(n_batches)])
     err = np.sqrt((n_batches - 1) / n_batches * np.sum((loo - loo.mean()) ** 2))
     return full, err
+
+
+def _outliers(z, bar, labels=None, limit=30):
+    z = np.asarray(z, dtype=np.float64)
+    idx = np.argwhere(np.abs(z) > bar)
+    order = np.argsort(-np.abs(z[tuple(idx.T)])) if idx.size else []
+    out = []
+    for k in order[:limit]:
+        i = tuple(int(v) for v in idx[k])
+        out.append((labels[i] if labels is not None else i, round(float(z[i]), 2)))
+    return out
+
+
+def assert_r22(z, what=""):
+    """At most 1% of the |z| beyond 3 and chi^2/dof at most 1.5."""
+    z = np.asarray(z, dtype=np.float64)
+    assert np.all(np.isfinite(z)), f"{what}: undefined z"
+    frac, chi2 = float(np.mean(np.abs(z) > 3)), float(np.mean(z ** 2))
+    msg = f"{what}: n={z.size} frac|z|>3={frac:.4f} chi2/dof={chi2:.3f} outliers={_outliers(z, 3.0)}"
+    print(msg, flush=True)
+    assert frac <= 0.01 and chi2 <= 1.5, msg
+
+
+def familywise_bar(n, dof=np.inf, alpha=1e-3):
+    """|z| that one of n independent null comparisons exceeds with probability alpha."""
+    p = alpha / (2 * n)
+    return float(stats.norm.isf(p) if not np.isfinite(dof) else stats.t.isf(p, dof))
+
+
+def assert_familywise(z, what="", dof=np.inf, alpha=1e-3):
+    z = np.asarray(z, dtype=np.float64)
+    assert np.all(np.isfinite(z)), f"{what}: undefined z"
+    bar = familywise_bar(z.size, dof, alpha)
+    chi2 = float(np.mean(z ** 2))
+    msg = f"{what}: n={z.size} max|z|={np.max(np.abs(z)):.2f} (bar {bar:.2f}) chi2/dof={chi2:.3f} " \
+          f"beyond 3: {_outliers(z, 3.0)}"
+    print(msg, flush=True)
+    assert np.max(np.abs(z)) <= bar, msg
+    if z.size >= 20:
+        assert chi2 <= 1.5, msg

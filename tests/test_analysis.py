@@ -185,3 +185,124 @@ def test_eta_and_kt_temperature_from_exact_scaling():
     assert abs(t0 - 0.894) > 0.005
     t, err = analysis.t_eta(T, L, recs(24, np.random.default_rng(5)), discard=0.0)
     assert 0 < err < 0.01 and abs(t - 0.894) < 5 * err
+
+
+def test_compare_chains_calibrated_and_detects_bias():
+    """compare_chains on synthetic chains with known law: two independent
+    sets of AR(1) chains (autocorrelation time 5 records, bins of 50) with
+    equal means give z-scores with the standard normal's tails (fraction
+    beyond 3 sigma near 0.27%, chi^2/dof near 1), for the per-sample and the
+    disorder-paired comparisons; a shift of 6 standard errors planted in one
+    (temperature, observable) of one set is flagged there, and only there,
+    by the disorder-paired comparison."""
+    rng = np.random.default_rng(7)
+    n, G, R, Q = 1000, 64, 12, 5
+    phi = np.exp(-1 / 5)
+
+    def ar1():
+        x = np.empty((n, G, R, Q))
+        x[0] = rng.standard_normal((G, R, Q))
+        e = rng.standard_normal((n, G, R, Q)) * np.sqrt(1 - phi ** 2)
+        for t in range(1, n):
+            x[t] = phi * x[t - 1] + e[t]
+        return x
+
+    disorder = rng.standard_normal((1, G, R, Q)) * 3.0        # sample-to-sample offsets, shared by both sets
+    a, b = ar1() + disorder, ar1() + disorder
+    res = analysis.compare_chains(a, b, n_bins=20)
+    ps, dis = res["per_sample"], res["disorder"]
+    assert ps["n"] == G * R * Q and dis["n"] == R * Q
+    assert ps["frac_gt"] < 0.01 and 0.85 < ps["chi2_dof"] < 1.2, ps
+    assert dis["chi2_dof"] < 1.6 and dis["max_abs"] < 4.0, dis
+    # planted bias: set b shifted at (T index 3, observable 1) by 6 standard
+    # errors of the disorder mean of the difference
+    sd = np.sqrt(2 * (1 + phi) / (1 - phi) / n)               # error of one chain's mean
+    shift = 6 * sd * np.sqrt(2) / np.sqrt(G)
+    b2 = b.copy()
+    b2[:, :, 3, 1] += shift
+    res2 = analysis.compare_chains(a, b2, n_bins=20)
+    flagged = {idx for idx, _ in res2["disorder"]["outliers"]}
+    assert (3, 1) in flagged and len(flagged) <= 2, res2["disorder"]["outliers"]
+    # a shift of one chain by 8 of its own errors is a per-sample outlier
+    b3 = b.copy()
+    b3[:, 5, 7, 2] += 8 * sd * np.sqrt(2)
+    res3 = analysis.compare_chains(a, b3, n_bins=20)
+    assert (5, 7, 2) in {idx for idx, _ in res3["per_sample"]["outliers"]}
+    # drift: a chain that moves between the two halves of its records is flagged
+    b4 = b.copy()
+    b4[n // 2:, 9, 0, 0] += 10 * sd * np.sqrt(2)
+    res4 = analysis.compare_chains(a, b4, n_bins=20)
+    assert (1, 9, 0, 0) in {idx for idx, _ in res4["drift"]["outliers"]}
+
+
+def _fss_records(T, L, nu_bar=2.0, tc=1.93, bn=0.125, dbn=0.1, G=8, n_rec=4, noise=0.0, seed=0):
+    """Records of one size whose disorder-averaged U4 follows exact scaling,
+    U4(T, N) = 0.5 - 0.02 (T - tc) N^(1/nu_bar) (linear in T, so ladder
+    interpolation is exact), and whose <|m|^2> = 0.3 N^(-2 x(T)) with
+    x(T) = bn + dbn (T - tc) (Eq. mscaling with beta/nu_bar = x(tc))."""
+    N = float(L * L)
+    T = np.asarray(T)
+    u = 0.5 - 0.02 * (T - tc) * N ** (1.0 / nu_bar)
+    m2 = 0.3 * N ** (-2.0 * (bn + dbn * (T - tc)))
+    rec = np.zeros((n_rec, G, len(T), 8))
+    rng = np.random.default_rng(seed)
+    scale = 1.0 + noise * rng.standard_normal(G)        # per-sample scatter of |m|^2, U4 unchanged per sample
+    rec[:, :, :, 1] = m2[None, None, :] * scale[None, :, None]
+    rec[:, :, :, 2] = (1.0 + u)[None, None, :] * rec[:, :, :, 1] ** 2
+    return rec
+
+
+def test_app_c_joint_fits_recover_exact_scaling():
+    """App. C on synthetic exact scaling: the joint fit of Eq. Tfsscaling over
+    three U4 sets (common exponent, free exponents, fixed exponent) returns
+    T_c and x = 1/nu_bar; Eq. scaling_lndotU4 with a common slope returns
+    nu_bar; Eq. mscaling and Eq. chiscaling return x(T) and 1 - 2 x(T)
+    (Rushbrooke-Widom: gamma/nu_bar = 1 - 2 beta/nu_bar) at every ladder
+    temperature, and beta_over_nu_bar its value at T_c."""
+    T = np.linspace(1.5, 2.4, 19)                       # 1.93 is not a ladder point; 1.95 is
+    Ls = [16, 32, 64, 128]
+    Ns = [L * L for L in Ls]
+    recs = [_fss_records(T, L) for L in Ls]
+    targets = [0.4, 0.5, 0.6]
+    for kw in ({}, {"common_x": False}, {"x_fixed": 0.5}):
+        r = analysis.tc_from_u4_sets(T, Ns, recs, targets, **kw)
+        assert abs(r["T_c"] - 1.93) < 1e-9, (kw, r["T_c"])
+        assert np.allclose(r["x"], 0.5, atol=1e-7), (kw, r["x"])
+        assert r["T_c_error"] < 1e-9
+    nu, nu_err = analysis.nu_bar_joint(T, Ns, recs, targets)
+    assert abs(nu - 2.0) < 1e-10 and nu_err < 1e-10
+    x_m, e_m = analysis.size_exponent_curve(T, Ns, recs, "m")
+    x_c, _ = analysis.size_exponent_curve(T, Ns, recs, "chi")
+    assert np.allclose(x_m, 0.125 + 0.1 * (T - 1.93), atol=1e-12) and np.all(e_m < 1e-12)
+    assert np.allclose(x_c, 1.0 - 2.0 * x_m, atol=1e-12)
+    b, _ = analysis.beta_over_nu_bar(T, Ns, recs, 1.95)
+    assert abs(b - (0.125 + 0.1 * 0.02)) < 1e-12
+    g, _ = analysis.gamma_over_nu_bar(T, Ns, recs, 1.95)
+    assert abs(g - (1.0 - 2.0 * b)) < 1e-12
+
+
+def test_tf_joint_fit_free_exponents_and_errors():
+    """Eq. Tfsscaling with exponents that differ between the U4 sets (the
+    paper's choice for rho > 3.75) is recovered exactly; per-sample scatter of
+    |m|^2 (U4 per sample unchanged) leaves T_c exact; scatter of U4 gives a
+    jackknife error that shrinks as 1/sqrt(samples)."""
+    N = np.array([256.0, 1024.0, 4096.0, 16384.0, 65536.0])
+    A, x = np.array([0.8, -0.3, 1.5]), np.array([0.35, 0.5, 0.7])
+    Tf = 1.75 + A[None, :] * N[:, None] ** (-x[None, :])
+    r = analysis.tf_joint_fit(Tf, N, common_x=False)
+    assert abs(r["T_c"] - 1.75) < 1e-8 and np.allclose(r["x"], x, atol=1e-6) and np.allclose(r["A"], A, atol=1e-6)
+    T = np.linspace(1.5, 2.4, 19)
+    Ls = [16, 32, 64]
+    recs = [_fss_records(T, L, noise=0.05, seed=L) for L in Ls]
+    r = analysis.tc_from_u4_sets(T, [L * L for L in Ls], recs, [0.45, 0.55])
+    assert abs(r["T_c"] - 1.93) < 1e-9
+    errs = []
+    for G in (16, 64):
+        recs = []
+        for L in Ls:
+            rec = _fss_records(T, L, G=G, seed=L)
+            rng = np.random.default_rng(100 + L + G)
+            rec[:, :, :, 2] += 0.02 * rng.standard_normal(G)[None, :, None] * rec[:, :, :, 1] ** 2
+            recs.append(rec)
+        errs.append(analysis.tc_from_u4_sets(T, [L * L for L in Ls], recs, [0.45, 0.55])["T_c_error"])
+    assert errs[0] > 0 and 1.3 < errs[0] / errs[1] < 3.2, errs

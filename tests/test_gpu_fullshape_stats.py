@@ -1,0 +1,68 @@
+"""Fixed-point sweep against the FP64 sweep at the two large workload shapes
+(through the C ABI): 64 samples of L=256 (rho=3.5, 24 temperatures in
+[1.0, 2.5]) and 32 samples of L=512 (rho=2.5, 16 temperatures in [1.5, 3.5]),
+z = 6, parallel tempering every sweep (App. B), in the launch configuration
+the benchmark uses (autotuned stream groups, HIP-graph replay).
+
+Both precisions sweep the same graphs from independent uniform random starts
+for the same number of sweeps, measuring E, |m|^2, |m|^4, F_x, F_y (Sec. 3)
+every 4 sweeps; the second half of the records is kept (the last time
+window, Sec. 4).  The FP64 sweep is the path whose decisions equal the
+oracle's bit for bit (tests/test_gpu_fp64_parity.py, also at this L=256
+shape), so this ties the fixed-point form, at its real shape, to the oracle's
+observables.  The bar: per (sample, temperature, observable) with jackknife
+errors over 20 time bins, and disorder-paired per (temperature, observable),
+at most 1% of the comparisons beyond 3 sigma and chi^2/dof at most 1.5; every
+outlier is printed.  The two chains of a sample follow the same law from the
+same initial law, so their windows compare even where a chain is still
+relaxing; the first-against-second-quarter drift of the kept records is
+printed as the equilibration check.
+
+The L=256 case runs the phase kernel with 24 slots per site (six threads per
+site, 42 sites per block); the L=512 case runs its int32-index
+instantiation with 4096-site degree windows.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1211_3991_amd import parity  # noqa: E402
+
+SWEEPS = {"headline_l256": 2048, "large_l512": 2048}
+
+
+def _report(out):
+    for k in ("per_sample", "disorder", "drift"):
+        s = out[k]
+        print(f"{out['workload']} {k}: n={s['n']} frac|z|>3={s['frac_gt']:.4f} chi2/dof={s['chi2_dof']:.3f} "
+              f"max|z|={s['max_abs']:.2f} outliers={s['outliers'][:20]}", flush=True)
+    print(json.dumps(out["per_observable"]), flush=True)
+    path = os.environ.get("XY_PARITY_OUT")
+    if path:
+        with open(os.path.join(path, f"parity_{out['workload']}.json"), "w") as fh:
+            json.dump(out, fh, indent=1)
+
+
+@pytest.mark.parametrize("name", ["headline_l256", "large_l512"])
+def test_fix16_matches_fp64_at_full_shape(name):
+    wl = workloads.ALL[name]()
+    out, rec16, rec64 = parity.fix16_vs_fp64(wl, SWEEPS[name], meas_every=4, n_bins=20)
+    _report(out)
+    n_rec = SWEEPS[name] // 4
+    assert rec16.shape == rec64.shape == (n_rec, len(wl.samples), wl.n_T, 8)
+    assert np.all(np.isfinite(rec16)) and np.all(np.isfinite(rec64))
+    for k in ("per_sample", "disorder"):
+        s = out[k]
+        assert s["n_undefined"] == 0, (k, s)
+        assert s["frac_gt"] <= 0.01, (k, s["frac_gt"], s["outliers"])
+        assert s["chi2_dof"] <= 1.5, (k, s["chi2_dof"])

@@ -17,7 +17,12 @@ paper's own 0.01.  The same run gives the mean-field exponents the paper
 reports for this graph: nu_bar = 2 from dU4/dT at fixed U4 (Eq. U4dot; paper
 2.00(2)), within three standard errors plus 0.1, and gamma/nu_bar = 1/2 from
 chi at T_c, within three standard errors plus 0.05 (finite-size corrections
-at these sizes).
+at these sizes).  The joint fits of App. C on the same records: T_c from Eq.
+Tfsscaling over three U4 values with a common exponent (within three
+standard errors plus 0.02), nu_bar from Eq. scaling_lndotU4 with a common
+slope (three standard errors plus 0.1) and beta/nu_bar = 1/4 from Eq.
+mscaling (three standard errors plus 0.025; chi = N <|m|^2> makes
+gamma/nu_bar + 2 beta/nu_bar = 1 an identity, checked too).
 """
 import pytest
 
@@ -45,6 +50,19 @@ def test_erdos_renyi_z4_critical_temperature_and_exponents():
     g, g_err = out["gamma_over_nu_bar"], out["gamma_over_nu_bar_error"]
     print(f"gamma/nu_bar = {g:.3f} +- {g_err:.3f} at T = {out['T_ref']:.4f}; mean field 0.5", flush=True)
     assert abs(g - 0.5) <= 3.0 * g_err + 0.05
+    # App. C joint fits on the same records
+    tj, tj_err = out["T_c_joint"], out["T_c_joint_error"]
+    print(f"T_c (Eq. Tfsscaling, U4 sets {[round(u, 3) for u in out['u4_sets']]}, common x = "
+          f"{out['x_joint'][0]:.3f} +- {out['x_joint_error']:.3f}) = {tj:.4f} +- {tj_err:.4f}", flush=True)
+    nj, nj_err = out["nu_bar_joint"], out["nu_bar_joint_error"]
+    print(f"nu_bar (Eq. scaling_lndotU4, common slope) = {nj:.3f} +- {nj_err:.3f}", flush=True)
+    b, b_err = out["beta_over_nu_bar"], out["beta_over_nu_bar_error"]
+    print(f"beta/nu_bar (Eq. mscaling) = {b:.4f} +- {b_err:.4f}; mean field 0.25; "
+          f"gamma/nu_bar + 2 beta/nu_bar = {out['rushbrooke_widom']:.6f}", flush=True)
+    assert abs(tj - ref) <= 3.0 * tj_err + 0.02
+    assert abs(nj - 2.0) <= 3.0 * nj_err + 0.1
+    assert abs(b - 0.25) <= 3.0 * b_err + 0.025
+    assert abs(out["rushbrooke_widom"] - 1.0) < 1e-9
 
 
 def test_free_boundary_rho_10_3_critical_temperature():
