@@ -247,17 +247,18 @@ xy_status xy_batch_set_phase_streams(xy_batch *b, int n_streams, void *stream);
 xy_status xy_batch_phase_streams(const xy_batch *b, int *n_streams);
 
 /* Fixed-point sweep configuration (fix16 batches; used by the autotuner).
- *   trig        : (cos, sin) of a 16-bit angle: 0 two-level LDS table, 1 2048-entry
- *                 LDS table with a small-angle rotation, 2 hardware sine/cosine
+ *   trig        : (cos, sin) of a 16-bit angle, for every sample: 0 two-level
+ *                 LDS table, 1 2048-entry LDS table with a small-angle
+ *                 rotation, 2 hardware sine/cosine
  *   allow_unit  : keep FP32 unit vectors in LDS for graphs that fit (else angles)
  *   force_global: keep every replica in global memory
  * Each choice samples the clock model with its own FP32 (cos, sin); all are
- * exact Metropolis samplers.  Samples in the phase form (graphs too large for
- * LDS, state stored site-major; chosen at xy_batch_init) always use the
- * hardware form and are not affected by this call.  Synchronises `stream`, then uploads the new
- * work-item lists.  Initial values: trig 2, allow_unit 1, force_global 0
- * (the environment variables XY_FIX16_TRIG, XY_FIX16_NOUNIT and
- * XY_FIX16_GLOBAL override them at xy_batch_init). */
+ * exact Metropolis samplers.  allow_unit and force_global concern the
+ * workgroup-per-replica samples only (the phase-form samples keep their
+ * site-major storage, chosen at xy_batch_init).  Synchronises `stream`, then
+ * uploads the new work-item lists.  Initial values: trig 2, allow_unit 1,
+ * force_global 0 (the environment variables XY_FIX16_TRIG, XY_FIX16_NOUNIT
+ * and XY_FIX16_GLOBAL override them at xy_batch_init). */
 xy_status xy_batch_set_fix16_form(xy_batch *b, int trig, int allow_unit, int force_global, void *stream);
 
 /* Storage form of each sample, as chosen at xy_batch_init: out[s] = 1 for

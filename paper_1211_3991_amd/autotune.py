@@ -1,10 +1,10 @@
 """Autotuner of the fixed-point sweep configuration.
 
-For workgroup-form samples the candidates are the (cos, sin) form (hardware
-sine/cosine, 2048-entry LDS table, two-level LDS table) times the storage form
-(unit vectors in LDS where a replica fits, or angles).  For phase-form samples
-the candidate is the number of stream groups (1 to 3), which changes only how
-the colour-phase launches overlap.  Each candidate is timed on the live batch
+The candidates are the (cos, sin) form (hardware sine/cosine, 2048-entry
+LDS table, two-level LDS table), which every sample uses, times, for batches
+with workgroup-form samples, the storage form (unit vectors in LDS where a
+replica fits, or angles); then, for phase-form samples, the number of stream
+groups (1 to 3), which changes only how the colour-phase launches overlap.  Each candidate is timed on the live batch
 with HIP events (``xy_kernel_timing``).  Trial sweeps run without tempering or
 records, and the spins, permutations and sweep counter are restored
 afterwards, so tuning does not change the trajectory's inputs.  The choice is
@@ -62,7 +62,7 @@ def autotune(batch, sweeps=3, n_or=5, use_cache=True):
     cache = _load(path) if use_cache else {}
     if key in cache and "phase_streams" in cache[key]:
         c = cache[key]
-        if not forms.all():
+        if "trig" in c:
             batch.set_fix16_form(c["trig"], c["allow_unit"])
         batch.set_phase_streams(c["phase_streams"])
         return {"tuned": True, "cached": True, "trig": c.get("trig"), "allow_unit": c.get("allow_unit"),
@@ -80,12 +80,24 @@ def autotune(batch, sweeps=3, n_or=5, use_cache=True):
         rep.update(trig=trig, allow_unit=unit,
                    ms_per_sweep={f"trig{t}_unit{u}": round(v, 4) for (t, u), v in times.items()})
         entry.update(trig=trig, allow_unit=unit, ms_per_sweep=rep["ms_per_sweep"])
-    n_best = batch.phase_streams()
-    if n_phase >= 2:
-        # the group counts differ by a few percent: each trial runs about
-        # 40 ms of sweeps (at least 2 x sweeps), twice, keeping the faster
+    n_sw = sweeps
+    if n_phase >= 1:
+        # the candidates differ by a few percent: each trial runs about 40 ms
+        # of sweeps (at least 2 x sweeps), twice, keeping the faster
         probe = _time(batch, sweeps, n_or, saved)
         n_sw = int(min(256, max(2 * sweeps, 40.0 / max(probe, 1e-3))))
+    if forms.all():
+        # every sample in the phase form: the (cos, sin) form alone
+        times = {}
+        for trig in (2, 1, 0):
+            batch.set_fix16_form(trig, 1)
+            times[trig] = min(_time(batch, n_sw, n_or, saved) for _ in range(2))
+        trig = min(times, key=times.get)
+        batch.set_fix16_form(trig, 1)
+        rep.update(trig=trig, allow_unit=1, trig_ms_per_sweep={f"trig{t}": round(v, 4) for t, v in times.items()})
+        entry.update(trig=trig, allow_unit=1, trig_ms_per_sweep=rep["trig_ms_per_sweep"])
+    n_best = batch.phase_streams()
+    if n_phase >= 2:
         # (trials run without tempering, whose per-group tails favour fewer
         # groups, and the caller's stream plus three others fill the four
         # hardware queues a process gets by default: one to three groups, and

@@ -14,7 +14,8 @@ namespace {
 // read once for the four slots and their four angles are one 8-byte load, so
 // graph and gather traffic are shared by four replicas.  Random words: one
 // Philox call per (site, sweep, slot 4q), word r for slot 4q + r.  (cos, sin)
-// is the hardware form.
+// of an angle: the form kTrig of Trig (an LDS table loaded by the block, or
+// the hardware sine and cosine).
 
 // The hardware deals the workgroups of a launch to the 8 XCDs in turn
 // (workgroup w to XCD w mod 8).  Work unit of workgroup `lin` out of `n`:
@@ -26,11 +27,12 @@ __device__ __forceinline__ int xcd_contiguous(int lin, int n)
     return x * per + min(x, rem) + k;
 }
 
-template <typename Idx, bool kLast>
+template <typename Idx, bool kLast, int kTrig>
 __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const int4 *units, int colour, int sub,
                                                             int max_blocks, int grp)
 {
     __shared__ float esum[kLast ? kPhaseBlock * 4 : 1];
+    __shared__ float2 tab[Trig<kTrig>::kBytes ? Trig<kTrig>::kBytes / sizeof(float2) : 1];
     const int R = b.R, Lq = R >> 2, S = kPhaseBlock / Lq;
     const int t = threadIdx.x;
     // t / Lq through the FP32 reciprocal: exact for t < 256, Lq <= 64, even
@@ -76,6 +78,11 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
     for (int k = 0; k < 8; ++k) jj[k] = (int)*reinterpret_cast<const Idx *>(colb + k * 64 * sizeof(Idx));
 #pragma unroll
     for (int k = 0; k < 8; ++k) vv[k] = word(jj[k]);
+    // the (cos, sin) table of a table form, while the gathers are in flight
+    if constexpr (Trig<kTrig>::kBytes > 0) {
+        Trig<kTrig>::load(tab, b, t, kPhaseBlock);
+        __syncthreads();
+    }
     float beta[4];
     {
         const int4 tq = *reinterpret_cast<const int4 *>(b.T_of_slot + s * R + 4 * q);
@@ -94,7 +101,7 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
         const uint32_t th[4] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16};
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const float2 u = Trig<2>::unit(th[r], nullptr);
+            const float2 u = Trig<kTrig>::unit(th[r], tab);
             hx[r] = first ? u.x : hx[r] + u.x;
             hy[r] = first ? u.y : hy[r] + u.y;
         }
@@ -128,7 +135,7 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
         const int slot = 4 * q + r;
         const uint32_t th = cur_th[r];
         const uint32_t th_new = sub == 0 ? (words[r] & 0xFFFFu) : ((field_axis2(hx[r], hy[r]) - th) & 0xFFFFu);
-        const float2 cur = Trig<2>::unit(th, nullptr), nu = Trig<2>::unit(th_new, nullptr);
+        const float2 cur = Trig<kTrig>::unit(th, tab), nu = Trig<kTrig>::unit(th_new, tab);
         const float dE = hx[r] * (cur.x - nu.x) + hy[r] * (cur.y - nu.y);
         const bool acc = accept_move(dE, beta[r], words[r], (uint32_t)i, sweep, (uint32_t)slot, (uint32_t)sub, d);
         out[r] = acc ? th_new : th;
@@ -155,12 +162,19 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
 
 int fix16_phase_sites_per_block(int R) { return kPhaseBlock / (R / 4); }
 
+template <int kTrig>
+void (*phase_kernel(int idx16, int last))(DevBatch, const int4 *, int, int, int, int)
+{
+    return idx16 ? (last ? k_fix16_phase<uint16_t, true, kTrig> : k_fix16_phase<uint16_t, false, kTrig>)
+                 : (last ? k_fix16_phase<int32_t, true, kTrig> : k_fix16_phase<int32_t, false, kTrig>);
+}
+
 hipError_t launch_fix16_phase(const DevBatch &b, const int4 *units, int colour, int sub,
                               int last, int n_units, int max_blocks, int grp, hipStream_t s)
 {
     if (n_units == 0) return hipSuccess;
-    auto k = b.idx16 ? (last ? k_fix16_phase<uint16_t, true> : k_fix16_phase<uint16_t, false>)
-                     : (last ? k_fix16_phase<int32_t, true> : k_fix16_phase<int32_t, false>);
+    auto k = b.trig == 0 ? phase_kernel<0>(b.idx16, last) : b.trig == 1 ? phase_kernel<1>(b.idx16, last)
+                                                                         : phase_kernel<2>(b.idx16, last);
     hipLaunchKernelGGL(k, dim3((unsigned)n_units), dim3(kPhaseBlock), 0, s, b, units, colour, sub, max_blocks, grp);
     return hipGetLastError();
 }

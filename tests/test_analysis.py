@@ -5,6 +5,8 @@ linear observable, and its bias correction of a square equals the closed
 form mean^2 - s^2/n; on infinite-temperature oracle records (independent
 uniform spins) U4 = 1 - 1/N, chi(0)/chi(k_min) = 1 and xi_2 = 0 within errors.
 """
+import json
+
 import numpy as np
 import pytest
 
@@ -306,3 +308,25 @@ def test_tf_joint_fit_free_exponents_and_errors():
             recs.append(rec)
         errs.append(analysis.tc_from_u4_sets(T, [L * L for L in Ls], recs, [0.45, 0.55])["T_c_error"])
     assert errs[0] > 0 and 1.3 < errs[0] / errs[1] < 3.2, errs
+
+
+def test_graph_reports():
+    """The Fig. 1 / Fig. 15 report entry point on small sizes: every P(k)
+    sums to 1 with mean degree exactly z; rho = 1/2 is close to the Poisson
+    law of mean z (Sec. 2: the rho -> 0 limit is Erdos-Renyi); colour-class
+    fractions sum to 1, sorted largest first, at most 6 classes (App. B)."""
+    from paper_1211_3991_amd import reports
+    d = reports.degree_report(L=64, rhos=(0.5, 14 / 3), samples=2)
+    assert len(d["curves"]) == 4
+    for c in d["curves"]:
+        P = np.asarray(c["P"])
+        assert abs(P.sum() - 1.0) < 1e-12 and abs(c["mean_degree"] - 4.0) < 1e-12
+    mf = np.asarray(d["curves"][0]["P"])
+    pois = np.asarray(d["poisson"][:mf.size])
+    assert np.max(np.abs(mf - pois)) < 0.02
+    c = reports.colour_report(exps=(8, 10), samples=2)
+    for s in c["sizes"]:
+        f = np.asarray(s["fractions"])
+        assert abs(f.sum() - 1.0) < 1e-12 and np.all(np.diff(f) <= 0) and f.size <= 6
+        assert s["spread"] == pytest.approx(f[0] - f[-1], abs=0.05)
+    json.dumps(d), json.dumps(c)

@@ -125,14 +125,17 @@ def test_tiny_graphs_exact_energy(name, n, edges, trig, monkeypatch):
     _tiny_check(rec[:, :, :, 0], T, name, f"{name} trig{trig}")
 
 
+@pytest.mark.parametrize("trig", TRIG_FORMS)
 @pytest.mark.parametrize("R", [8, 64, 256])
 @pytest.mark.parametrize("name,n,edges", [("triangle", 3, [(0, 1), (1, 2), (2, 0)]),
                                           ("cycle4", 4, [(0, 1), (1, 2), (2, 3), (3, 0)])])
-def test_tiny_graphs_exact_energy_phase_form(name, n, edges, R, monkeypatch):
+def test_tiny_graphs_exact_energy_phase_form(name, n, edges, R, trig, monkeypatch):
     """The phase form at R = 8, 64, 256 (four temperatures, each repeated R/4
     times: tempering between equal temperatures only permutes the labels)
-    against the exact energies; every (sample, label) is one chain."""
+    against the exact energies, for each (cos, sin) form; every (sample,
+    label) is one chain."""
     monkeypatch.setenv("XY_FIX16_PHASE", "1")
+    monkeypatch.setenv("XY_FIX16_TRIG", str(trig))
     base = np.array([0.8, 1.2, 1.6, 2.0])
     T = np.repeat(base, R // 4)
     n_samples = max(4, 1024 // R)
@@ -144,7 +147,7 @@ def test_tiny_graphs_exact_energy_phase_form(name, n, edges, R, monkeypatch):
     rec = b.records().cpu().numpy()            # [250, samples, R, 8]
     # chains grouped by temperature: [250, samples * R/4, 4]
     chains = rec[:, :, :, 0].reshape(rec.shape[0], n_samples, 4, R // 4).transpose(0, 1, 3, 2)
-    _tiny_check(chains.reshape(rec.shape[0], -1, 4), base, name, f"{name} phase R={R}")
+    _tiny_check(chains.reshape(rec.shape[0], -1, 4), base, name, f"{name} phase R={R} trig{trig}")
 
 
 def _energy_bound(m_links):
@@ -198,7 +201,7 @@ def _oracle_l16_chains(n_chains=16):
 
 
 @pytest.mark.parametrize("trig,form", [(0, "lds"), (1, "lds"), (2, "lds"), (2, "global"), (2, "unit"), (0, "unit"),
-                                       (2, "phase")])
+                                       (2, "phase"), (1, "phase"), (0, "phase")])
 def test_l16_observables_match_oracle(trig, form, monkeypatch):
     """fix16 on 128 independent chains of the L=16 graph vs 16 chains of the
     FP64 oracle (1e4 sweeps each), for each (cos, sin) form and spin storage
@@ -391,16 +394,19 @@ def test_phase_form_pt_batch_matches_fp64_gpu(monkeypatch):
     _pt_batch_vs_fp64([xy.Graph.levy(32, 6, 3.5, s) for s in range(64)], workloads.linear_ladder(1.0, 2.5, 8))
 
 
-@pytest.mark.parametrize("streams,n_T", [("1", 8), ("2", 8), ("3", 8), ("2", 4), ("2", 12), ("2", 24), ("2", 256)])
-def test_tempering_energies_equal_state_energy(streams, n_T, monkeypatch):
+@pytest.mark.parametrize("streams,n_T,trig", [("1", 8, 2), ("2", 8, 2), ("3", 8, 2), ("2", 4, 2), ("2", 12, 2),
+                                              ("2", 24, 2), ("2", 256, 2), ("2", 24, 0), ("2", 24, 1)])
+def test_tempering_energies_equal_state_energy(streams, n_T, trig, monkeypatch):
     """The replica energies the tempering step uses (summed in the last
     sub-sweep over the links to lower colours) equal
     -sum_links cos(theta_i - theta_j) of the state, in FP64 from the exported
     links: phase form with its samples in one to three stream groups, and a
     workgroup-form sample.  4, 8 and 12 temperatures put more than 64 sites in
-    a block (blocks spanning three to five chunks); 24 is the headline's; 256,
-    the most a batch takes, puts four sites in a block."""
+    a block (blocks spanning three to five chunks); 24 is the headline's (also
+    with both table forms of (cos, sin)); 256, the most a batch takes, puts
+    four sites in a block."""
     monkeypatch.setenv("XY_PHASE_STREAMS", streams)
+    monkeypatch.setenv("XY_FIX16_TRIG", str(trig))
     graphs = [xy.Graph.levy(128, 6, 3.5, s) for s in range(5)] + [xy.Graph.levy(32, 6, 2.5, 7)]
     T = workloads.linear_ladder(1.0, 2.5, n_T)
     b = xy.Batch(graphs, T, precision="fix16", seeds=np.arange(6) + 40)
@@ -416,8 +422,8 @@ def test_tempering_energies_equal_state_energy(streams, n_T, monkeypatch):
             assert abs(E[k, slot] - ref) <= _energy_bound(len(e)), (k, slot, E[k, slot], ref)
 
 
-@pytest.mark.parametrize("mixed", [False, True])
-def test_stream_groups_give_identical_trajectories(mixed, monkeypatch):
+@pytest.mark.parametrize("mixed,trig", [(False, 2), (True, 2), (False, 0)])
+def test_stream_groups_give_identical_trajectories(mixed, trig, monkeypatch):
     """The phase form in one, two or three stream groups updates every site in
     the same order with the same random words: states, temperature labels,
     records and tempering counters are identical.  With every sample in the
@@ -425,6 +431,7 @@ def test_stream_groups_give_identical_trajectories(mixed, monkeypatch):
     tempering, records and sweep counter (once also replayed from a captured
     HIP graph, once regrouped from two to four groups half way); in a batch
     that also holds workgroup-form samples the groups join every sweep."""
+    monkeypatch.setenv("XY_FIX16_TRIG", str(trig))
     graphs = [xy.Graph.levy(128, 6, 3.5, s) for s in range(5)]
     if mixed:
         graphs += [xy.Graph.levy(32, 6, 2.5, 11), xy.Graph.levy(16, 6, 3.5, 12)]
