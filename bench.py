@@ -385,6 +385,14 @@ def main():
           f"{sorted(set(g.n_colours for g in graphs))}", file=sys.stderr, flush=True)
 
     upd_per_sweep = wl.updates_per_sweep()
+    threshold = None
+    if args.precision == "fix16" and len({s.L for s in wl.samples}) > 1 and "XY_FIX16_PHASE_MIN" not in os.environ:
+        # uneven sizes: which samples take the phase form is tuned on trial batches
+        from paper_1211_3991_amd import autotune
+        threshold = autotune.tune_phase_threshold(graphs, wl.T, [s.seed for s in wl.samples], use_cache=False)
+        if threshold.get("phase_min"):
+            os.environ["XY_FIX16_PHASE_MIN"] = str(threshold["phase_min"])
+        print(f"# phase-form threshold: {threshold}", file=sys.stderr, flush=True)
     main_run = time_gpu(wl, args.precision, args.steps, args.warmup, graphs, torch, xy,
                         phase_streams=args.phase_streams, replay=not args.direct)
     value = upd_per_sweep * args.steps / (main_run["ms"] * 1e6)
@@ -534,6 +542,7 @@ def main():
         "cpu_baseline": cpu,
         "pt_acceptance": round(main_run["pt_rate"], 4),
         "autotune": main_run["autotune"],
+        "phase_threshold": threshold,
     }
     print(json.dumps(out), flush=True)
 

@@ -246,6 +246,19 @@ xy_status xy_kernel_time(xy_batch *b, double *ms_total, int *n_timed);
 xy_status xy_batch_set_phase_streams(xy_batch *b, int n_streams, void *stream);
 xy_status xy_batch_phase_streams(const xy_batch *b, int *n_streams);
 
+/* Workgroups of each colour-phase launch of the phase form (fix16 batches;
+ * used by the autotuner): 0 (the initial value; XY_PHASE_GRID overrides it
+ * at xy_batch_init) gives one workgroup per work unit (a block of sites of
+ * one sample's colour class); max_workgroups >= 8 caps a launch at that
+ * many workgroups (rounded down to a multiple of 8), each then looping over
+ * every gridDim-th unit with the next units' loads in flight while it
+ * computes (App. B's colour phases are unchanged: every site of the class is
+ * updated once, with the same random words, so the trajectory does not
+ * depend on the choice).  Takes effect with the next sweep.  XY_EINVAL for
+ * max_workgroups < 0. */
+xy_status xy_batch_set_phase_grid(xy_batch *b, int max_workgroups);
+xy_status xy_batch_phase_grid(const xy_batch *b, int *max_workgroups);
+
 /* Fixed-point sweep configuration (fix16 batches; used by the autotuner).
  *   trig        : (cos, sin) of a 16-bit angle, for every sample: 0 two-level
  *                 LDS table, 1 2048-entry LDS table with a small-angle
@@ -296,6 +309,23 @@ xy_status xy_walk_bytes(const xy_graph *const *g, int n_graphs, size_t *graph_by
 xy_status xy_random_walk(const xy_graph *const *g, int n_graphs, int n_walkers, int n_steps,
                          const uint64_t *seeds, int start_mode, void *d_graph, size_t graph_bytes,
                          uint64_t *d_hist, void *stream, float *kernel_ms);
+
+/* xy_random_walk for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same walks, histograms and errors, but the walk graphs
+ * are staged in the library's static device workspace instead of a
+ * caller-provided d_graph.  The workspace is 32 MiB (33554432 bytes) per
+ * device, held from the library's load to the end of the process; a set of
+ * graphs whose xy_walk_bytes exceeds it is rejected with XY_EINVAL before any
+ * device work.  The call allocates no device memory (it still builds the
+ * records in host memory, uploads them on `stream` and synchronises it, as
+ * xy_random_walk does).  Every call on a device shares that device's
+ * workspace: calls that overlap on one device (other threads or streams)
+ * race and must be serialised by the caller; a call overwrites what the
+ * previous one staged.  d_hist: caller-owned uint64[n_graphs][n_steps + 1]. */
+xy_status xy_random_walk_noalloc(const xy_graph *const *g, int n_graphs, int n_walkers, int n_steps,
+                                 const uint64_t *seeds, int start_mode, uint64_t *d_hist, void *stream,
+                                 float *kernel_ms);
 
 const char *xy_last_error(void);
 void xy_batch_free(xy_batch *b);

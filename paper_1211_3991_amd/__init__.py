@@ -19,7 +19,7 @@ import numpy as np
 from . import _lib
 from ._lib import XY_FIX16, XY_FP64, XY_NOBS, XYError
 
-__all__ = ["Graph", "Batch", "random_walk", "XYError", "XY_FP64", "XY_FIX16", "XY_NOBS", "OBS_NAMES"]
+__all__ = ["Graph", "Batch", "random_walk", "random_walk_noalloc", "XYError", "XY_FP64", "XY_FIX16", "XY_NOBS", "OBS_NAMES"]
 
 OBS_NAMES = ("E", "m2", "m4", "Fx", "Fy", "mx", "my", "pad")
 _PREC = {"fp64": XY_FP64, "fix16": XY_FIX16}
@@ -161,6 +161,16 @@ class Batch:
         trajectory does not depend on it."""
         _lib.call("xy_batch_set_phase_streams", self._h, int(n), self._s())
 
+    def set_phase_grid(self, max_workgroups):
+        """Workgroups per colour-phase launch of the phase form (0: one per
+        work unit); the trajectory does not depend on it."""
+        _lib.call("xy_batch_set_phase_grid", self._h, int(max_workgroups))
+
+    def phase_grid(self):
+        n = ctypes.c_int()
+        _lib.call("xy_batch_phase_grid", self._h, ctypes.byref(n))
+        return n.value
+
     def phase_streams(self):
         n = ctypes.c_int()
         _lib.call("xy_batch_phase_streams", self._h, ctypes.byref(n))
@@ -296,4 +306,25 @@ def random_walk(graphs, n_walkers, n_steps, seeds=None, start="degree3", stream=
               ctypes.c_void_p(hist.data_ptr()), ctypes.c_void_p(st.cuda_stream),
               ctypes.byref(ms) if timing else None)
     # d_graph is released to the caching allocator on `st`, after the walk in stream order
+    return (hist, ms.value) if timing else hist
+
+
+def random_walk_noalloc(graphs, n_walkers, n_steps, seeds=None, start="degree3", stream=None, timing=False):
+    """random_walk through xy_random_walk_noalloc: the walk graphs are staged
+    in the library's static device workspace (32 MiB per device) instead of a
+    buffer allocated here; only the output histogram is allocated.  Calls
+    that overlap on one device race on that workspace."""
+    import torch
+    G = len(graphs)
+    seeds = np.arange(G, dtype=np.uint64) if seeds is None else np.ascontiguousarray(seeds, dtype=np.uint64)
+    if seeds.shape != (G,):
+        raise ValueError("one seed per graph")
+    garr = (ctypes.c_void_p * G)(*[g._h.value for g in graphs])
+    st = stream if stream is not None else torch.cuda.current_stream()
+    with torch.cuda.stream(st):
+        hist = torch.empty((G, n_steps + 1), dtype=torch.int64, device="cuda")
+    ms = ctypes.c_float()
+    _lib.call("xy_random_walk_noalloc", garr, G, int(n_walkers), int(n_steps), ctypes.c_void_p(seeds.ctypes.data),
+              _WALK_START[start], ctypes.c_void_p(hist.data_ptr()), ctypes.c_void_p(st.cuda_stream),
+              ctypes.byref(ms) if timing else None)
     return (hist, ms.value) if timing else hist

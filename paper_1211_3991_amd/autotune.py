@@ -123,3 +123,73 @@ def autotune(batch, sweeps=3, n_or=5, use_cache=True):
         except OSError:
             pass
     return rep
+
+
+def threshold_candidates(graphs, R):
+    """Phase-form thresholds worth trying for a batch: every distinct graph
+    size (the smallest graphs of that size and all larger ones take the phase
+    form), plus "none" (every sample in a workgroup per replica); only when
+    the temperature count allows the phase form (a multiple of 4)."""
+    if R % 4:
+        return []
+    sizes = sorted({g.n for g in graphs})
+    return sizes + [sizes[-1] + 1]
+
+
+def tune_phase_threshold(graphs, T, seeds=None, sweeps=4, n_or=5, use_cache=True, device="cuda"):
+    """Chooses the graph size from which samples take the phase form (site-
+    major state, a launch per colour phase) instead of a workgroup per
+    replica, for this batch: builds a trial batch per candidate threshold
+    (threshold_candidates), tunes it and times `sweeps` sweeps with the
+    kernel-event timer, and returns the fastest threshold with the timings.
+    The form is fixed when a batch is created, so the caller creates its
+    batch with the result (environment variable XY_FIX16_PHASE_MIN, which
+    xy_batch_sizes and xy_batch_init read).  Cached like autotune()."""
+    import numpy as np
+    import torch
+
+    from . import Batch
+    T = np.asarray(T, dtype=np.float64)
+    R = T.shape[-1]
+    cands = threshold_candidates(graphs, R)
+    if not cands:
+        return {"phase_min": None, "reason": "n_T is not a multiple of 4"}
+    arch = torch.cuda.get_device_properties(torch.device(device)).gcnArchName.split(":")[0]
+    sizes = {}
+    for g in graphs:
+        sizes[g.n] = sizes.get(g.n, 0) + 1
+    key = f"{arch}|R={R}|" + ",".join(f"{n}x{c}" for n, c in sorted(sizes.items())) + "|phase_min"
+    path = cache_path()
+    cache = _load(path) if use_cache else {}
+    if key in cache:
+        return dict(cache[key], cached=True)
+    old = os.environ.get("XY_FIX16_PHASE_MIN")
+    times = {}
+    try:
+        for thr in cands:
+            os.environ["XY_FIX16_PHASE_MIN"] = str(thr)
+            b = Batch(graphs, T, precision="fix16", seeds=seeds, device=device, stream=torch.cuda.Stream())
+            try:
+                autotune(b, sweeps=2, n_or=n_or, use_cache=False)
+                saved = b.get_state()
+                times[thr] = min(_time(b, sweeps, n_or, saved) for _ in range(2))
+            finally:
+                b.close()
+                torch.cuda.empty_cache()
+    finally:
+        if old is None:
+            os.environ.pop("XY_FIX16_PHASE_MIN", None)
+        else:
+            os.environ["XY_FIX16_PHASE_MIN"] = old
+    best = min(times, key=times.get)
+    out = {"phase_min": int(best), "ms_per_sweep": {str(k): round(v, 4) for k, v in times.items()}, "cached": False}
+    if use_cache:
+        cache[key] = {k: v for k, v in out.items() if k != "cached"}
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            with open(path + ".tmp", "w") as fh:
+                json.dump(cache, fh, indent=1, sort_keys=True)
+            os.replace(path + ".tmp", path)
+        except OSError:
+            pass
+    return out

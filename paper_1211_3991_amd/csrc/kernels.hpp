@@ -26,7 +26,7 @@ struct DevBatch {
     double *E_slot;           // [G][R]
     double *obs_slot;         // [G][R][XY_NOBS]
     double *partial;          // [G][64][R][11] block partial sums of the observables (fp64, fix16 phase form)
-    double *epart;            // fix16 phase form: [n_phase][31][max_blocks][R] energy partials
+    double *epart;            // energy partials: fix16 phase form [n_phase][31][max_blocks][R], fp64 [G][Q][max_blocks][R]
     unsigned long long *pt_acc, *pt_try;  // [G][R]
     double *records;          // [max_records][G][R][XY_NOBS]
     int G, R, max_records, max_n;
@@ -38,7 +38,15 @@ struct DevBatch {
 
 // FP64 path (kernels_fp64.hip, built with -ffp-contract=off).
 hipError_t launch_fp64_init(const DevBatch &b, int max_n, hipStream_t s);
-hipError_t launch_fp64_phase(const DevBatch &b, int colour, int met, int max_class, hipStream_t s);
+// energy: also sum the replica energies into b.epart (the last sub-sweep of a
+// tempering sweep), [G][n_col][max_blocks][R] with n_col the batch's largest
+// colour count and max_blocks at least fp64_phase_blocks of every colour.
+int fp64_phase_blocks(int max_class, int R);
+hipError_t launch_fp64_phase(const DevBatch &b, int colour, int met, int energy, int max_class, int n_col,
+                             int max_blocks, hipStream_t s);
+// E_slot from those partials (max_class: the launch sizes of the n_colours colours)
+hipError_t launch_fp64_energy_final(const DevBatch &b, const int *max_class, int n_colours, int max_blocks,
+                                    hipStream_t s);
 hipError_t launch_fp64_observe(const DevBatch &b, int full, double *out_by_T, hipStream_t s);
 // samples: the samples to temper and record (NULL: all); ctl: b.ctl[grp]
 hipError_t launch_end_sweep(const DevBatch &b, const int32_t *samples, int n_samples, int grp, int do_pt,
@@ -59,9 +67,10 @@ int fix16_phase_sites_per_block(int R);
 // units: the n_units work units (two int4 each, see k_fix16_phase) of this
 // colour; max_blocks: stride of the energy partials (the largest block count
 // of any colour); last: fuse the energy; grp: the control block b.ctl[grp]
-// whose sweep counter keys the random words.
+// whose sweep counter keys the random words; max_grid: 0 for a workgroup per
+// unit, else at most that many workgroups looping over the units.
 hipError_t launch_fix16_phase(const DevBatch &b, const int4 *units, int colour, int sub,
-                              int last, int n_units, int max_blocks, int grp, hipStream_t s);
+                              int last, int n_units, int max_blocks, int grp, int max_grid, hipStream_t s);
 // phase samples [k_first, k_first + n_phase) of the list
 hipError_t launch_fix16_phase_energy(const DevBatch &b, const int32_t *phase_samples, int k_first, int n_phase,
                                      int max_blocks, hipStream_t s);

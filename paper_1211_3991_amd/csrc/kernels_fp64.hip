@@ -54,8 +54,18 @@ __global__ __launch_bounds__(kBlock) void k_fp64_init(DevBatch b)
 // site colour_off[c] + t / R in slot t % R; neighbouring threads read
 // neighbouring slots of the same site, so every gather is a contiguous run of
 // R * 16 bytes.
-__global__ __launch_bounds__(kBlock) void k_fp64_phase(DevBatch b, int colour, int met)
+// energy: the last sub-sweep of a sweep that tempers: the replica energies
+// are summed here.  A row's neighbours are sorted by colour-major index, so
+// its links to lower colours (whose sites are final in this sub-sweep) are a
+// prefix, and their field is the running sum taken after the last of them;
+// E = -sum_i S_i . (that field) counts every link once, at its upper colour.
+// Per block and slot the site terms are added in site order into
+// epart[s][colour][block][slot] (colour stride n_col, block stride
+// max_blocks); k_fp64_energy_final adds the blocks in order.
+__global__ __launch_bounds__(kBlock) void k_fp64_phase(DevBatch b, int colour, int met, int energy, int n_col,
+                                                      int max_blocks)
 {
+    __shared__ double esum[kBlock];
     const int s = blockIdx.y;
     const SampleDesc &d = b.desc[s];
     if (colour >= d.Q) return;
@@ -63,44 +73,78 @@ __global__ __launch_bounds__(kBlock) void k_fp64_phase(DevBatch b, int colour, i
     const int R = b.R;
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int site = c0 + (int)(t / R), slot = (int)(t % R);
-    if (site >= c1) return;
+    double e = 0.0;
+    if (site < c1) {
+        double2 *S = static_cast<double2 *>(b.state) + d.state;
+        const int32_t *row = b.i32 + d.row_ptr;
+        const int32_t *col = b.i32 + d.col;
+        double hx = 0.0, hy = 0.0, lx = 0.0, ly = 0.0;
+        for (int a = row[site]; a < row[site + 1]; ++a) {
+            const int j = col[a];
+            const double2 v = S[(int64_t)j * R + slot];
+            hx = hx + v.x;
+            hy = hy + v.y;
+            if (j < c0) { lx = hx; ly = hy; }
+        }
+        const int64_t me = (int64_t)site * R + slot;
+        const double2 cur = S[me];
+        double2 fin = cur;
+        if (met) {
+            const uint32_t sweep = b.ctl->sweep;
+            const uint32_t lattice = (uint32_t)b.i32[d.perm + site];
+            const double beta = b.beta[s * R + b.T_of_slot[s * R + slot]];
+            const double2 nw = uniform_direction(d, lattice, sweep, (uint32_t)slot, kMet);
+            const double e_old = hx * cur.x + hy * cur.y;
+            const double e_new = hx * nw.x + hy * nw.y;
+            const double dE = e_old - e_new;                 // H = -h.S
+            const U4 w = draw(d, lattice, sweep, (uint32_t)slot, tag(kMetAcc));
+            const bool accept = dE <= 0.0 || unit53(w.x, w.y) < exp(-(beta * dE));
+            if (accept) { S[me] = nw; fin = nw; }
+            if (b.log) {
+                const uint32_t rel = sweep - b.ctl->log_base;
+                if (rel < (uint32_t)b.log_sweeps)
+                    b.log[(((int64_t)rel * b.G + s) * R + slot) * b.max_n + lattice] = accept ? 1 : 0;
+            }
+        } else {
+            // over-relaxation: reflection of S about h (h = 0: unchanged)
+            const double hh = hx * hx + hy * hy;
+            if (hh != 0.0) {
+                const double a = (hx * cur.x + hy * cur.y) / hh;
+                const double two_a = 2.0 * a;
+                fin = make_double2(two_a * hx - cur.x, two_a * hy - cur.y);
+                S[me] = fin;
+            }
+        }
+        e = -(fin.x * lx + fin.y * ly);
+    }
+    if (!energy) return;                                 // uniform: the whole launch
+    esum[threadIdx.x] = e;
+    __syncthreads();
+    if ((int)threadIdx.x < R) {
+        // slot r's threads of this block: (lin0 + k) % R == r, in site order
+        const int r = threadIdx.x;
+        const int first = (int)(((int64_t)r - (int64_t)blockIdx.x * kBlock % R + R) % R);
+        double acc = 0.0;
+        for (int k = first; k < kBlock; k += R) acc += esum[k];
+        b.epart[(((int64_t)s * n_col + colour) * max_blocks + blockIdx.x) * R + r] = acc;
+    }
+}
 
-    double2 *S = static_cast<double2 *>(b.state) + d.state;
-    const int32_t *row = b.i32 + d.row_ptr;
-    const int32_t *col = b.i32 + d.col;
-    double hx = 0.0, hy = 0.0;
-    for (int a = row[site]; a < row[site + 1]; ++a) {
-        const double2 v = S[(int64_t)col[a] * R + slot];
-        hx = hx + v.x;
-        hy = hy + v.y;
-    }
-    const int64_t me = (int64_t)site * R + slot;
-    const double2 cur = S[me];
-    if (met) {
-        const uint32_t sweep = b.ctl->sweep;
-        const uint32_t lattice = (uint32_t)b.i32[d.perm + site];
-        const double beta = b.beta[s * R + b.T_of_slot[s * R + slot]];
-        const double2 nw = uniform_direction(d, lattice, sweep, (uint32_t)slot, kMet);
-        const double e_old = hx * cur.x + hy * cur.y;
-        const double e_new = hx * nw.x + hy * nw.y;
-        const double dE = e_old - e_new;                 // H = -h.S
-        const U4 w = draw(d, lattice, sweep, (uint32_t)slot, tag(kMetAcc));
-        const bool accept = dE <= 0.0 || unit53(w.x, w.y) < exp(-(beta * dE));
-        if (accept) S[me] = nw;
-        if (b.log) {
-            const uint32_t rel = sweep - b.ctl->log_base;
-            if (rel < (uint32_t)b.log_sweeps)
-                b.log[(((int64_t)rel * b.G + s) * R + slot) * b.max_n + lattice] = accept ? 1 : 0;
-        }
-    } else {
-        // over-relaxation: reflection of S about h (h = 0: unchanged)
-        const double hh = hx * hx + hy * hy;
-        if (hh != 0.0) {
-            const double a = (hx * cur.x + hy * cur.y) / hh;
-            const double two_a = 2.0 * a;
-            S[me] = make_double2(two_a * hx - cur.x, two_a * hy - cur.y);
-        }
-    }
+// E_slot of every (sample, slot) from the energy partials of the last
+// sub-sweep: colours in order, blocks in order.  nblk[c]: blocks of colour
+// c's launch.
+struct BlockCounts { int n[kMaxColours]; };
+
+__global__ __launch_bounds__(kBlock) void k_fp64_energy_final(DevBatch b, BlockCounts nblk, int n_col, int max_blocks)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)b.G * b.R) return;
+    const int R = b.R, s = (int)(t / R), slot = (int)(t % R);
+    const int Q = b.desc[s].Q;
+    double acc = 0.0;
+    for (int c = 0; c < Q; ++c)
+        for (int k = 0; k < nblk.n[c]; ++k) acc += b.epart[(((int64_t)s * n_col + c) * max_blocks + k) * R + slot];
+    b.E_slot[s * R + slot] = acc;
 }
 
 // Energy (and, when full, the observables) of every (sample, slot), in two
@@ -252,12 +296,26 @@ hipError_t launch_fp64_init(const DevBatch &b, int max_n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_fp64_phase(const DevBatch &b, int colour, int met, int max_class, hipStream_t s)
+int fp64_phase_blocks(int max_class, int R) { return (int)(((int64_t)max_class * R + kBlock - 1) / kBlock); }
+
+hipError_t launch_fp64_phase(const DevBatch &b, int colour, int met, int energy, int max_class, int n_col,
+                             int max_blocks, hipStream_t s)
 {
-    const int64_t threads = (int64_t)max_class * b.R;
-    if (threads == 0) return hipSuccess;
-    dim3 grid((unsigned)((threads + kBlock - 1) / kBlock), (unsigned)b.G);
-    hipLaunchKernelGGL(k_fp64_phase, grid, dim3(kBlock), 0, s, b, colour, met);
+    const int nb = fp64_phase_blocks(max_class, b.R);
+    if (nb == 0) return hipSuccess;
+    dim3 grid((unsigned)nb, (unsigned)b.G);
+    hipLaunchKernelGGL(k_fp64_phase, grid, dim3(kBlock), 0, s, b, colour, met, energy, n_col, max_blocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_fp64_energy_final(const DevBatch &b, const int *max_class, int n_colours, int max_blocks,
+                                    hipStream_t s)
+{
+    BlockCounts nblk{};
+    for (int c = 0; c < n_colours && c < kMaxColours; ++c) nblk.n[c] = fp64_phase_blocks(max_class[c], b.R);
+    const int64_t n = (int64_t)b.G * b.R;
+    hipLaunchKernelGGL(k_fp64_energy_final, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, b,
+                       nblk, n_colours, max_blocks);
     return hipGetLastError();
 }
 

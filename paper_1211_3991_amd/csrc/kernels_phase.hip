@@ -10,12 +10,18 @@
 namespace xy {
 namespace {
 
-// Thread (site, q) updates slots 4q..4q+3 of one site: the neighbour index is
-// read once for the four slots and their four angles are one 8-byte load, so
-// graph and gather traffic are shared by four replicas.  Random words: one
-// Philox call per (site, sweep, slot 4q), word r for slot 4q + r.  (cos, sin)
-// of an angle: the form kTrig of Trig (an LDS table loaded by the block, or
-// the hardware sine and cosine).
+// A thread (site, q) of a work unit updates slots 4q..4q+3 of one site: the
+// neighbour index is read once for the four slots and their four angles are
+// one 8-byte load, so graph and gather traffic are shared by four replicas.
+// Random words: one Philox call per (site, sweep, slot 4q), word r for slot
+// 4q + r.  (cos, sin) of an angle: the form kTrig of Trig (an LDS table
+// loaded by the workgroup, or the hardware sine and cosine).
+//
+// A work unit is two int4: the pool offsets of the columns of the block's
+// first two chunks, the sample's state base / 8, the block's first site; then
+// sample, phase-sample index, block index in the colour class, and
+// kmin | kmax << 8 | (sites - 1) << 16 | (first site's chunk lane) << 24.
+// The index loads depend on nothing but the unit.
 
 // The hardware deals the workgroups of a launch to the 8 XCDs in turn
 // (workgroup w to XCD w mod 8).  Work unit of workgroup `lin` out of `n`:
@@ -27,62 +33,94 @@ __device__ __forceinline__ int xcd_contiguous(int lin, int n)
     return x * per + min(x, rem) + k;
 }
 
-template <typename Idx, bool kLast, int kTrig>
-__global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const int4 *units, int colour, int sub,
-                                                            int max_blocks, int grp)
+// Lane layout of a workgroup: Lq = R/4 threads per site, S sites.
+struct PhaseLanes {
+    int R, Lq, S, sl, q;
+};
+
+__device__ __forceinline__ PhaseLanes phase_lanes(const DevBatch &b)
 {
-    __shared__ float esum[kLast ? kPhaseBlock * 4 : 1];
-    __shared__ float2 tab[Trig<kTrig>::kBytes ? Trig<kTrig>::kBytes / sizeof(float2) : 1];
-    const int R = b.R, Lq = R >> 2, S = kPhaseBlock / Lq;
-    const int t = threadIdx.x;
+    PhaseLanes pl;
+    pl.R = b.R;
+    pl.Lq = pl.R >> 2;
+    pl.S = kPhaseBlock / pl.Lq;
     // t / Lq through the FP32 reciprocal: exact for t < 256, Lq <= 64, even
     // with a reciprocal 1 ulp off (checked exhaustively)
-    const int sl = (int)(((float)t + 0.5f) * __builtin_amdgcn_rcpf((float)Lq)), q = t - sl * Lq;
-    // work unit, two int4: the pool offsets of the columns of the block's
-    // first two chunks, the sample's state base / 8, the block's first site;
-    // then sample, phase-sample index, block index in the colour class, and
-    // kmin | kmax << 8 | (sites - 1) << 16 | (first site's chunk lane) << 24.
-    // The index loads depend on nothing but the unit.
-    const int u = xcd_contiguous(blockIdx.x, gridDim.x);
-    const int4 ua = units[2 * u], ub = units[2 * u + 1];
-    const int s = ub.x, k_ph = ub.y, bx = ub.z;
-    const int kmin = ub.w & 255, kmax = (ub.w >> 8) & 255, n_act = ((ub.w >> 16) & 255) + 1;
-    const int lnA = (int)((uint32_t)ub.w >> 24);
-    // lanes past the block's last site mirror that site and store nothing
-    const bool active = sl < n_act;
-    const int sc = min(sl, n_act - 1);
-    const int i = ua.w + sc;                                      // colour-major site index in the sample
-    const SampleDesc &d = b.desc[s];
+    pl.sl = (int)(((float)threadIdx.x + 0.5f) * __builtin_amdgcn_rcpf((float)pl.Lq));
+    pl.q = (int)threadIdx.x - pl.sl * pl.Lq;
+    return pl;
+}
+
+// Where one thread's work of a unit lives: its site, whether it stores (lanes
+// past the unit's last site mirror that site and store nothing), its chunk
+// column (row k at colb + k * 64 * sizeof(Idx)) and the sample's state.
+struct UnitPtrs {
+    int i;
+    bool active;
+    const char *colb;
+    char *Ab;
+};
+
+template <typename Idx>
+__device__ __forceinline__ UnitPtrs unit_ptrs(const DevBatch &b, const PhaseLanes &pl, const int4 &ua, const int4 &ub,
+                                              int colour)
+{
+    UnitPtrs p;
+    const int n_act = ((ub.w >> 16) & 255) + 1, lnA = (int)((uint32_t)ub.w >> 24);
+    p.active = pl.sl < n_act;
+    const int sc = min(pl.sl, n_act - 1);
+    p.i = ua.w + sc;                                              // colour-major site index in the sample
     const int pos = lnA + sc, ln = pos & 63;
     uint32_t cbase = pos < 64 ? (uint32_t)ua.x : (uint32_t)ua.y;  // pool element offset of the site's chunk
     if (pos >= 128) {                                             // blocks of more than 64 sites (R < 16)
+        const SampleDesc &d = b.desc[ub.x];
         const int c0 = d.colour_off[colour];
-        cbase = (uint32_t)(d.sell_col + b.i32[d.sell_ptr + d.chunk_off[colour] + ((i - c0) >> 6)]);
+        cbase = (uint32_t)(d.sell_col + b.i32[d.sell_ptr + d.chunk_off[colour] + ((p.i - c0) >> 6)]);
     }
-    const char *colb = reinterpret_cast<const char *>(sizeof(Idx) == 2 ? (const void *)b.u16 : (const void *)b.i32) +
-                       ((uint64_t)cbase + (uint32_t)ln) * sizeof(Idx);
-    // [site][Lq] words of 4 angles; 32-bit byte offsets from the sample's base
-    char *Ab = reinterpret_cast<char *>(b.state) + (uint64_t)(uint32_t)ua.z * 16u;
-    const uint32_t q8 = 8u * (uint32_t)q, Lq8 = 8u * (uint32_t)Lq;
-    auto word = [&](int j) -> uint2 & { return *reinterpret_cast<uint2 *>(Ab + (__umul24((uint32_t)j, Lq8) + q8)); };
+    p.colb = reinterpret_cast<const char *>(sizeof(Idx) == 2 ? (const void *)b.u16 : (const void *)b.i32) +
+             ((uint64_t)cbase + (uint32_t)ln) * sizeof(Idx);
+    p.Ab = reinterpret_cast<char *>(b.state) + (uint64_t)(uint32_t)ua.z * 16u;
+    return p;
+}
 
-    // 8 rows of neighbour indices (every chunk has at least 8; a site's rows
-    // past its degree hold the site itself, which is never its own
-    // neighbour), then the 4-slot angle words of all 8, in flight before the
-    // first use (unconditional loads keep the wait counts exact; a padding
-    // row reads the site's own word)
+// [site][Lq] words of 4 angles; 32-bit byte offsets from the sample's base
+__device__ __forceinline__ uint2 &angle_word(char *Ab, const PhaseLanes &pl, int j)
+{
+    return *reinterpret_cast<uint2 *>(Ab + (__umul24((uint32_t)j, 8u * (uint32_t)pl.Lq) + 8u * (uint32_t)pl.q));
+}
+
+// 8 rows of neighbour indices (every chunk has at least 8; a site's rows past
+// its degree hold the site itself, which is never its own neighbour)
+template <typename Idx>
+__device__ __forceinline__ void load_rows(const char *colb, int *jj)
+{
     static_assert(kSellRows >= 8, "the phase kernel reads 8 rows of every chunk");
-    int jj[8];
-    uint2 vv[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) jj[k] = (int)*reinterpret_cast<const Idx *>(colb + k * 64 * sizeof(Idx));
+}
+
+// the 4-slot angle words of those 8 (unconditional loads keep the wait
+// counts exact; a padding row reads the site's own word)
+__device__ __forceinline__ void load_words(char *Ab, const PhaseLanes &pl, const int *jj, uint2 *vv)
+{
 #pragma unroll
-    for (int k = 0; k < 8; ++k) vv[k] = word(jj[k]);
-    // the (cos, sin) table of a table form, while the gathers are in flight
-    if constexpr (Trig<kTrig>::kBytes > 0) {
-        Trig<kTrig>::load(tab, b, t, kPhaseBlock);
-        __syncthreads();
-    }
+    for (int k = 0; k < 8; ++k) vv[k] = angle_word(Ab, pl, jj[k]);
+}
+
+// The update of one unit's sites by this thread, from its loaded rows jj and
+// neighbour words vv.  kLast: the last sub-sweep of the sweep, which also sums
+// the links to lower colours into the energy partials (uses esum and a
+// workgroup barrier, two when kReuse: esum is used again for another unit;
+// every thread of the workgroup calls it).
+template <typename Idx, bool kLast, int kTrig, bool kReuse>
+__device__ __forceinline__ void update_unit(const DevBatch &b, const PhaseLanes &pl, const float2 *tab, float *esum,
+                                            int colour, int sub, int max_blocks, uint32_t sweep, const int4 &ua,
+                                            const int4 &ub, const UnitPtrs &p, const int *jj, const uint2 *vv)
+{
+    const int R = pl.R, Lq = pl.Lq, S = pl.S, q = pl.q, i = p.i;
+    const int s = ub.x, k_ph = ub.y, bx = ub.z;
+    const int kmin = ub.w & 255, kmax = (ub.w >> 8) & 255;
+    const SampleDesc &d = b.desc[s];
     float beta[4];
     {
         const int4 tq = *reinterpret_cast<const int4 *>(b.T_of_slot + s * R + 4 * q);
@@ -101,9 +139,9 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
         const uint32_t th[4] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16};
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const float2 u = Trig<kTrig>::unit(th[r], tab);
-            hx[r] = first ? u.x : hx[r] + u.x;
-            hy[r] = first ? u.y : hy[r] + u.y;
+            const float2 e = Trig<kTrig>::unit(th[r], tab);
+            hx[r] = first ? e.x : hx[r] + e.x;
+            hy[r] = first ? e.y : hy[r] + e.y;
         }
         if (kLast && j < c0) {
 #pragma unroll
@@ -118,15 +156,14 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
     if (kmax > 8) {                                               // uniform: rows past the eighth
         const int dg = b.u8[d.deg + i];
         for (int k = 8; k < dg; ++k) {
-            const int j = (int)*reinterpret_cast<const Idx *>(colb + k * 64 * (int)sizeof(Idx));
-            add(word(j), j, false);
+            const int j = (int)*reinterpret_cast<const Idx *>(p.colb + k * 64 * (int)sizeof(Idx));
+            add(angle_word(p.Ab, pl, j), j, false);
         }
     }
-    const uint32_t sweep = b.ctl[grp].sweep;
     const U4 w = philox4x32_10({(uint32_t)i, sweep, (uint32_t)(4 * q), tag(sub == 0 ? kMet : kOR, (uint32_t)sub)},
                                d.seed_lo, d.seed_hi);
     const uint32_t words[4] = {w.x, w.y, w.z, w.w};
-    const uint2 me = word(i);
+    const uint2 me = angle_word(p.Ab, pl, i);
     const uint32_t cur_th[4] = {me.x & 0xFFFFu, me.x >> 16, me.y & 0xFFFFu, me.y >> 16};
     uint32_t out[4];
     float e_q[4];
@@ -140,12 +177,13 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
         const bool acc = accept_move(dE, beta[r], words[r], (uint32_t)i, sweep, (uint32_t)slot, (uint32_t)sub, d);
         out[r] = acc ? th_new : th;
         const float2 f = acc ? nu : cur;
-        e_q[r] = active ? -(f.x * lx[r] + f.y * ly[r]) : 0.f;
+        e_q[r] = p.active ? -(f.x * lx[r] + f.y * ly[r]) : 0.f;
     }
-    if (active) word(i) = make_uint2(out[0] | (out[1] << 16), out[2] | (out[3] << 16));
+    if (p.active) angle_word(p.Ab, pl, i) = make_uint2(out[0] | (out[1] << 16), out[2] | (out[3] << 16));
     if constexpr (kLast) {
-        // per-slot energy of this block, summed in a fixed order, to
+        // per-slot energy of this unit, summed in a fixed order, to
         // epart[k_ph][colour][block][slot]; a final pass adds the blocks in order
+        const int t = threadIdx.x;
 #pragma unroll
         for (int r = 0; r < 4; ++r) esum[t * 4 + r] = e_q[r];
         __syncthreads();
@@ -155,6 +193,100 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
             for (int k = 0; k < S; ++k) acc += (double)esum[(k * Lq + qq) * 4 + r];
             b.epart[(((int64_t)k_ph * kMaxColours + colour) * max_blocks + bx) * R + t] = acc;
         }
+        if (kReuse) __syncthreads();                              // before esum is reused
+    }
+}
+
+// One work unit per workgroup (gridDim.x == n_units).
+template <typename Idx, bool kLast, int kTrig>
+__global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const int4 *units, int n_units, int colour,
+                                                            int sub, int max_blocks, int grp)
+{
+    __shared__ float esum[kLast ? kPhaseBlock * 4 : 1];
+    __shared__ float2 tab[Trig<kTrig>::kBytes ? Trig<kTrig>::kBytes / sizeof(float2) : 1];
+    const PhaseLanes pl = phase_lanes(b);
+    const int u = xcd_contiguous(blockIdx.x, n_units);
+    const int4 ua = units[2 * u], ub = units[2 * u + 1];
+    const UnitPtrs p = unit_ptrs<Idx>(b, pl, ua, ub, colour);
+    // rows and neighbour words in flight before the first use
+    int jj[8];
+    uint2 vv[8];
+    load_rows<Idx>(p.colb, jj);
+    load_words(p.Ab, pl, jj, vv);
+    // the (cos, sin) table of a table form, while the gathers are in flight
+    if constexpr (Trig<kTrig>::kBytes > 0) {
+        Trig<kTrig>::load(tab, b, threadIdx.x, kPhaseBlock);
+        __syncthreads();
+    }
+    update_unit<Idx, kLast, kTrig, false>(b, pl, tab, esum, colour, sub, max_blocks, b.ctl[grp].sweep, ua, ub, p, jj,
+                                          vv);
+}
+
+// Fewer workgroups than units: workgroup w takes units w, w + gridDim.x, ...
+// through xcd_contiguous (gridDim.x a multiple of 8 keeps all of them in its
+// XCD's run of units), in a three-stage pipeline: while unit k is computed,
+// the neighbour words of unit k + 1 and the index rows of unit k + 2 are in
+// flight, and the descriptor of unit k + 3 is being read.  The loop count is
+// uniform over the workgroup (it depends on blockIdx.x only).
+template <typename Idx, bool kLast, int kTrig>
+__global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase_loop(DevBatch b, const int4 *units, int n_units,
+                                                                 int colour, int sub, int max_blocks, int grp)
+{
+    __shared__ float esum[kLast ? kPhaseBlock * 4 : 1];
+    __shared__ float2 tab[Trig<kTrig>::kBytes ? Trig<kTrig>::kBytes / sizeof(float2) : 1];
+    const PhaseLanes pl = phase_lanes(b);
+    const int stride = (int)gridDim.x;
+    const int lin0 = blockIdx.x;
+    auto unit_at = [&](int lin, int4 &ua, int4 &ub) {
+        const int u = xcd_contiguous(lin, n_units);
+        ua = units[2 * u];
+        ub = units[2 * u + 1];
+    };
+    // prologue: unit 0 with its words in flight, unit 1 with its rows in
+    // flight, the descriptor of unit 2
+    int4 ua0, ub0, ua1 = make_int4(0, 0, 0, 0), ub1 = ua1, ua2 = ua1, ub2 = ua1;
+    unit_at(lin0, ua0, ub0);
+    UnitPtrs p0 = unit_ptrs<Idx>(b, pl, ua0, ub0, colour), p1 = p0;
+    int jj0[8], jj1[8];
+    uint2 vv0[8];
+    load_rows<Idx>(p0.colb, jj0);
+    load_words(p0.Ab, pl, jj0, vv0);
+    bool has1 = lin0 + stride < n_units, has2 = lin0 + 2 * stride < n_units;
+    if (has1) {
+        unit_at(lin0 + stride, ua1, ub1);
+        p1 = unit_ptrs<Idx>(b, pl, ua1, ub1, colour);
+        load_rows<Idx>(p1.colb, jj1);
+    }
+    if (has2) unit_at(lin0 + 2 * stride, ua2, ub2);
+    if constexpr (Trig<kTrig>::kBytes > 0) {
+        Trig<kTrig>::load(tab, b, threadIdx.x, kPhaseBlock);
+        __syncthreads();
+    }
+    const uint32_t sweep = b.ctl[grp].sweep;
+    for (int lin = lin0;; lin += stride) {
+        // stage the next units: words of unit 1, rows of unit 2, descriptor of unit 3
+        uint2 vv1[8];
+        int jj2[8];
+        UnitPtrs p2 = p1;
+        int4 ua3 = ua2, ub3 = ub2;
+        const bool has3 = lin + 3 * stride < n_units;
+        if (has1) load_words(p1.Ab, pl, jj1, vv1);
+        if (has2) {
+            p2 = unit_ptrs<Idx>(b, pl, ua2, ub2, colour);
+            load_rows<Idx>(p2.colb, jj2);
+        }
+        if (has3) unit_at(lin + 3 * stride, ua3, ub3);
+
+        update_unit<Idx, kLast, kTrig, true>(b, pl, tab, esum, colour, sub, max_blocks, sweep, ua0, ub0, p0, jj0, vv0);
+
+        if (!has1) break;
+        ua0 = ua1; ub0 = ub1; p0 = p1;
+        ua1 = ua2; ub1 = ub2; p1 = p2;
+        ua2 = ua3; ub2 = ub3;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) { jj0[k] = jj1[k]; vv0[k] = vv1[k]; jj1[k] = jj2[k]; }
+        has1 = has2;
+        has2 = has3;
     }
 }
 
@@ -163,19 +295,30 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
 int fix16_phase_sites_per_block(int R) { return kPhaseBlock / (R / 4); }
 
 template <int kTrig>
-void (*phase_kernel(int idx16, int last))(DevBatch, const int4 *, int, int, int, int)
+void (*phase_kernel(int idx16, int last, bool loop))(DevBatch, const int4 *, int, int, int, int, int)
 {
+    if (loop)
+        return idx16 ? (last ? k_fix16_phase_loop<uint16_t, true, kTrig> : k_fix16_phase_loop<uint16_t, false, kTrig>)
+                     : (last ? k_fix16_phase_loop<int32_t, true, kTrig> : k_fix16_phase_loop<int32_t, false, kTrig>);
     return idx16 ? (last ? k_fix16_phase<uint16_t, true, kTrig> : k_fix16_phase<uint16_t, false, kTrig>)
                  : (last ? k_fix16_phase<int32_t, true, kTrig> : k_fix16_phase<int32_t, false, kTrig>);
 }
 
 hipError_t launch_fix16_phase(const DevBatch &b, const int4 *units, int colour, int sub,
-                              int last, int n_units, int max_blocks, int grp, hipStream_t s)
+                              int last, int n_units, int max_blocks, int grp, int max_grid, hipStream_t s)
 {
     if (n_units == 0) return hipSuccess;
-    auto k = b.trig == 0 ? phase_kernel<0>(b.idx16, last) : b.trig == 1 ? phase_kernel<1>(b.idx16, last)
-                                                                         : phase_kernel<2>(b.idx16, last);
-    hipLaunchKernelGGL(k, dim3((unsigned)n_units), dim3(kPhaseBlock), 0, s, b, units, colour, sub, max_blocks, grp);
+    // max_grid >= 8: at most that many workgroups (rounded down to a multiple
+    // of 8, so that a workgroup's units stay on its XCD), each taking every
+    // gridDim.x-th unit, when that is fewer than the units; else one
+    // workgroup per unit.  Every workgroup has at least one unit.
+    const int g8 = max_grid & ~7;
+    const bool loop = g8 >= 8 && g8 < n_units;
+    const int grid = loop ? g8 : n_units;
+    auto k = b.trig == 0 ? phase_kernel<0>(b.idx16, last, loop)
+                         : b.trig == 1 ? phase_kernel<1>(b.idx16, last, loop) : phase_kernel<2>(b.idx16, last, loop);
+    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kPhaseBlock), 0, s, b, units, n_units, colour, sub, max_blocks,
+                       grp);
     return hipGetLastError();
 }
 

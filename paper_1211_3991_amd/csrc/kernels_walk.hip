@@ -16,6 +16,8 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "xy_internal.hpp"
@@ -166,20 +168,23 @@ extern "C" xy_status xy_walk_bytes(const xy_graph *const *g, int n_graphs, size_
     return XY_OK;
 }
 
-extern "C" xy_status xy_random_walk(const xy_graph *const *g, int n_graphs, int n_walkers, int n_steps,
-                                    const uint64_t *seeds, int start_mode, void *d_graph, size_t graph_bytes,
-                                    uint64_t *d_hist, void *stream, float *kernel_ms)
+// Workspace of xy_random_walk_noalloc: the walk records of its graphs.  Each
+// device holds its own copy from the library's load to the end of the
+// process; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device (kept per device).
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// The walk: stages the graphs' walk records from a host image into d_graph
+// (at least p.total bytes, 256-byte aligned), then runs the walks.
+xy_status walk_run(const xy_graph *const *g, int n_graphs, int n_walkers, int n_steps, const uint64_t *seeds,
+                   int start_mode, const WalkPlan &plan, void *d_graph, uint64_t *d_hist, void *stream,
+                   float *kernel_ms)
 {
-    if (n_walkers < 0 || n_steps < 0 || n_steps >= (1 << 24) || !seeds || !d_graph || !d_hist ||
-        (start_mode != 0 && start_mode != 1))
-        return set_error(XY_EINVAL, "xy_random_walk: bad arguments");
-    if ((reinterpret_cast<uintptr_t>(d_graph) & 255) != 0)
-        return set_error(XY_EINVAL, "xy_random_walk: d_graph must be 256-byte aligned");
     try {
-        WalkPlan p;
-        const xy_status st = plan_walk(g, n_graphs, p);
-        if (st != XY_OK) return st;
-        if (graph_bytes < p.total) return set_error(XY_EINVAL, "xy_random_walk: d_graph smaller than xy_walk_bytes");
+        WalkPlan p = plan;
         std::vector<unsigned char> img(p.total, 0);
         int4 *od = reinterpret_cast<int4 *>(img.data() + p.off_od);
         int32_t *i32 = reinterpret_cast<int32_t *>(img.data() + p.off_i32);
@@ -277,4 +282,74 @@ extern "C" xy_status xy_random_walk(const xy_graph *const *g, int n_graphs, int 
     } catch (const std::bad_alloc &) {
         return set_error(XY_ENOMEM, "xy_random_walk: host allocation failed");
     }
+}
+
+xy_status walk_args(int n_walkers, int n_steps, const uint64_t *seeds, int start_mode, const uint64_t *d_hist)
+{
+    if (n_walkers < 0 || n_steps < 0 || n_steps >= (1 << 24) || !seeds || !d_hist ||
+        (start_mode != 0 && start_mode != 1))
+        return set_error(XY_EINVAL, "xy_random_walk: bad arguments");
+    return XY_OK;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on the current device (looked up on the first call
+// on that device, with it current).
+hipError_t scratch_address(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255) != 0) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" xy_status xy_random_walk(const xy_graph *const *g, int n_graphs, int n_walkers, int n_steps,
+                                    const uint64_t *seeds, int start_mode, void *d_graph, size_t graph_bytes,
+                                    uint64_t *d_hist, void *stream, float *kernel_ms)
+{
+    xy_status st = walk_args(n_walkers, n_steps, seeds, start_mode, d_hist);
+    if (st != XY_OK) return st;
+    if (!d_graph) return set_error(XY_EINVAL, "xy_random_walk: bad arguments");
+    if ((reinterpret_cast<uintptr_t>(d_graph) & 255) != 0)
+        return set_error(XY_EINVAL, "xy_random_walk: d_graph must be 256-byte aligned");
+    WalkPlan p;
+    st = plan_walk(g, n_graphs, p);
+    if (st != XY_OK) return st;
+    if (graph_bytes < p.total) return set_error(XY_EINVAL, "xy_random_walk: d_graph smaller than xy_walk_bytes");
+    return walk_run(g, n_graphs, n_walkers, n_steps, seeds, start_mode, p, d_graph, d_hist, stream, kernel_ms);
+}
+
+extern "C" xy_status xy_random_walk_noalloc(const xy_graph *const *g, int n_graphs, int n_walkers, int n_steps,
+                                            const uint64_t *seeds, int start_mode, uint64_t *d_hist, void *stream,
+                                            float *kernel_ms)
+{
+    xy_status st = walk_args(n_walkers, n_steps, seeds, start_mode, d_hist);
+    if (st != XY_OK) return st;
+    WalkPlan p;
+    st = plan_walk(g, n_graphs, p);
+    if (st != XY_OK) return st;
+    if (p.total > kScratchBytes)
+        return set_error(XY_EINVAL, "xy_random_walk_noalloc: the walk graphs need " + std::to_string(p.total) +
+                                        " bytes, more than the " + std::to_string(kScratchBytes) +
+                                        "-byte static workspace (use xy_random_walk)");
+    void *ws = nullptr;
+    const hipError_t e = scratch_address(&ws);
+    if (e != hipSuccess)
+        return set_error(XY_EHIP, std::string("xy_random_walk_noalloc: workspace address: ") + hipGetErrorString(e));
+    return walk_run(g, n_graphs, n_walkers, n_steps, seeds, start_mode, p, ws, d_hist, stream, kernel_ms);
 }

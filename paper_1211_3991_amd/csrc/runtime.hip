@@ -36,6 +36,7 @@ struct xy_batch {
     std::vector<size_t> phase_unit_off;       // per colour: first int4 of its units in d_units
     int4 *d_units = nullptr;                  // two int4 per unit (see k_fix16_phase)
     int phase_stride = 0;                     // largest block count (energy partial stride)
+    int phase_grid = 0;                       // workgroups per colour-phase launch (0: one per work unit)
     // the phase launches of a sweep split by sample over the caller's stream
     // and `aux`, so that the ramp and tail of one launch overlap the other
     // stream's work; fork and join through events on the caller's stream
@@ -253,8 +254,16 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
     wl.pt_acc = off;    off = align_up(off + 8 * GR, 256);
     wl.pt_try = off;    off = align_up(off + 8 * GR, 256);
     wl.partial = off;   off = align_up(off + ((fix16 && n_phase == 0) ? 0 : 8 * 64 * 11 * GR), 256);
-    wl.epart = off;     off = align_up(off + 8 * (size_t)n_phase * kMaxColours * phase_blocks * R, 256);
-    p.phase_blocks = phase_blocks;
+    // FP64: the energy partials of the last sub-sweep, [G][Qmax][blocks][R]
+    int fp64_blocks = 0;
+    if (!fix16)
+        for (int s = 0; s < G; ++s)
+            for (int c = 0; c < g[s]->Q; ++c)
+                fp64_blocks = std::max(fp64_blocks, fp64_phase_blocks(g[s]->colour_off[c + 1] - g[s]->colour_off[c], R));
+    wl.epart = off;
+    off = align_up(off + (fix16 ? 8 * (size_t)n_phase * kMaxColours * phase_blocks * R
+                                : 8 * (size_t)G * p.Qmax * fp64_blocks * R), 256);
+    p.phase_blocks = fix16 ? phase_blocks : fp64_blocks;
     wl.total = off;
     p.state_bytes = align_up(state_elems * (precision == XY_FP64 ? 16 : 2), 256);
     p.obs_bytes = align_up((size_t)max_records * GR * XY_NOBS * 8, 256);
@@ -371,6 +380,7 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
         b->wl = p.wl;
         b->state_bytes = p.state_bytes;
         b->state_off = p.state_off;
+        b->phase_stride = p.phase_blocks;
         b->max_class.assign(p.Qmax, 0);
         b->perm.resize(G);
         b->n.resize(G);
@@ -522,6 +532,7 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
             b->unit_k.resize(units.size() / 2);
             for (size_t a = 0; a < b->unit_k.size(); ++a) b->unit_k[a] = units[2 * a + 1].y;
             b->n_phase = (int)phase.size();
+            if (const char *env = std::getenv("XY_PHASE_GRID")) b->phase_grid = std::max(0, std::atoi(env));
             int n_streams = 2;   // XY_PHASE_STREAMS=1..4 overrides
             if (const char *env = std::getenv("XY_PHASE_STREAMS")) n_streams = std::atoi(env);
             const hipError_t e = setup_phase_groups(b, n_streams);
@@ -658,11 +669,17 @@ hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream
     }
     const int n_st = 1 + (int)b->aux.size();
     if (b->precision == XY_FP64) {
+        // the energies for tempering are summed in the last sub-sweep, except
+        // on a measurement sweep, whose observation pass sums them anyway
+        const int fuse = do_pt && !do_rec;
         for (int sub = 0; sub <= n_or && e == hipSuccess; ++sub)
             for (int c = 0; c < b->Qmax && e == hipSuccess; ++c)
-                e = launch_fp64_phase(b->dev, c, sub == 0, b->max_class[c], s);
+                e = launch_fp64_phase(b->dev, c, sub == 0, fuse && sub == n_or, b->max_class[c], b->Qmax,
+                                      b->phase_stride, s);
         if (e == hipSuccess && ev1) e = hipEventRecord(ev1, s);
-        if (e == hipSuccess && (do_pt || do_rec)) e = launch_fp64_observe(b->dev, do_rec, nullptr, s);
+        if (e == hipSuccess && do_rec) e = launch_fp64_observe(b->dev, 1, nullptr, s);
+        if (e == hipSuccess && fuse)
+            e = launch_fp64_energy_final(b->dev, b->max_class.data(), b->Qmax, b->phase_stride, s);
     } else if (b->indep) {
         // each group: its colour phases, then its energies, tempering,
         // records and sweep counter, all on its own stream
@@ -672,7 +689,7 @@ hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream
                 const int4 *u = b->d_units + b->phase_unit_off[c];
                 for (int g = 0; g < n_st && e == hipSuccess; ++g)
                     e = launch_fix16_phase(b->dev, u + 2 * (size_t)bd[g], c, sub, sub == n_or, bd[g + 1] - bd[g],
-                                           b->phase_stride, g, g == 0 ? s : b->aux[g - 1]);
+                                           b->phase_stride, g, b->phase_grid, g == 0 ? s : b->aux[g - 1]);
             }
         for (int g = 0; g < n_st && e == hipSuccess; ++g) {
             hipStream_t st = g == 0 ? s : b->aux[g - 1];
@@ -697,7 +714,7 @@ hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream
                 const int4 *u = b->d_units + b->phase_unit_off[c];
                 for (int g = 0; g < n_st && e == hipSuccess; ++g)
                     e = launch_fix16_phase(b->dev, u + 2 * (size_t)bd[g], c, sub, sub == n_or, bd[g + 1] - bd[g],
-                                           b->phase_stride, 0, g == 0 ? s : b->aux[g - 1]);
+                                           b->phase_stride, 0, b->phase_grid, g == 0 ? s : b->aux[g - 1]);
             }
         if (e == hipSuccess && fork) e = join_groups(b, s);
         // the timed part: the sweep kernels (with their fused energies) and the
@@ -1094,6 +1111,21 @@ extern "C" xy_status xy_batch_set_phase_streams(xy_batch *b, int n_streams, void
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
     return e == hipSuccess ? XY_OK : hip_err(e, "xy_batch_set_phase_streams");
+}
+
+extern "C" xy_status xy_batch_set_phase_grid(xy_batch *b, int max_workgroups)
+{
+    if (!b || max_workgroups < 0) return set_error(XY_EINVAL, "xy_batch_set_phase_grid: bad arguments");
+    b->phase_grid = max_workgroups;
+    if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+    return XY_OK;
+}
+
+extern "C" xy_status xy_batch_phase_grid(const xy_batch *b, int *max_workgroups)
+{
+    if (!b || !max_workgroups) return set_error(XY_EINVAL, "xy_batch_phase_grid: NULL argument");
+    *max_workgroups = b->phase_grid;
+    return XY_OK;
 }
 
 extern "C" xy_status xy_batch_phase_streams(const xy_batch *b, int *n_streams)

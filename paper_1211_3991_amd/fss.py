@@ -111,6 +111,40 @@ def app_c_fits(T, N, records, u_star, rho, T_ref):
     return out
 
 
+def kt_eta_run(sizes=(32, 64, 128, 256, 384), samples=32, T=(0.80, 1.00, 16), sweeps=1 << 14, meas_every=16,
+               seed_base=20_000, r_values=(1.0 / 16, -1.0 / 16, 0.0), log=None):
+    """The square-lattice limit (rho -> infinity, z = 4: every link a nearest
+    neighbour; rho = 60 gives exactly the square lattice) and the temperature
+    where eta(T) = 1/4 (Sec. 4, square-lattice limit, Eq. chi_SR):
+    chi = N <|m|^2> ~ L^(2 - eta) (ln L)^(-2r) fitted over the sizes at every
+    ladder temperature, for each log-correction exponent r in r_values.
+    Returns dict(T_eta={r: (T, error)}, eta={r: eta(T) per ladder T}, ...)."""
+    import torch
+
+    import paper_1211_3991_amd as xy
+    ladder = np.linspace(T[0], T[1], int(T[2]))
+    recs = []
+    for L in sizes:
+        if log:
+            log(f"square lattice L={L}: {samples} chains, {sweeps} sweeps")
+        seeds = [seed_base * L + s for s in range(samples)]
+        g = xy.Graph.levy(L, 4, 60.0, seeds[0])
+        b = xy.Batch([g] * samples, ladder, precision="fix16", seeds=seeds, max_records=sweeps // meas_every)
+        b.sweep(sweeps, n_or=5, pt_every=1, meas_every=meas_every)
+        torch.cuda.synchronize()
+        recs.append(b.records().cpu().numpy())
+        b.close()
+    out = {"sizes": list(sizes), "samples": samples, "sweeps": sweeps, "T": ladder.tolist(), "T_eta": {}, "eta": {}}
+    for r in r_values:
+        t, e = analysis.t_eta(ladder, list(sizes), recs, 0.25, r)
+        out["T_eta"][str(r)] = (t, e)
+        out["eta"][str(r)] = analysis.eta_of_T(ladder, list(sizes), recs, r).tolist()
+    rec_last = np.asarray(recs[-1])[len(recs[-1]) // 2:]
+    out["E_per_site_largest"] = (rec_last[:, :, :, analysis.E].mean(axis=(0, 1)) / (sizes[-1] ** 2)).tolist()
+    out["records"] = recs
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--rho", type=lambda v: float(Fraction(v)), default=0.0, help="e.g. 0, 7/3, 3.5")

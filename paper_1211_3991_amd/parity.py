@@ -2,7 +2,7 @@
 
 Both precisions run the method (App. B: Metropolis + over-relaxation sweeps
 with parallel tempering every sweep) on the same graphs and temperature
-ladder from independent uniform random starts, for the same number of sweeps
+ladder from the ordered start (or the random one), for the same number of sweeps
 and the same measurement cadence; their records of E, |m|^2, |m|^4, F_x and
 F_y (Sec. 3) are then compared with ``analysis.compare_chains``: per (sample,
 temperature) with jackknife errors over time bins, and disorder-paired per
@@ -38,12 +38,28 @@ def build_graphs(samples, threads=None):
         return list(ex.map(lambda s: Graph.levy(s.L, s.z, s.rho, s.seed), samples))
 
 
-def run_records(graphs, T, precision, seeds, n_sweeps, meas_every, n_or=5, pt_every=1, tune=False, chunk=0):
-    """Records [n_rec, G, n_T, 8] of n_sweeps sweeps from the random start."""
+def cold_state(graphs, n_T, precision):
+    """Every spin along x (angle 0) in every slot: the ordered start."""
+    if precision == "fp64":
+        out = []
+        for g in graphs:
+            a = np.zeros((n_T, g.n, 2))
+            a[:, :, 0] = 1.0
+            out.append(a)
+        return out
+    return [np.zeros((n_T, g.n), np.uint16) for g in graphs]
+
+
+def run_records(graphs, T, precision, seeds, n_sweeps, meas_every, n_or=5, pt_every=1, tune=False, chunk=0,
+                start="cold"):
+    """Records [n_rec, G, n_T, 8] of n_sweeps sweeps from the ordered start
+    (start="cold") or the library's random start ("random")."""
     import torch
     stream = torch.cuda.Stream()
     b = Batch(graphs, T, precision=precision, seeds=seeds, max_records=n_sweeps // meas_every, stream=stream)
     try:
+        if start == "cold":
+            b.set_state(cold_state(graphs, np.shape(T)[-1], precision), sweep=0)
         if tune and precision == "fix16":
             b.autotune(sweeps=1, n_or=n_or, use_cache=False)
         if chunk:
@@ -85,20 +101,26 @@ def compare(rec16, rec64, n_bins=20, keep=0.5):
     return out
 
 
-def fix16_vs_fp64(wl, n_sweeps, meas_every=4, n_bins=20, keep=0.5, graphs=None, chunk=32, tune=True):
+def fix16_vs_fp64(wl, n_sweeps, meas_every=4, n_bins=20, keep=0.5, graphs=None, chunk=32, tune=True, start="cold"):
     """Runs both precisions on workload wl and compares them; returns the
-    summary (JSON-able) and the two record arrays."""
+    summary (JSON-able) and the two record arrays.
+
+    start="cold": both from the ordered state, so that the low-temperature
+    chains do not freeze into the twisted (winding) states a random start
+    leaves on the torus, which relax only through vortex pairs and would make
+    one chain's window differ from another's by far more than its own
+    fluctuations; "random": the library's random start."""
     graphs = graphs if graphs is not None else build_graphs(wl.samples)
     seeds16 = np.array([s.seed for s in wl.samples], np.uint64)
     t0 = time.perf_counter()
     rec16 = run_records(graphs, wl.T, "fix16", seeds16, n_sweeps, meas_every, wl.n_or, wl.pt_every, tune=tune,
-                        chunk=chunk if chunk % meas_every == 0 else 0)
+                        chunk=chunk if chunk % meas_every == 0 else 0, start=start)
     t1 = time.perf_counter()
     rec64 = run_records(graphs, wl.T, "fp64", seeds16 + np.uint64(FP64_KEY_OFFSET), n_sweeps, meas_every, wl.n_or,
-                        wl.pt_every)
+                        wl.pt_every, start=start)
     t2 = time.perf_counter()
     out = compare(rec16, rec64, n_bins=n_bins, keep=keep)
-    out.update(workload=wl.name, sweeps=n_sweeps, meas_every=meas_every, keep=keep,
+    out.update(workload=wl.name, sweeps=n_sweeps, meas_every=meas_every, keep=keep, start=start,
                fix16_s=round(t1 - t0, 2), fp64_s=round(t2 - t1, 2),
                fp64_key="sample seed + 2^32", fix16_key="sample seed")
     return out, rec16, rec64
@@ -117,10 +139,11 @@ def main(argv=None):
     ap.add_argument("--sweeps", type=int, default=2048)
     ap.add_argument("--meas-every", type=int, default=4)
     ap.add_argument("--bins", type=int, default=20)
+    ap.add_argument("--start", choices=["cold", "random"], default="cold")
     ap.add_argument("--out", help="write the summary JSON here")
     args = ap.parse_args(argv)
     wl = workloads.ALL[args.workload]()
-    out, _, _ = fix16_vs_fp64(wl, args.sweeps, args.meas_every, args.bins)
+    out, _, _ = fix16_vs_fp64(wl, args.sweeps, args.meas_every, args.bins, start=args.start)
     out["r22_ok"] = r22_ok(out)
     text = json.dumps(out, indent=1)
     if args.out:

@@ -487,3 +487,24 @@ def test_phase_form_state_roundtrip_and_resume(monkeypatch):
     sim = oracle.Sim(1024, e, col, 32, T, 2)
     sim.set_state(_unit(got[0][1]), got[1][1], got[2])
     assert np.allclose(o[1, :, :7], sim.measure()[:, :7], rtol=1e-11, atol=1e-11)
+
+
+def test_phase_threshold_tuner(tmp_path, monkeypatch):
+    """The phase-form threshold of an uneven batch is chosen by timing trial
+    batches: one candidate per distinct graph size plus "none"; the
+    environment is restored and a batch created with the choice has the
+    forms it implies; the result is cached."""
+    monkeypatch.setenv("XY_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    monkeypatch.delenv("XY_FIX16_PHASE_MIN", raising=False)
+    monkeypatch.delenv("XY_FIX16_PHASE", raising=False)
+    from paper_1211_3991_amd import autotune
+    graphs = [xy.Graph.levy(32, 6, 3.5, s) for s in range(6)] + [xy.Graph.levy(128, 6, 3.5, s) for s in range(4)]
+    T = workloads.linear_ladder(1.0, 2.5, 8)
+    rep = autotune.tune_phase_threshold(graphs, T, sweeps=2)
+    assert set(rep["ms_per_sweep"]) == {"1024", "16384", "16385"} and not rep["cached"]
+    assert "XY_FIX16_PHASE_MIN" not in __import__("os").environ
+    monkeypatch.setenv("XY_FIX16_PHASE_MIN", str(rep["phase_min"]))
+    b = xy.Batch(graphs, T, precision="fix16")
+    assert list(b.forms()) == [int(g.n >= rep["phase_min"]) for g in graphs]
+    assert autotune.tune_phase_threshold(graphs, T)["cached"]
+    assert autotune.tune_phase_threshold(graphs, np.arange(1.0, 4.0))["phase_min"] is None   # 3 temperatures

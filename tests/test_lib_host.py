@@ -133,3 +133,21 @@ def test_single_hip_runtime_in_process():
     maps = open("/proc/self/maps").read()
     paths = {ln.split()[-1] for ln in maps.splitlines() if "libamdhip64" in ln}
     assert len(paths) == 1, paths
+
+
+def test_noalloc_walk_rejects_oversized_input_on_the_host():
+    """xy_random_walk_noalloc checks its arguments and the static workspace's
+    limit (32 MiB of walk records) before any device call."""
+    import ctypes
+    n = 2048 * 2048                                   # 16 B of record per site: 64 MiB
+    g = xy.Graph.from_edges(n, np.zeros((0, 2), np.int32), L=2048)
+    garr = (ctypes.c_void_p * 1)(g._h.value)
+    seeds = np.zeros(1, np.uint64)
+    raw = _lib.raw()
+    hist = ctypes.c_void_p(256)                       # never dereferenced: the call returns first
+    assert raw.xy_random_walk_noalloc(garr, 1, 1, 1, ctypes.c_void_p(seeds.ctypes.data), 1, hist, None,
+                                      None) == _lib.XY_EINVAL
+    assert b"static workspace" in raw.xy_last_error()
+    assert raw.xy_random_walk_noalloc(garr, 1, -1, 1, ctypes.c_void_p(seeds.ctypes.data), 1, hist, None,
+                                      None) == _lib.XY_EINVAL
+    assert raw.xy_random_walk_noalloc(garr, 1, 1, 1, None, 1, hist, None, None) == _lib.XY_EINVAL
