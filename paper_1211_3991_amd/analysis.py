@@ -412,6 +412,41 @@ def compare_chains(a, b, n_bins=20, z_bar=3.0):
             "mean_a": ma, "mean_b": mb}
 
 
+def familywise_z_bar(n, dof=np.inf, alpha=1e-3):
+    """|z| that the largest of n independent null comparisons exceeds with
+    probability alpha (Bonferroni; Student t with dof degrees of freedom
+    when the errors are estimated from dof + 1 independent values)."""
+    from scipy import stats
+    p = alpha / (2 * n)
+    return float(stats.norm.isf(p) if not np.isfinite(dof) else stats.t.isf(p, dof))
+
+
+def chi2_dof_bar(n, dof=np.inf, alpha=1e-3, floor=1.5):
+    """Bar on chi^2/dof = mean(z^2) of n comparisons: the larger of `floor`
+    (the fixed bar used for many comparisons) and the value the mean of n
+    independent squared null z exceeds with probability alpha (the chi^2_n / n
+    quantile, times the variance dof / (dof - 2) of a Student t).  For a few
+    tens of comparisons a fixed 1.5 is not a 3-sigma test: chi^2_20 / 20
+    exceeds it with probability 0.07 even for normal z."""
+    from scipy import stats
+    var = dof / (dof - 2.0) if np.isfinite(dof) and dof > 2 else 1.0
+    return max(floor, float(stats.chi2.isf(alpha, n) / n * var))
+
+
+def comparison_ok(summary, kind, dof=np.inf, frac=0.01, alpha=1e-3):
+    """The bar on one set of comparisons (a summary of compare_chains).
+    kind "many" (per (sample, temperature) comparisons, thousands): at most
+    `frac` of them beyond 3 sigma and chi^2/dof at most 1.5.  kind "few"
+    (disorder-paired ones, tens): the largest |z| below familywise_z_bar and
+    chi^2/dof below chi2_dof_bar, with the errors' degrees of freedom."""
+    n = summary["n"]
+    if summary.get("n_undefined", 0) or n == 0:
+        return False
+    if kind == "many":
+        return summary["frac_gt"] <= frac and summary["chi2_dof"] <= 1.5
+    return summary["max_abs"] <= familywise_z_bar(n, dof, alpha) and summary["chi2_dof"] <= chi2_dof_bar(n, dof, alpha)
+
+
 # ---------------------------------------------------------------------------
 # App. C: joint finite-size-scaling fits
 # ---------------------------------------------------------------------------

@@ -126,10 +126,13 @@ def fix16_vs_fp64(wl, n_sweeps, meas_every=4, n_bins=20, keep=0.5, graphs=None, 
     return out, rec16, rec64
 
 
-def r22_ok(summary, frac=0.01, chi2=1.5):
-    """The bar: at most `frac` of the comparisons beyond 3 sigma and
-    chi^2/dof at most `chi2`, for the per-sample and the disorder-paired sets."""
-    return all(summary[k]["frac_gt"] <= frac and summary[k]["chi2_dof"] <= chi2 for k in ("per_sample", "disorder"))
+def r22_ok(summary, n_samples):
+    """The bar (analysis.comparison_ok): per (sample, temperature), at most 1%
+    of the comparisons beyond 3 sigma and chi^2/dof at most 1.5;
+    disorder-paired, the family-wise bar with n_samples - 1 degrees of
+    freedom."""
+    return (analysis.comparison_ok(summary["per_sample"], "many")
+            and analysis.comparison_ok(summary["disorder"], "few", dof=n_samples - 1))
 
 
 def main(argv=None):
@@ -144,7 +147,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     wl = workloads.ALL[args.workload]()
     out, _, _ = fix16_vs_fp64(wl, args.sweeps, args.meas_every, args.bins, start=args.start)
-    out["r22_ok"] = r22_ok(out)
+    out["r22_ok"] = r22_ok(out, len(wl.samples))
     text = json.dumps(out, indent=1)
     if args.out:
         with open(args.out, "w") as fh:

@@ -8,10 +8,12 @@ Bars:
 * few comparisons (pooled means, disorder averages): the largest |z| below
   the quantile a family of that size exceeds with probability 1e-3 under the
   null (Bonferroni, Student t with the errors' degrees of freedom), and
-  chi^2/dof at most 1.5 when there are at least 20 (assert_familywise).
+  chi^2/dof below the larger of 1.5 and its own 1e-3 quantile for that many
+  comparisons (assert_familywise; analysis.familywise_z_bar, chi2_dof_bar).
 """
 import numpy as np
-from scipy import stats
+
+from paper_1211_3991_amd.analysis import chi2_dof_bar, familywise_z_bar
 
 
 def batch_mean_err(x, n_batches=50):
@@ -66,18 +68,16 @@ def assert_r22(z, what=""):
 
 def familywise_bar(n, dof=np.inf, alpha=1e-3):
     """|z| that one of n independent null comparisons exceeds with probability alpha."""
-    p = alpha / (2 * n)
-    return float(stats.norm.isf(p) if not np.isfinite(dof) else stats.t.isf(p, dof))
+    return familywise_z_bar(n, dof, alpha)
 
 
 def assert_familywise(z, what="", dof=np.inf, alpha=1e-3):
     z = np.asarray(z, dtype=np.float64)
     assert np.all(np.isfinite(z)), f"{what}: undefined z"
     bar = familywise_bar(z.size, dof, alpha)
-    chi2 = float(np.mean(z ** 2))
+    chi2, chi2_bar = float(np.mean(z ** 2)), chi2_dof_bar(z.size, dof, alpha)
     msg = f"{what}: n={z.size} max|z|={np.max(np.abs(z)):.2f} (bar {bar:.2f}) chi2/dof={chi2:.3f} " \
-          f"beyond 3: {_outliers(z, 3.0)}"
+          f"(bar {chi2_bar:.2f}) beyond 3: {_outliers(z, 3.0)}"
     print(msg, flush=True)
     assert np.max(np.abs(z)) <= bar, msg
-    if z.size >= 20:
-        assert chi2 <= 1.5, msg
+    assert chi2 <= chi2_bar, msg

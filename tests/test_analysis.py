@@ -237,6 +237,35 @@ def test_compare_chains_calibrated_and_detects_bias():
     assert (1, 9, 0, 0) in {idx for idx, _ in res4["drift"]["outliers"]}
 
 
+def test_comparison_bars_are_calibrated():
+    """The bars the statistical comparisons use, checked by simulation under
+    the null: the family-wise |z| bar and the chi^2/dof bar (without its 1.5
+    floor) are each exceeded by about alpha of the families of independent
+    normal z, and by at most a few alpha when the z are Student t with the
+    stated degrees of freedom; the fixed 1.5 on 20 normal z would false-fail
+    several percent of the time (the reason for the quantile)."""
+    rng = np.random.default_rng(11)
+    alpha, trials = 0.01, 40000
+    for n, dof in ((20, np.inf), (20, 15), (80, 31), (120, 63)):
+        z = rng.standard_normal((trials, n)) if not np.isfinite(dof) else rng.standard_t(dof, (trials, n))
+        zb = analysis.familywise_z_bar(n, dof, alpha)
+        cb = analysis.chi2_dof_bar(n, dof, alpha, floor=0.0)
+        p_max = np.mean(np.abs(z).max(axis=1) > zb)
+        p_chi = np.mean((z ** 2).mean(axis=1) > cb)
+        assert 0.5 * alpha < p_max < 1.5 * alpha, (n, dof, p_max)
+        assert (0.5 * alpha < p_chi < 1.5 * alpha) if not np.isfinite(dof) else (p_chi < 4 * alpha), (n, dof, p_chi)
+    z = rng.standard_normal((trials, 20))
+    assert np.mean((z ** 2).mean(axis=1) > 1.5) > 0.05
+    # comparison_ok applies them to compare_chains summaries
+    few = {"n": 20, "n_undefined": 0, "frac_gt": 0.05, "chi2_dof": 1.65, "max_abs": 2.99}
+    assert analysis.comparison_ok(few, "few", dof=15)
+    assert not analysis.comparison_ok(dict(few, max_abs=6.0), "few", dof=15)
+    assert not analysis.comparison_ok(dict(few, chi2_dof=2.7), "few", dof=15)
+    assert not analysis.comparison_ok(few, "many")
+    assert analysis.comparison_ok(dict(few, n=2000, frac_gt=0.008, chi2_dof=1.1), "many")
+    assert not analysis.comparison_ok(dict(few, n_undefined=1), "few", dof=15)
+
+
 def _fss_records(T, L, nu_bar=2.0, tc=1.93, bn=0.125, dbn=0.1, G=8, n_rec=4, noise=0.0, seed=0):
     """Records of one size whose disorder-averaged U4 follows exact scaling,
     U4(T, N) = 0.5 - 0.02 (T - tc) N^(1/nu_bar) (linear in T, so ladder

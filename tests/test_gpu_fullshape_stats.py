@@ -11,9 +11,12 @@ window, Sec. 4).  The FP64 sweep is the path whose decisions equal the
 oracle's bit for bit (tests/test_gpu_fp64_parity.py, also at this L=256
 shape), so this ties the fixed-point form, at its real shape, to the oracle's
 observables.  The bar: per (sample, temperature, observable) with jackknife
-errors over 20 time bins, and disorder-paired per (temperature, observable),
-at most 1% of the comparisons beyond 3 sigma and chi^2/dof at most 1.5; every
-outlier is printed.  The two chains of a sample follow the same law from the
+errors over 20 time bins (thousands of comparisons), at most 1% beyond 3
+sigma and chi^2/dof at most 1.5; disorder-paired per (temperature,
+observable) (tens of comparisons, errors from the sample-to-sample spread),
+the largest |z| below the 1e-3 family-wise bar and chi^2/dof below the
+larger of 1.5 and its 1e-3 quantile (analysis.comparison_ok); every outlier
+is printed.  The two chains of a sample follow the same law from the
 same initial law, so their windows compare even where a chain is still
 relaxing; the first-against-second-quarter drift of the kept records is
 printed as the equilibration check.
@@ -36,7 +39,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
-from paper_1211_3991_amd import parity  # noqa: E402
+from paper_1211_3991_amd import analysis, parity  # noqa: E402
 
 SWEEPS = {"headline_l256": 2048, "large_l512": 2048}
 
@@ -61,8 +64,9 @@ def test_fix16_matches_fp64_at_full_shape(name):
     n_rec = SWEEPS[name] // 4
     assert rec16.shape == rec64.shape == (n_rec, len(wl.samples), wl.n_T, 8)
     assert np.all(np.isfinite(rec16)) and np.all(np.isfinite(rec64))
-    for k in ("per_sample", "disorder"):
+    G = len(wl.samples)
+    for k, kind in (("per_sample", "many"), ("disorder", "few")):
         s = out[k]
         assert s["n_undefined"] == 0, (k, s)
-        assert s["frac_gt"] <= 0.01, (k, s["frac_gt"], s["outliers"])
-        assert s["chi2_dof"] <= 1.5, (k, s["chi2_dof"])
+        assert analysis.comparison_ok(s, kind, dof=G - 1), (k, s["frac_gt"], s["chi2_dof"], s["max_abs"],
+                                                             s["outliers"])
