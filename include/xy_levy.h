@@ -310,11 +310,12 @@ xy_status xy_random_walk(const xy_graph *const *g, int n_graphs, int n_walkers, 
                          const uint64_t *seeds, int start_mode, void *d_graph, size_t graph_bytes,
                          uint64_t *d_hist, void *stream, float *kernel_ms);
 
-/* xy_random_walk for callers that cannot allocate device memory (code under
- * HIP graph capture, tight serving loops, harnesses that forbid
- * allocation): the same walks, histograms and errors, but the walk graphs
- * are staged in the library's static device workspace instead of a
- * caller-provided d_graph.  The workspace is 32 MiB (33554432 bytes) per
+/* xy_random_walk for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid allocation): the same walks,
+ * histograms and errors, but the walk graphs are staged in the library's
+ * static device workspace instead of a caller-provided d_graph.  Like
+ * xy_random_walk it synchronises `stream` after the upload, so it is not a
+ * call to record into a HIP graph.  The workspace is 32 MiB (33554432 bytes) per
  * device, held from the library's load to the end of the process; a set of
  * graphs whose xy_walk_bytes exceeds it is rejected with XY_EINVAL before any
  * device work.  The call allocates no device memory (it still builds the
