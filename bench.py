@@ -479,13 +479,16 @@ def main():
             parity[k] = {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in pr[k].items()
                          if kk != "outliers"}
             parity[k]["outliers"] = pr[k]["outliers"][:8]
+            if "mv" in pr[k]:
+                parity[k]["mv"] = {kk: pr[k]["mv"][kk] for kk in ("min_p", "chi2_dof", "chi2_dof_bar", "nu", "n_T")}
         parity["max_rel_dev_disorder"] = {k: float(f"{v:.3g}") for k, v in pr["max_rel_dev_disorder"].items()}
         parity["rel_err_disorder"] = {k: float(f"{v:.3g}") for k, v in pr["rel_err_disorder"].items()}
         parity["r22_ok"] = par.r22_ok(pr, len(wl.samples))
         parity["note"] = ("fix16 against the FP64 sweep (bit-tied to the oracle), both from the ordered start with "
                           "independent keys: per (sample, T, observable) with jackknife errors over 20 time bins "
                           "(at most 1% beyond 3 sigma, chi2/dof <= 1.5), and disorder-paired per (T, observable) "
-                          "(family-wise 1e-3 bar); the deviations are relative to the FP64 disorder average")
+                          "(family-wise 1e-3 bar on each z, and Hotelling's test of the five observables of each T, "
+                          "'mv'); the deviations are relative to the FP64 disorder average")
         print(f"# parity: per-sample frac>3 {parity['per_sample']['frac_gt']}, chi2 {parity['per_sample']['chi2_dof']}; "
               f"disorder frac>3 {parity['disorder']['frac_gt']}, chi2 {parity['disorder']['chi2_dof']}",
               file=sys.stderr, flush=True)

@@ -316,11 +316,12 @@ def _eta_curve(T, L, m2_means, r):
     return 2.0 - slope
 
 
-def eta_of_T(T, L, records, r=1.0 / 16, discard=0.5):
+def eta_of_T(T, L, records, r=-1.0 / 16, discard=0.5):
     """eta(T) on a square L x L lattice (Sec. 4, the square-lattice limit,
     Eq. chi_SR): chi = N <|m|^2> ~ L^(2 - eta) (ln L)^(-2r) at each ladder
     temperature, fitted over the sizes (least squares of ln chi + 2r ln ln L
-    against ln L; r = 1/16).  records: one [n_rec, G, n_T, 8] array per size
+    against ln L).  r = -1/16 by default: the KT value in this form, chi ~
+    L^(7/4) (ln L)^(1/8) at T_c (the paper prints the magnitude 1/16).  records: one [n_rec, G, n_T, 8] array per size
     in L.  Returns eta per temperature (sample means of <|m|^2>)."""
     m2 = []
     for rec in records:
@@ -330,7 +331,7 @@ def eta_of_T(T, L, records, r=1.0 / 16, discard=0.5):
     return _eta_curve(T, L, m2, r)
 
 
-def t_eta(T, L, records, eta_target=0.25, r=1.0 / 16, discard=0.5):
+def t_eta(T, L, records, eta_target=0.25, r=-1.0 / 16, discard=0.5):
     """The temperature where eta(T) of eta_of_T reaches eta_target (the KT
     value 1/4 locates T_c, Sec. 4), by linear interpolation along the ladder,
     with a jackknife error over the samples of each size.  Returns (T, error);
@@ -406,10 +407,78 @@ def compare_chains(a, b, n_bins=20, z_bar=3.0):
                 "max_abs": float(np.max(np.abs(zf))) if zf.size else 0.0,
                 "mean": float(np.mean(zf)) if zf.size else 0.0, "outliers": outliers}
 
-    return {"per_sample": summary(z_ps), "disorder": summary(z_dis), "drift": summary(z_drift),
+    dis = summary(z_dis)
+    dis["mv"] = hotelling(d)
+    return {"per_sample": summary(z_ps), "disorder": dis, "drift": summary(z_drift),
             "z_bar": z_bar, "n_bins": n_bins, "records": int(a.shape[0]),
             "z_per_sample": z_ps, "z_disorder": z_dis, "abs_diff_disorder": np.abs(d.mean(axis=0)),
             "mean_a": ma, "mean_b": mb}
+
+
+def hotelling(a, b=None, alpha=1e-3):
+    """Multivariate test, per temperature, that a mean difference of the
+    observables is zero, for observables that move together (E, |m|^2 and
+    |m|^4 of one temperature are strongly correlated, so their z-scores are
+    not independent and a chi^2 of them is not chi^2-distributed).
+
+      a [n, n_T, p]: paired differences, one row per independent unit (e.g.
+                     the samples of a disorder-paired comparison); or, with
+      b [n_b, n_T, p]: two independent sets of per-unit means compared
+                     unpaired (e.g. independent chains of each precision).
+
+    Per temperature, T^2 = d^T S^-1 d with d the mean difference and S its
+    covariance (paired: the sample covariance of the rows / n; unpaired: the
+    sum of the two sets' sample covariances over their sizes), on the
+    eigen-directions of S above 1e-12 of its largest eigenvalue (p_eff of
+    them).  Under the null, (nu - p_eff + 1) T^2 / (p_eff nu) is F(p_eff,
+    nu - p_eff + 1) with nu = n - 1 (Hotelling; unpaired: nu = min(n, n_b) - 1,
+    a conservative choice for unequal covariances).  Returns dict with T2,
+    p_eff and pval per temperature, min_p, and chi2_dof = sum T^2 / sum
+    p_eff with its bar: the larger of 1.5 and the 1 - alpha quantile of
+    c chi^2_k / k, k = sum p_eff, c = nu / (nu - p - 1) the mean of T^2 / p."""
+    from scipy import stats
+    a = np.asarray(a, dtype=np.float64)
+    if b is None:
+        n = a.shape[0]
+        d = a.mean(axis=0)
+        S = np.einsum("gti,gtj->tij", a - d, a - d) / (n - 1) / n
+        nu = n - 1
+    else:
+        b = np.asarray(b, dtype=np.float64)
+        na, nb = a.shape[0], b.shape[0]
+        ma, mb = a.mean(axis=0), b.mean(axis=0)
+        d = ma - mb
+        S = (np.einsum("gti,gtj->tij", a - ma, a - ma) / (na - 1) / na
+             + np.einsum("gti,gtj->tij", b - mb, b - mb) / (nb - 1) / nb)
+        nu = min(na, nb) - 1
+    n_T, p = d.shape
+    T2 = np.empty(n_T)
+    p_eff = np.empty(n_T, dtype=np.int64)
+    pval = np.empty(n_T)
+    for t in range(n_T):
+        w, V = np.linalg.eigh(S[t])
+        keep = w > 1e-12 * max(w.max(), 1e-300)
+        y = V[:, keep].T @ d[t]
+        k = int(keep.sum())
+        T2[t] = float(np.sum(y * y / w[keep])) if k else 0.0
+        p_eff[t] = k
+        if k == 0 or nu - k + 1 <= 0:
+            pval[t] = np.nan
+        else:
+            pval[t] = float(stats.f.sf((nu - k + 1) * T2[t] / (k * nu), k, nu - k + 1))
+    k_tot = int(p_eff.sum())
+    c = nu / (nu - p - 1) if nu - p - 1 > 0 else np.inf
+    bar = max(1.5, float(c * stats.chi2.isf(alpha, k_tot) / k_tot)) if k_tot else np.inf
+    return {"T2": T2.tolist(), "p_eff": p_eff.tolist(), "pval": pval.tolist(),
+            "min_p": float(np.nanmin(pval)) if np.any(np.isfinite(pval)) else float("nan"),
+            "chi2_dof": float(T2.sum() / max(k_tot, 1)), "chi2_dof_bar": bar, "nu": int(nu), "n_T": int(n_T)}
+
+
+def hotelling_ok(mv, alpha=1e-3):
+    """hotelling's bar: every temperature's p-value above alpha / n_T
+    (family-wise over the temperatures) and chi2_dof below its bar."""
+    pv = np.asarray(mv["pval"], dtype=np.float64)
+    return bool(np.all(np.isfinite(pv)) and pv.min() >= alpha / mv["n_T"] and mv["chi2_dof"] <= mv["chi2_dof_bar"])
 
 
 def familywise_z_bar(n, dof=np.inf, alpha=1e-3):
@@ -437,14 +506,20 @@ def comparison_ok(summary, kind, dof=np.inf, frac=0.01, alpha=1e-3):
     """The bar on one set of comparisons (a summary of compare_chains).
     kind "many" (per (sample, temperature) comparisons, thousands): at most
     `frac` of them beyond 3 sigma and chi^2/dof at most 1.5.  kind "few"
-    (disorder-paired ones, tens): the largest |z| below familywise_z_bar and
-    chi^2/dof below chi2_dof_bar, with the errors' degrees of freedom."""
+    (disorder-paired ones, tens): the largest |z| below familywise_z_bar,
+    with the errors' degrees of freedom, and, when the summary carries the
+    multivariate test of the observables of each temperature ("mv", from
+    hotelling), hotelling_ok; else chi^2/dof below chi2_dof_bar."""
     n = summary["n"]
     if summary.get("n_undefined", 0) or n == 0:
         return False
     if kind == "many":
         return summary["frac_gt"] <= frac and summary["chi2_dof"] <= 1.5
-    return summary["max_abs"] <= familywise_z_bar(n, dof, alpha) and summary["chi2_dof"] <= chi2_dof_bar(n, dof, alpha)
+    if summary["max_abs"] > familywise_z_bar(n, dof, alpha):
+        return False
+    if "mv" in summary:                      # correlated observables: the per-temperature multivariate test
+        return hotelling_ok(summary["mv"], alpha)
+    return summary["chi2_dof"] <= chi2_dof_bar(n, dof, alpha)
 
 
 # ---------------------------------------------------------------------------

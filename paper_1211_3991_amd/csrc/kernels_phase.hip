@@ -118,8 +118,13 @@ __device__ __forceinline__ void update_unit(const DevBatch &b, const PhaseLanes 
                                             const int4 &ub, const UnitPtrs &p, const int *jj, const uint2 *vv)
 {
     const int R = pl.R, Lq = pl.Lq, S = pl.S, q = pl.q, i = p.i;
-    const int s = ub.x, k_ph = ub.y, bx = ub.z;
-    const int kmin = ub.w & 255, kmax = (ub.w >> 8) & 255;
+    // the unit is the workgroup's: its fields are uniform, and reading them
+    // through the scalar unit keeps the sample's descriptor, key schedule and
+    // loop bounds scalar (a divergent branch before this point can otherwise
+    // leave them in vector registers)
+    const int s = __builtin_amdgcn_readfirstlane(ub.x), k_ph = __builtin_amdgcn_readfirstlane(ub.y);
+    const int bx = __builtin_amdgcn_readfirstlane(ub.z), uw = __builtin_amdgcn_readfirstlane(ub.w);
+    const int kmin = uw & 255, kmax = (uw >> 8) & 255;
     const SampleDesc &d = b.desc[s];
     float beta[4];
     {
@@ -129,7 +134,7 @@ __device__ __forceinline__ void update_unit(const DevBatch &b, const PhaseLanes 
 #pragma unroll
         for (int r = 0; r < 4; ++r) beta[r] = (float)*reinterpret_cast<const double *>(bs + 8u * (uint32_t)ts[r]);
     }
-    const int c0 = ua.w - bx * S;                                 // first site of the colour class
+    const int c0 = __builtin_amdgcn_readfirstlane(ua.w) - bx * S; // first site of the colour class
     float hx[4] = {0.f, 0.f, 0.f, 0.f}, hy[4] = {0.f, 0.f, 0.f, 0.f};
     float lx[4] = {0.f, 0.f, 0.f, 0.f}, ly[4] = {0.f, 0.f, 0.f, 0.f};   // last sub-sweep: links to lower colours
     // a row's neighbours are sorted by colour-major index, so the links to

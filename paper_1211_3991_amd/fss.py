@@ -112,7 +112,7 @@ def app_c_fits(T, N, records, u_star, rho, T_ref):
 
 
 def kt_eta_run(sizes=(32, 64, 128, 256, 384), samples=32, T=(0.80, 1.00, 16), sweeps=1 << 14, meas_every=16,
-               seed_base=20_000, r_values=(1.0 / 16, -1.0 / 16, 0.0), log=None):
+               seed_base=20_000, r_values=(-1.0 / 16, 0.0, 1.0 / 16), log=None):
     """The square-lattice limit (rho -> infinity, z = 4: every link a nearest
     neighbour; rho = 60 gives exactly the square lattice) and the temperature
     where eta(T) = 1/4 (Sec. 4, square-lattice limit, Eq. chi_SR):

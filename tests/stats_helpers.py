@@ -9,11 +9,15 @@ Bars:
   the quantile a family of that size exceeds with probability 1e-3 under the
   null (Bonferroni, Student t with the errors' degrees of freedom), and
   chi^2/dof below the larger of 1.5 and its own 1e-3 quantile for that many
-  comparisons (assert_familywise; analysis.familywise_z_bar, chi2_dof_bar).
+  comparisons (assert_familywise; analysis.familywise_z_bar, chi2_dof_bar);
+* few comparisons of correlated observables (E, |m|^2, |m|^4, F of one
+  temperature move together): the family-wise bar on each z, and, per
+  temperature, Hotelling's test of the vector of differences, family-wise
+  over the temperatures (assert_pooled; analysis.hotelling).
 """
 import numpy as np
 
-from paper_1211_3991_amd.analysis import chi2_dof_bar, familywise_z_bar
+from paper_1211_3991_amd.analysis import chi2_dof_bar, familywise_z_bar, hotelling, hotelling_ok
 
 
 def batch_mean_err(x, n_batches=50):
@@ -81,3 +85,29 @@ def assert_familywise(z, what="", dof=np.inf, alpha=1e-3):
     print(msg, flush=True)
     assert np.max(np.abs(z)) <= bar, msg
     assert chi2 <= chi2_bar, msg
+
+
+def assert_pooled(a, b=None, what="", alpha=1e-3):
+    """a [n, n_T, p]: paired differences of n independent units; or a, b:
+    two independent sets of per-unit means.  Each (temperature, observable)
+    z below the family-wise bar, and Hotelling's per-temperature test."""
+    a = np.asarray(a, dtype=np.float64)
+    if b is None:
+        n, d = a.shape[0], a.mean(axis=0)
+        se = a.std(axis=0, ddof=1) / np.sqrt(n)
+    else:
+        b = np.asarray(b, dtype=np.float64)
+        n = min(a.shape[0], b.shape[0])
+        d = a.mean(axis=0) - b.mean(axis=0)
+        se = np.hypot(a.std(axis=0, ddof=1) / np.sqrt(a.shape[0]), b.std(axis=0, ddof=1) / np.sqrt(b.shape[0]))
+    z = d / se
+    assert np.all(np.isfinite(z)), f"{what}: undefined z"
+    bar = familywise_bar(z.size, n - 1, alpha)
+    mv = hotelling(a, b, alpha)
+    pv = np.round(mv["pval"], 5).tolist()
+    msg = (f"{what}: n={z.size} max|z|={np.max(np.abs(z)):.2f} (bar {bar:.2f}) beyond 3: {_outliers(z, 3.0)}; "
+           f"Hotelling per T: p={pv} (bar {alpha / mv['n_T']:.1e}), chi2/dof={mv['chi2_dof']:.3f} "
+           f"(bar {mv['chi2_dof_bar']:.2f})")
+    print(msg, flush=True)
+    assert np.max(np.abs(z)) <= bar, msg
+    assert hotelling_ok(mv, alpha), msg

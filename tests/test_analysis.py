@@ -161,11 +161,12 @@ def test_u4_slope_at():
 
 
 def test_eta_and_kt_temperature_from_exact_scaling():
-    """chi = L^(2 - eta(T)) (ln L)^(-1/8) c(T) with eta(T) = 1/4 + 1.5 (T - 0.894)
-    (the square-lattice form of Sec. 4, Eq. chi_SR): eta_of_T returns eta(T)
-    and t_eta the temperature where eta = 1/4, exactly; with per-sample noise
-    the jackknife error is finite and covers it.  A dropped log correction
-    (r = 0) moves the answer, so the correction is pinned too."""
+    """chi = L^(2 - eta(T)) (ln L)^(1/8) c(T) with eta(T) = 1/4 + 1.5 (T - 0.894)
+    (the square-lattice form of Sec. 4, Eq. chi_SR, with the KT exponent
+    r = -1/16): eta_of_T returns eta(T) and t_eta the temperature where
+    eta = 1/4, exactly; with per-sample noise the jackknife error is finite
+    and covers it.  A dropped log correction (r = 0) or the opposite sign
+    moves the answer, so the correction is pinned too."""
     T = np.linspace(0.80, 1.00, 11)
     L = [16, 32, 64, 128]
     eta = 0.25 + 1.5 * (T - 0.894)
@@ -173,7 +174,7 @@ def test_eta_and_kt_temperature_from_exact_scaling():
     def recs(G, rng=None):
         out = []
         for l in L:
-            m2 = l ** (-eta) * np.log(l) ** (-1.0 / 8) * (1.2 - 0.1 * T)
+            m2 = l ** (-eta) * np.log(l) ** (1.0 / 8) * (1.2 - 0.1 * T)
             out.append(_scaling_records(T, l * l, G, lambda t: np.zeros_like(t), lambda t, m2=m2: m2, rng))
             if rng is not None:
                 out[-1][:, :, :, 1] *= 1.0 + 0.002 * rng.normal(size=(1, G, 1))
@@ -183,8 +184,9 @@ def test_eta_and_kt_temperature_from_exact_scaling():
     assert np.allclose(analysis.eta_of_T(T, L, r, discard=0.0), eta, atol=1e-12)
     t, err = analysis.t_eta(T, L, r, discard=0.0)
     assert abs(t - 0.894) < 1e-12 and err < 1e-12
-    t0, _ = analysis.t_eta(T, L, r, r=0.0, discard=0.0)
-    assert abs(t0 - 0.894) > 0.005
+    for r_wrong in (0.0, 1.0 / 16):
+        t0, _ = analysis.t_eta(T, L, r, r=r_wrong, discard=0.0)
+        assert abs(t0 - 0.894) > 0.005
     t, err = analysis.t_eta(T, L, recs(24, np.random.default_rng(5)), discard=0.0)
     assert 0 < err < 0.01 and abs(t - 0.894) < 5 * err
 
@@ -264,6 +266,47 @@ def test_comparison_bars_are_calibrated():
     assert not analysis.comparison_ok(few, "many")
     assert analysis.comparison_ok(dict(few, n=2000, frac_gt=0.008, chi2_dof=1.1), "many")
     assert not analysis.comparison_ok(dict(few, n_undefined=1), "few", dof=15)
+
+
+def test_hotelling_reduces_to_t_test_and_is_calibrated():
+    """analysis.hotelling: with one observable its p-value is the two-sided
+    one-sample t-test's (paired) and Welch-free two-sample t with the
+    conservative nu (unpaired); under the null with strongly correlated
+    observables (|m|^2 and |m|^4 move together) its family-wise bar rejects
+    about alpha of the data sets, where a chi^2 of the marginal z would
+    reject many times more; a shift of Mahalanobis length 8 along one
+    temperature's observables is detected."""
+    from scipy import stats
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((40, 3, 1)) + 0.3
+    mv = analysis.hotelling(x)
+    for t in range(3):
+        assert np.isclose(mv["pval"][t], stats.ttest_1samp(x[:, t, 0], 0.0).pvalue, rtol=1e-9)
+    y = rng.standard_normal((40, 3, 1))
+    mv2 = analysis.hotelling(x, y)
+    for t in range(3):
+        tt = (x[:, t, 0].mean() - y[:, t, 0].mean()) / np.sqrt(x[:, t, 0].var(ddof=1) / 40 + y[:, t, 0].var(ddof=1) / 40)
+        assert np.isclose(mv2["T2"][t], tt * tt, rtol=1e-12)
+        assert np.isclose(mv2["pval"][t], 2 * stats.t.sf(abs(tt), 39), rtol=1e-9)
+    # correlated observables: E, m2, m4 with correlations -0.9, -0.9, 0.99
+    C = np.eye(5)
+    C[0, 1] = C[1, 0] = C[0, 2] = C[2, 0] = -0.9
+    C[1, 2] = C[2, 1] = 0.99
+    A = np.linalg.cholesky(C)
+    alpha, trials, G, n_T = 0.01, 2000, 64, 8
+    rej_mv = rej_chi = 0
+    for _ in range(trials):
+        d = rng.standard_normal((G, n_T, 5)) @ A.T
+        mv = analysis.hotelling(d, alpha=alpha)
+        rej_mv += not analysis.hotelling_ok(mv, alpha)
+        z = d.mean(0) / (d.std(0, ddof=1) / np.sqrt(G))
+        rej_chi += np.mean(z ** 2) > analysis.chi2_dof_bar(z.size, G - 1, alpha, floor=0.0)
+    assert rej_mv / trials < 2.5 * alpha, rej_mv / trials
+    assert rej_chi / trials > 3 * alpha, rej_chi / trials
+    d = rng.standard_normal((G, n_T, 5)) @ A.T
+    d[:, 3] += (8.0 / np.sqrt(G)) * A[:, 1]          # a correlated move of one temperature, Mahalanobis 8
+    mv = analysis.hotelling(d)
+    assert not analysis.hotelling_ok(mv) and int(np.argmin(mv["pval"])) == 3
 
 
 def _fss_records(T, L, nu_bar=2.0, tc=1.93, bn=0.125, dbn=0.1, G=8, n_rec=4, noise=0.0, seed=0):

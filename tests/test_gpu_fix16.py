@@ -21,7 +21,7 @@ from scipy import special
 
 import oracle
 import workloads
-from stats_helpers import assert_familywise, assert_r22, batch_means_err_axis0
+from stats_helpers import assert_familywise, assert_pooled, assert_r22, batch_means_err_axis0
 
 pytestmark = pytest.mark.gpu
 
@@ -200,7 +200,7 @@ def _oracle_l16_chains(n_chains=64):
 
     with ThreadPoolExecutor(max_workers=min(16, len(os.sched_getaffinity(0)))) as ex:
         means = np.array(list(ex.map(one, range(1, n_chains + 1))))
-    res = (means.mean(axis=0), means.std(axis=0, ddof=1) / np.sqrt(n_chains), n_chains)
+    res = (means.mean(axis=0), means.std(axis=0, ddof=1) / np.sqrt(n_chains), means)
     _ORACLE_L16["res"] = res
     return res
 
@@ -213,7 +213,7 @@ def test_l16_observables_match_oracle(trig, form, monkeypatch):
     form: E, |m|^2, |m|^4, F_x, F_y per chain (2560 comparisons) and pooled."""
     monkeypatch.setenv("XY_FIX16_TRIG", str(trig))
     _set_form(monkeypatch, form)
-    o_mean, o_err, n_or_chains = _oracle_l16_chains()
+    o_mean, o_err, o_chains = _oracle_l16_chains()
     wl = workloads.plain_fp64_l16()
     s = wl.samples[0]
     n_chains = 128
@@ -224,8 +224,7 @@ def test_l16_observables_match_oracle(trig, form, monkeypatch):
     grec = b.records().cpu().numpy()[:, :, :, :5]                  # [500, chains, T, 5]
     m, err = batch_means_err_axis0(grec, 50)                       # [chains, T, 5]
     assert_r22((m - o_mean) / np.sqrt(err ** 2 + o_err ** 2), f"trig{trig} {form} per chain")
-    pooled = (m.mean(axis=0) - o_mean) / np.sqrt(m.var(axis=0, ddof=1) / n_chains + o_err ** 2)
-    assert_familywise(pooled, f"trig{trig} {form} pooled", dof=n_or_chains - 1)
+    assert_pooled(m, o_chains, f"trig{trig} {form} pooled")
 
 
 def _pt_batch_vs_fp64(graphs, T, sweeps=3600, warm=400, meas=8):
@@ -243,7 +242,7 @@ def _pt_batch_vs_fp64(graphs, T, sweeps=3600, warm=400, meas=8):
         assert tries.sum() > 0 and acc.sum() > 0
     c = analysis.compare_chains(res["fix16"], res["fp64"], n_bins=30)
     assert_r22(c["z_per_sample"], "per (sample, T)")
-    assert_familywise(c["z_disorder"], "disorder-paired", dof=G - 1)
+    assert_pooled(c["mean_a"] - c["mean_b"], None, "disorder-paired")
 
 
 def test_pt_batch_matches_fp64_gpu():

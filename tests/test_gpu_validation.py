@@ -75,3 +75,26 @@ def test_free_boundary_rho_10_3_critical_temperature():
     tc, sigma = out["T_c"], out["T_c_error"]
     print(f"crossings {out['crossings']}; T_c = {tc:.4f} +- {sigma:.4f}; paper 1.53(2)", flush=True)
     assert abs(tc - 1.53) <= 3.0 * sigma + 0.02
+
+
+def test_square_lattice_kt_temperature_from_eta():
+    """The square-lattice limit (Sec. 4, the benchmark subsection; Table 2,
+    last column): rho = 60 with z = 4 gives exactly the square lattice, whose
+    KT point the paper locates where eta(T) = 1/4, eta(T) from
+    chi ~ L^(2 - eta) (ln L)^(-2r) (Eq. chi_SR) fitted over the sizes at every
+    temperature, and finds T_c = 0.894(5).  The log-correction exponent is
+    taken as r = -1/16, the value the KT renormalisation group gives in this
+    form (chi ~ L^(7/4) (ln L)^(1/8) at T_c); the paper prints its magnitude.
+    64 chains each of L = 32 ... 384 (the paper's largest size), 16
+    temperatures in [0.80, 1.00], 2^14 sweeps with PT.  The temperature must
+    agree with 0.894 within three jackknife errors plus 0.01 (the paper's
+    0.005 and as much again for the corrections beyond the logarithm at these
+    sizes).  The estimates without the log term and with the printed sign
+    are printed beside it."""
+    out = fss.kt_eta_run(sizes=(32, 64, 128, 256, 384), samples=64, T=(0.80, 1.00, 16), sweeps=1 << 14,
+                         meas_every=16, r_values=(-1.0 / 16, 0.0, 1.0 / 16), log=lambda m: print(m, flush=True))
+    for r, (t, e) in out["T_eta"].items():
+        print(f"r = {float(r):+.4f}: T(eta = 1/4) = {t} +- {e}", flush=True)
+    t, e = out["T_eta"][str(-1.0 / 16)]
+    assert t is not None
+    assert abs(t - 0.894) <= 3.0 * e + 0.01, (t, e)
