@@ -229,11 +229,31 @@ def write_traffic(wl, paths, argv, phase_streams):
            "write_kib_per_sweep": round(w_kib, 1), "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
            "bytes_per_sweep": int(bytes_sweep), "bytes_per_update": round(bytes_sweep / upd, 4),
            "updates_per_sweep": upd, "phase_streams": phase_streams, "command": f"python bench.py {argv}"}
-    if len(paths) > 4:
+    # further counter CSVs (SQ_*, TCC_*, TCP_*): every counter they hold,
+    # summed over a sweep's dispatches of the same kernels
+    cnt = {}
+    for path in paths[4:]:
+        rows = _pmc_rows(path)
+        for name in sorted({r["Counter_Name"] for r in rows}):
+            cnt[name] = per_sweep(rows, name)[1]
+    if cnt:
+        out["counters_per_sweep"] = {k: round(v, 1) for k, v in cnt.items()}
+    if "SQ_INSTS_VALU" in cnt:
         # VALU wave instructions of the same dispatches; x 64 lanes
-        _, valu, _ = per_sweep(_pmc_rows(paths[4]), "SQ_INSTS_VALU")
-        out["valu_lane_instr_per_sweep"] = int(valu * 64)
-        out["valu_lane_instr_per_update"] = round(valu * 64 / upd, 2)
+        out["valu_lane_instr_per_sweep"] = int(cnt["SQ_INSTS_VALU"] * 64)
+        out["valu_lane_instr_per_update"] = round(cnt["SQ_INSTS_VALU"] * 64 / upd, 2)
+    if "SQ_INSTS_VMEM_RD" in cnt:
+        out["vmem_rd_lane_instr_per_update"] = round(cnt["SQ_INSTS_VMEM_RD"] * 64 / upd, 2)
+    if "SQ_WAIT_INST_ANY" in cnt and cnt.get("SQ_WAVE_CYCLES"):
+        out["wave_cycles_waiting_frac"] = round(cnt["SQ_WAIT_INST_ANY"] / cnt["SQ_WAVE_CYCLES"], 4)
+    if cnt.get("TCC_HIT_sum", 0) + cnt.get("TCC_MISS_sum", 0) > 0:
+        out["l2_hit_rate"] = round(cnt["TCC_HIT_sum"] / (cnt["TCC_HIT_sum"] + cnt["TCC_MISS_sum"]), 4)
+    if "TCC_READ_SECTORS_sum" in cnt:
+        # 32-byte sectors read from the L2 by the kernels: the gathers' L2 traffic
+        out["l2_read_bytes_per_sweep"] = int(cnt["TCC_READ_SECTORS_sum"] * 32)
+        out["l2_read_bytes_per_update"] = round(cnt["TCC_READ_SECTORS_sum"] * 32 / upd, 3)
+    if cnt.get("TCC_EA0_RDREQ_sum"):
+        out["l2_miss_reads_to_dram_frac"] = round(cnt.get("TCC_EA0_RDREQ_DRAM_sum", 0.0) / cnt["TCC_EA0_RDREQ_sum"], 4)
     with open(traffic_file(wl.name), "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
@@ -346,13 +366,14 @@ def main():
                     help="stream groups of the phase-form samples (default: the autotuner's choice); with "
                          "--traffic-from, the count the counters were taken with")
     ap.add_argument("--traffic-from", nargs="+", metavar="CSV",
-                    help="no GPU work: FETCH_CSV WRITE_CSV CAL_FETCH_CSV CAL_WRITE_CSV [SQ_CSV]: turn rocprofv3 --pmc "
-                         "FETCH_SIZE / WRITE_SIZE counter CSVs of this workload and of --calibrate-copy 512 (and "
-                         "optionally one with SQ_INSTS_VALU) into profiles/traffic_<workload>.json")
+                    help="no GPU work: FETCH_CSV WRITE_CSV CAL_FETCH_CSV CAL_WRITE_CSV [COUNTER_CSV ...]: turn "
+                         "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter CSVs of this workload and of "
+                         "--calibrate-copy 512 (and optionally further counter CSVs: SQ_INSTS_VALU, SQ_WAIT_INST_ANY, "
+                         "TCC_HIT_sum, TCC_READ_SECTORS_sum, ...) into profiles/traffic_<workload>.json")
     args = ap.parse_args()
     if args.traffic_from:
-        if len(args.traffic_from) not in (4, 5):
-            ap.error("--traffic-from takes 4 or 5 CSV paths")
+        if len(args.traffic_from) < 4:
+            ap.error("--traffic-from takes at least 4 CSV paths")
         if not args.phase_streams:
             ap.error("--traffic-from needs --phase-streams: the group count the counters were taken with")
         write_traffic(workloads.ALL[args.workload](), args.traffic_from, " ".join(sys.argv[1:]), args.phase_streams)
@@ -437,6 +458,9 @@ def main():
             roofline["l2_read_gbs"] = round(tr["l2_read_bytes_per_sweep"] / (k_ms * 1e6), 1)
         if tr.get("l2_hit_rate") is not None:
             roofline["l2_hit_rate"] = tr["l2_hit_rate"]
+        for k in ("l2_read_bytes_per_update", "l2_miss_reads_to_dram_frac", "wave_cycles_waiting_frac"):
+            if tr.get(k) is not None:
+                roofline[k] = tr[k]
     # VALU issue, from the counted VALU instructions of the same launches
     # (same digest rule as the traffic)
     alu = None

@@ -246,19 +246,6 @@ xy_status xy_kernel_time(xy_batch *b, double *ms_total, int *n_timed);
 xy_status xy_batch_set_phase_streams(xy_batch *b, int n_streams, void *stream);
 xy_status xy_batch_phase_streams(const xy_batch *b, int *n_streams);
 
-/* Workgroups of each colour-phase launch of the phase form (fix16 batches;
- * used by the autotuner): 0 (the initial value; XY_PHASE_GRID overrides it
- * at xy_batch_init) gives one workgroup per work unit (a block of sites of
- * one sample's colour class); max_workgroups >= 8 caps a launch at that
- * many workgroups (rounded down to a multiple of 8), each then looping over
- * every gridDim-th unit with the next units' loads in flight while it
- * computes (App. B's colour phases are unchanged: every site of the class is
- * updated once, with the same random words, so the trajectory does not
- * depend on the choice).  Takes effect with the next sweep.  XY_EINVAL for
- * max_workgroups < 0. */
-xy_status xy_batch_set_phase_grid(xy_batch *b, int max_workgroups);
-xy_status xy_batch_phase_grid(const xy_batch *b, int *max_workgroups);
-
 /* Fixed-point sweep configuration (fix16 batches; used by the autotuner).
  *   trig        : (cos, sin) of a 16-bit angle, for every sample: 0 two-level
  *                 LDS table, 1 2048-entry LDS table with a small-angle

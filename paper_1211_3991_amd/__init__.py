@@ -161,16 +161,6 @@ class Batch:
         trajectory does not depend on it."""
         _lib.call("xy_batch_set_phase_streams", self._h, int(n), self._s())
 
-    def set_phase_grid(self, max_workgroups):
-        """Workgroups per colour-phase launch of the phase form (0: one per
-        work unit); the trajectory does not depend on it."""
-        _lib.call("xy_batch_set_phase_grid", self._h, int(max_workgroups))
-
-    def phase_grid(self):
-        n = ctypes.c_int()
-        _lib.call("xy_batch_phase_grid", self._h, ctypes.byref(n))
-        return n.value
-
     def phase_streams(self):
         n = ctypes.c_int()
         _lib.call("xy_batch_phase_streams", self._h, ctypes.byref(n))

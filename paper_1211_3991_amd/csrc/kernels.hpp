@@ -65,12 +65,13 @@ size_t fix16_lds_bytes(int n_pad, int trig, int mode);
 // samples listed in phase_samples; sites_per_block(R) sites per block.
 int fix16_phase_sites_per_block(int R);
 // units: the n_units work units (two int4 each, see k_fix16_phase) of this
-// colour; max_blocks: stride of the energy partials (the largest block count
-// of any colour); last: fuse the energy; grp: the control block b.ctl[grp]
-// whose sweep counter keys the random words; max_grid: 0 for a workgroup per
-// unit, else at most that many workgroups looping over the units.
+// colour, one workgroup each; max_blocks: stride of the energy partials (the
+// largest block count of any colour); last: fuse the energy; grp: the
+// control block b.ctl[grp] whose sweep counter keys the random words;
+// reverse: each XCD takes its run of units from the end (alternated between
+// consecutive colour phases).
 hipError_t launch_fix16_phase(const DevBatch &b, const int4 *units, int colour, int sub,
-                              int last, int n_units, int max_blocks, int grp, int max_grid, hipStream_t s);
+                              int last, int n_units, int max_blocks, int grp, int reverse, hipStream_t s);
 // phase samples [k_first, k_first + n_phase) of the list
 hipError_t launch_fix16_phase_energy(const DevBatch &b, const int32_t *phase_samples, int k_first, int n_phase,
                                      int max_blocks, hipStream_t s);

@@ -27,10 +27,14 @@ namespace {
 // (workgroup w to XCD w mod 8).  Work unit of workgroup `lin` out of `n`:
 // each XCD takes one contiguous run of units, so the neighbouring blocks of a
 // sample, whose gathers overlap, meet in the same L2.  A bijection on [0, n).
-__device__ __forceinline__ int xcd_contiguous(int lin, int n)
+// With `reverse`, each XCD takes its run from the end: consecutive colour
+// phases alternate the direction, so that an XCD starts a launch on the
+// samples it finished the previous one with, whose state is still in its L2.
+__device__ __forceinline__ int xcd_contiguous(int lin, int n, int reverse)
 {
     const int x = lin & 7, k = lin >> 3, per = n >> 3, rem = n & 7;
-    return x * per + min(x, rem) + k;
+    const int count = per + (x < rem ? 1 : 0);
+    return x * per + min(x, rem) + (reverse ? count - 1 - k : k);
 }
 
 // Lane layout of a workgroup: Lq = R/4 threads per site, S sites.
@@ -110,9 +114,8 @@ __device__ __forceinline__ void load_words(char *Ab, const PhaseLanes &pl, const
 // The update of one unit's sites by this thread, from its loaded rows jj and
 // neighbour words vv.  kLast: the last sub-sweep of the sweep, which also sums
 // the links to lower colours into the energy partials (uses esum and a
-// workgroup barrier, two when kReuse: esum is used again for another unit;
-// every thread of the workgroup calls it).
-template <typename Idx, bool kLast, int kTrig, bool kReuse>
+// workgroup barrier; every thread of the workgroup calls it).
+template <typename Idx, bool kLast, int kTrig>
 __device__ __forceinline__ void update_unit(const DevBatch &b, const PhaseLanes &pl, const float2 *tab, float *esum,
                                             int colour, int sub, int max_blocks, uint32_t sweep, const int4 &ua,
                                             const int4 &ub, const UnitPtrs &p, const int *jj, const uint2 *vv)
@@ -198,19 +201,18 @@ __device__ __forceinline__ void update_unit(const DevBatch &b, const PhaseLanes 
             for (int k = 0; k < S; ++k) acc += (double)esum[(k * Lq + qq) * 4 + r];
             b.epart[(((int64_t)k_ph * kMaxColours + colour) * max_blocks + bx) * R + t] = acc;
         }
-        if (kReuse) __syncthreads();                              // before esum is reused
     }
 }
 
 // One work unit per workgroup (gridDim.x == n_units).
 template <typename Idx, bool kLast, int kTrig>
 __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const int4 *units, int n_units, int colour,
-                                                            int sub, int max_blocks, int grp)
+                                                            int sub, int max_blocks, int grp, int reverse)
 {
     __shared__ float esum[kLast ? kPhaseBlock * 4 : 1];
     __shared__ float2 tab[Trig<kTrig>::kBytes ? Trig<kTrig>::kBytes / sizeof(float2) : 1];
     const PhaseLanes pl = phase_lanes(b);
-    const int u = xcd_contiguous(blockIdx.x, n_units);
+    const int u = xcd_contiguous(blockIdx.x, n_units, reverse);
     const int4 ua = units[2 * u], ub = units[2 * u + 1];
     const UnitPtrs p = unit_ptrs<Idx>(b, pl, ua, ub, colour);
     // rows and neighbour words in flight before the first use
@@ -223,76 +225,8 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
         Trig<kTrig>::load(tab, b, threadIdx.x, kPhaseBlock);
         __syncthreads();
     }
-    update_unit<Idx, kLast, kTrig, false>(b, pl, tab, esum, colour, sub, max_blocks, b.ctl[grp].sweep, ua, ub, p, jj,
+    update_unit<Idx, kLast, kTrig>(b, pl, tab, esum, colour, sub, max_blocks, b.ctl[grp].sweep, ua, ub, p, jj,
                                           vv);
-}
-
-// Fewer workgroups than units: workgroup w takes units w, w + gridDim.x, ...
-// through xcd_contiguous (gridDim.x a multiple of 8 keeps all of them in its
-// XCD's run of units), in a three-stage pipeline: while unit k is computed,
-// the neighbour words of unit k + 1 and the index rows of unit k + 2 are in
-// flight, and the descriptor of unit k + 3 is being read.  The loop count is
-// uniform over the workgroup (it depends on blockIdx.x only).
-template <typename Idx, bool kLast, int kTrig>
-__global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase_loop(DevBatch b, const int4 *units, int n_units,
-                                                                 int colour, int sub, int max_blocks, int grp)
-{
-    __shared__ float esum[kLast ? kPhaseBlock * 4 : 1];
-    __shared__ float2 tab[Trig<kTrig>::kBytes ? Trig<kTrig>::kBytes / sizeof(float2) : 1];
-    const PhaseLanes pl = phase_lanes(b);
-    const int stride = (int)gridDim.x;
-    const int lin0 = blockIdx.x;
-    auto unit_at = [&](int lin, int4 &ua, int4 &ub) {
-        const int u = xcd_contiguous(lin, n_units);
-        ua = units[2 * u];
-        ub = units[2 * u + 1];
-    };
-    // prologue: unit 0 with its words in flight, unit 1 with its rows in
-    // flight, the descriptor of unit 2
-    int4 ua0, ub0, ua1 = make_int4(0, 0, 0, 0), ub1 = ua1, ua2 = ua1, ub2 = ua1;
-    unit_at(lin0, ua0, ub0);
-    UnitPtrs p0 = unit_ptrs<Idx>(b, pl, ua0, ub0, colour), p1 = p0;
-    int jj0[8], jj1[8];
-    uint2 vv0[8];
-    load_rows<Idx>(p0.colb, jj0);
-    load_words(p0.Ab, pl, jj0, vv0);
-    bool has1 = lin0 + stride < n_units, has2 = lin0 + 2 * stride < n_units;
-    if (has1) {
-        unit_at(lin0 + stride, ua1, ub1);
-        p1 = unit_ptrs<Idx>(b, pl, ua1, ub1, colour);
-        load_rows<Idx>(p1.colb, jj1);
-    }
-    if (has2) unit_at(lin0 + 2 * stride, ua2, ub2);
-    if constexpr (Trig<kTrig>::kBytes > 0) {
-        Trig<kTrig>::load(tab, b, threadIdx.x, kPhaseBlock);
-        __syncthreads();
-    }
-    const uint32_t sweep = b.ctl[grp].sweep;
-    for (int lin = lin0;; lin += stride) {
-        // stage the next units: words of unit 1, rows of unit 2, descriptor of unit 3
-        uint2 vv1[8];
-        int jj2[8];
-        UnitPtrs p2 = p1;
-        int4 ua3 = ua2, ub3 = ub2;
-        const bool has3 = lin + 3 * stride < n_units;
-        if (has1) load_words(p1.Ab, pl, jj1, vv1);
-        if (has2) {
-            p2 = unit_ptrs<Idx>(b, pl, ua2, ub2, colour);
-            load_rows<Idx>(p2.colb, jj2);
-        }
-        if (has3) unit_at(lin + 3 * stride, ua3, ub3);
-
-        update_unit<Idx, kLast, kTrig, true>(b, pl, tab, esum, colour, sub, max_blocks, sweep, ua0, ub0, p0, jj0, vv0);
-
-        if (!has1) break;
-        ua0 = ua1; ub0 = ub1; p0 = p1;
-        ua1 = ua2; ub1 = ub2; p1 = p2;
-        ua2 = ua3; ub2 = ub3;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) { jj0[k] = jj1[k]; vv0[k] = vv1[k]; jj1[k] = jj2[k]; }
-        has1 = has2;
-        has2 = has3;
-    }
 }
 
 }  // namespace
@@ -300,30 +234,20 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase_loop(DevBatch b, co
 int fix16_phase_sites_per_block(int R) { return kPhaseBlock / (R / 4); }
 
 template <int kTrig>
-void (*phase_kernel(int idx16, int last, bool loop))(DevBatch, const int4 *, int, int, int, int, int)
+void (*phase_kernel(int idx16, int last))(DevBatch, const int4 *, int, int, int, int, int, int)
 {
-    if (loop)
-        return idx16 ? (last ? k_fix16_phase_loop<uint16_t, true, kTrig> : k_fix16_phase_loop<uint16_t, false, kTrig>)
-                     : (last ? k_fix16_phase_loop<int32_t, true, kTrig> : k_fix16_phase_loop<int32_t, false, kTrig>);
     return idx16 ? (last ? k_fix16_phase<uint16_t, true, kTrig> : k_fix16_phase<uint16_t, false, kTrig>)
                  : (last ? k_fix16_phase<int32_t, true, kTrig> : k_fix16_phase<int32_t, false, kTrig>);
 }
 
 hipError_t launch_fix16_phase(const DevBatch &b, const int4 *units, int colour, int sub,
-                              int last, int n_units, int max_blocks, int grp, int max_grid, hipStream_t s)
+                              int last, int n_units, int max_blocks, int grp, int reverse, hipStream_t s)
 {
     if (n_units == 0) return hipSuccess;
-    // max_grid >= 8: at most that many workgroups (rounded down to a multiple
-    // of 8, so that a workgroup's units stay on its XCD), each taking every
-    // gridDim.x-th unit, when that is fewer than the units; else one
-    // workgroup per unit.  Every workgroup has at least one unit.
-    const int g8 = max_grid & ~7;
-    const bool loop = g8 >= 8 && g8 < n_units;
-    const int grid = loop ? g8 : n_units;
-    auto k = b.trig == 0 ? phase_kernel<0>(b.idx16, last, loop)
-                         : b.trig == 1 ? phase_kernel<1>(b.idx16, last, loop) : phase_kernel<2>(b.idx16, last, loop);
-    hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kPhaseBlock), 0, s, b, units, n_units, colour, sub, max_blocks,
-                       grp);
+    auto k = b.trig == 0 ? phase_kernel<0>(b.idx16, last)
+                         : b.trig == 1 ? phase_kernel<1>(b.idx16, last) : phase_kernel<2>(b.idx16, last);
+    hipLaunchKernelGGL(k, dim3((unsigned)n_units), dim3(kPhaseBlock), 0, s, b, units, n_units, colour, sub, max_blocks,
+                       grp, reverse);
     return hipGetLastError();
 }
 

@@ -36,7 +36,7 @@ struct xy_batch {
     std::vector<size_t> phase_unit_off;       // per colour: first int4 of its units in d_units
     int4 *d_units = nullptr;                  // two int4 per unit (see k_fix16_phase)
     int phase_stride = 0;                     // largest block count (energy partial stride)
-    int phase_grid = 0;                       // workgroups per colour-phase launch (0: one per work unit)
+    bool serpentine = true;                   // alternate the unit order of consecutive colour phases
     // the phase launches of a sweep split by sample over the caller's stream
     // and `aux`, so that the ramp and tail of one launch overlap the other
     // stream's work; fork and join through events on the caller's stream
@@ -532,7 +532,7 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
             b->unit_k.resize(units.size() / 2);
             for (size_t a = 0; a < b->unit_k.size(); ++a) b->unit_k[a] = units[2 * a + 1].y;
             b->n_phase = (int)phase.size();
-            if (const char *env = std::getenv("XY_PHASE_GRID")) b->phase_grid = std::max(0, std::atoi(env));
+            if (const char *env = std::getenv("XY_PHASE_SERPENTINE")) b->serpentine = std::atoi(env) != 0;
             int n_streams = 2;   // XY_PHASE_STREAMS=1..4 overrides
             if (const char *env = std::getenv("XY_PHASE_STREAMS")) n_streams = std::atoi(env);
             const hipError_t e = setup_phase_groups(b, n_streams);
@@ -687,9 +687,10 @@ hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream
             for (int c = 0; c < (int)b->phase_units.size() && e == hipSuccess; ++c) {
                 const int *bd = b->phase_bounds.data() + (size_t)c * (n_st + 1);
                 const int4 *u = b->d_units + b->phase_unit_off[c];
+                const int rev = b->serpentine ? (sub * (int)b->phase_units.size() + c) & 1 : 0;
                 for (int g = 0; g < n_st && e == hipSuccess; ++g)
                     e = launch_fix16_phase(b->dev, u + 2 * (size_t)bd[g], c, sub, sub == n_or, bd[g + 1] - bd[g],
-                                           b->phase_stride, g, b->phase_grid, g == 0 ? s : b->aux[g - 1]);
+                                           b->phase_stride, g, rev, g == 0 ? s : b->aux[g - 1]);
             }
         for (int g = 0; g < n_st && e == hipSuccess; ++g) {
             hipStream_t st = g == 0 ? s : b->aux[g - 1];
@@ -712,9 +713,10 @@ hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream
             for (int c = 0; c < (int)b->phase_units.size() && e == hipSuccess; ++c) {
                 const int *bd = b->phase_bounds.data() + (size_t)c * (n_st + 1);
                 const int4 *u = b->d_units + b->phase_unit_off[c];
+                const int rev = b->serpentine ? (sub * (int)b->phase_units.size() + c) & 1 : 0;
                 for (int g = 0; g < n_st && e == hipSuccess; ++g)
                     e = launch_fix16_phase(b->dev, u + 2 * (size_t)bd[g], c, sub, sub == n_or, bd[g + 1] - bd[g],
-                                           b->phase_stride, 0, b->phase_grid, g == 0 ? s : b->aux[g - 1]);
+                                           b->phase_stride, 0, rev, g == 0 ? s : b->aux[g - 1]);
             }
         if (e == hipSuccess && fork) e = join_groups(b, s);
         // the timed part: the sweep kernels (with their fused energies) and the
@@ -1111,21 +1113,6 @@ extern "C" xy_status xy_batch_set_phase_streams(xy_batch *b, int n_streams, void
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
     return e == hipSuccess ? XY_OK : hip_err(e, "xy_batch_set_phase_streams");
-}
-
-extern "C" xy_status xy_batch_set_phase_grid(xy_batch *b, int max_workgroups)
-{
-    if (!b || max_workgroups < 0) return set_error(XY_EINVAL, "xy_batch_set_phase_grid: bad arguments");
-    b->phase_grid = max_workgroups;
-    if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
-    return XY_OK;
-}
-
-extern "C" xy_status xy_batch_phase_grid(const xy_batch *b, int *max_workgroups)
-{
-    if (!b || !max_workgroups) return set_error(XY_EINVAL, "xy_batch_phase_grid: NULL argument");
-    *max_workgroups = b->phase_grid;
-    return XY_OK;
 }
 
 extern "C" xy_status xy_batch_phase_streams(const xy_batch *b, int *n_streams)
