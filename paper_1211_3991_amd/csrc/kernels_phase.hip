@@ -156,17 +156,29 @@ __device__ __forceinline__ void update_unit(const DevBatch &b, const PhaseLanes 
             for (int r = 0; r < 4; ++r) { lx[r] = hx[r]; ly[r] = hy[r]; }
         }
     };
+    // the site's degree, in flight while the first eight rows are added
+    // (needed only for blocks with rows past the eighth; uniform branch)
+    const int dg = kmax > 8 ? (int)b.u8[d.deg + i] : 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         if (k < kmin) add(vv[k], jj[k], k == 0);                 // uniform, unmasked
         else if (k < kmax && jj[k] != i) add(vv[k], jj[k], false);
     }
-    if (kmax > 8) {                                               // uniform: rows past the eighth
-        const int dg = b.u8[d.deg + i];
-        for (int k = 8; k < dg; ++k) {
-            const int j = (int)*reinterpret_cast<const Idx *>(p.colb + k * 64 * (int)sizeof(Idx));
-            add(angle_word(p.Ab, pl, j), j, false);
-        }
+    // rows past the eighth, eight at a time: the indices of a batch, then its
+    // neighbour words, all in flight before the first use (a lane reads only
+    // the rows below its own degree, which its chunk holds; the batch count
+    // kmax is uniform)
+    for (int k0 = 8; k0 < kmax; k0 += 8) {
+        int j2[8];
+        uint2 v2[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            j2[k] = k0 + k < dg ? (int)*reinterpret_cast<const Idx *>(p.colb + (k0 + k) * 64 * (int)sizeof(Idx)) : i;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v2[k] = k0 + k < dg ? angle_word(p.Ab, pl, j2[k]) : make_uint2(0u, 0u);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (k0 + k < dg) add(v2[k], j2[k], false);
     }
     const U4 w = philox4x32_10({(uint32_t)i, sweep, (uint32_t)(4 * q), tag(sub == 0 ? kMet : kOR, (uint32_t)sub)},
                                d.seed_lo, d.seed_hi);

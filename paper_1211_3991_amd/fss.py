@@ -18,16 +18,34 @@ import numpy as np
 from . import analysis
 
 
+def _sweep_records(graphs, ladder, seeds, sweeps, meas_every, chunk):
+    """Records of `sweeps` sweeps (1 Metropolis + 5 OR, PT every sweep) of the
+    fixed-point path, the sweeps replayed from a HIP graph of `chunk` sweeps
+    (a multiple of meas_every; 0: direct launches)."""
+    import torch
+
+    import paper_1211_3991_amd as xy
+    stream = torch.cuda.Stream()
+    b = xy.Batch(graphs, ladder, precision="fix16", seeds=seeds, max_records=sweeps // meas_every, stream=stream)
+    try:
+        if chunk:
+            b.use_graph(chunk)
+        b.sweep(sweeps, n_or=5, pt_every=1, meas_every=meas_every)
+        b.synchronize()
+        return b.records().cpu().numpy()
+    finally:
+        b.close()
+
+
 def run(rho, z=4, sizes=(16, 32, 64, 128), samples=64, T=(1.7, 2.2, 16), sweeps=1 << 14, meas_every=16,
-        seed_base=10_000, nu_bar=2.0, T_ref=None, boundary="periodic", log=None):
+        seed_base=10_000, nu_bar=2.0, T_ref=None, boundary="periodic", log=None, chunk=256):
     """Runs the sweeps and returns the FSS estimates as a dict.
 
     T: (first, last, count) of a linear temperature ladder.  Graph and dynamics
     seeds of sample s at size L are seed_base * L + s.  nu_bar is the exponent
     assumed in the T_c extrapolation; T_ref (default: the extrapolated T_c) is
-    where gamma/nu_bar is taken."""
-    import torch
-
+    where gamma/nu_bar is taken.  chunk: sweeps per HIP-graph replay (a
+    multiple of meas_every; 0 for direct launches)."""
     import paper_1211_3991_amd as xy
     ladder = np.linspace(T[0], T[1], int(T[2]))
     rec = {}
@@ -36,11 +54,7 @@ def run(rho, z=4, sizes=(16, 32, 64, 128), samples=64, T=(1.7, 2.2, 16), sweeps=
             log(f"rho={rho} z={z} L={L}: {samples} samples, {sweeps} sweeps")
         seeds = [seed_base * L + s for s in range(samples)]
         graphs = [xy.Graph.levy(L, z, rho, sd, boundary=boundary) for sd in seeds]
-        b = xy.Batch(graphs, ladder, precision="fix16", seeds=seeds, max_records=sweeps // meas_every)
-        b.sweep(sweeps, n_or=5, pt_every=1, meas_every=meas_every)
-        torch.cuda.synchronize()
-        rec[L] = b.records().cpu().numpy()
-        b.close()
+        rec[L] = _sweep_records(graphs, ladder, seeds, sweeps, meas_every, chunk)
     N, Tx, err = [], [], []
     for a, b_ in zip(sizes[:-1], sizes[1:]):
         t, e = analysis.u4_crossing(ladder, rec[a], rec[b_])
@@ -112,15 +126,13 @@ def app_c_fits(T, N, records, u_star, rho, T_ref):
 
 
 def kt_eta_run(sizes=(32, 64, 128, 256, 384), samples=32, T=(0.80, 1.00, 16), sweeps=1 << 14, meas_every=16,
-               seed_base=20_000, r_values=(-1.0 / 16, 0.0, 1.0 / 16), log=None):
+               seed_base=20_000, r_values=(-1.0 / 16, 0.0, 1.0 / 16), log=None, chunk=256):
     """The square-lattice limit (rho -> infinity, z = 4: every link a nearest
     neighbour; rho = 60 gives exactly the square lattice) and the temperature
     where eta(T) = 1/4 (Sec. 4, square-lattice limit, Eq. chi_SR):
     chi = N <|m|^2> ~ L^(2 - eta) (ln L)^(-2r) fitted over the sizes at every
     ladder temperature, for each log-correction exponent r in r_values.
     Returns dict(T_eta={r: (T, error)}, eta={r: eta(T) per ladder T}, ...)."""
-    import torch
-
     import paper_1211_3991_amd as xy
     ladder = np.linspace(T[0], T[1], int(T[2]))
     recs = []
@@ -129,11 +141,7 @@ def kt_eta_run(sizes=(32, 64, 128, 256, 384), samples=32, T=(0.80, 1.00, 16), sw
             log(f"square lattice L={L}: {samples} chains, {sweeps} sweeps")
         seeds = [seed_base * L + s for s in range(samples)]
         g = xy.Graph.levy(L, 4, 60.0, seeds[0])
-        b = xy.Batch([g] * samples, ladder, precision="fix16", seeds=seeds, max_records=sweeps // meas_every)
-        b.sweep(sweeps, n_or=5, pt_every=1, meas_every=meas_every)
-        torch.cuda.synchronize()
-        recs.append(b.records().cpu().numpy())
-        b.close()
+        recs.append(_sweep_records([g] * samples, ladder, seeds, sweeps, meas_every, chunk))
     out = {"sizes": list(sizes), "samples": samples, "sweeps": sweeps, "T": ladder.tolist(), "T_eta": {}, "eta": {}}
     for r in r_values:
         t, e = analysis.t_eta(ladder, list(sizes), recs, 0.25, r)
