@@ -87,12 +87,13 @@ def time_gpu(wl, precision, steps, warmup, graphs, torch, xy, n_or=None, form=No
     tune = None
     if precision == "fix16":
         if form is None:
-            tune = b.autotune(n_or=n_or, use_cache=False)
+            tune = b.autotune(n_or=n_or, use_cache=False, pt_every=wl.pt_every)
         else:
             b.set_fix16_form(trig=form[0], allow_unit=form[1])
         if phase_streams:
             b.set_phase_streams(phase_streams)
     kw = dict(n_or=n_or, pt_every=wl.pt_every, meas_every=wl.meas_every)
+    _, acc0, tries0 = b.counters()                             # the tuner's trial swaps, left out of the rate
     b.sweep(w0, **kw)                                          # direct warm-up, ends at the window's phase
 
     def timed():
@@ -125,6 +126,7 @@ def time_gpu(wl, precision, steps, warmup, graphs, torch, xy, n_or=None, form=No
         out["direct_ms"] = ms_d
         out["direct_kernel_ms"] = k_ms_d
     nrec, acc, tries = b.counters()
+    acc, tries = acc - acc0, tries - tries0
     n_groups = b.phase_streams() if precision == "fix16" else 1
     b.close()
     out.update(window=[w0 + (steps + phase if replay else 0), steps], records=nrec, phase_streams=n_groups,

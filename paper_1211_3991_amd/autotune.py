@@ -40,19 +40,21 @@ def _load(path):
         return {}
 
 
-def _time(batch, sweeps, n_or, saved):
-    batch.sweep(1, n_or=n_or, pt_every=0, meas_every=0)           # first launch of a kernel variant
+def _time(batch, sweeps, n_or, saved, pt_every=0):
+    batch.sweep(1, n_or=n_or, pt_every=pt_every, meas_every=0)    # first launch of a kernel variant
     batch.kernel_timing(True)
-    batch.sweep(sweeps, n_or=n_or, pt_every=0, meas_every=0)
+    batch.sweep(sweeps, n_or=n_or, pt_every=pt_every, meas_every=0)
     ms, n = batch.kernel_time()
     batch.kernel_timing(False)
     batch.set_state(*saved)
     return ms / max(n, 1)
 
 
-def autotune(batch, sweeps=3, n_or=5, use_cache=True):
+def autotune(batch, sweeps=3, n_or=5, use_cache=True, pt_every=1):
     """Picks and applies the fastest (trig, allow_unit) and stream-group count;
-    returns a report dict."""
+    returns a report dict.  The stream-group trials temper every pt_every
+    sweeps, as the run will (their swaps add to the batch's PT counters; the
+    state, labels and sweep counter are restored)."""
     if batch.precision != "fix16":
         return {"tuned": False, "reason": "fp64 batch"}
     forms = batch.forms()
@@ -98,16 +100,17 @@ def autotune(batch, sweeps=3, n_or=5, use_cache=True):
         entry.update(trig=trig, allow_unit=1, trig_ms_per_sweep=rep["trig_ms_per_sweep"])
     n_best = batch.phase_streams()
     if n_phase >= 2:
-        # (trials run without tempering, whose per-group tails favour fewer
-        # groups, and the caller's stream plus three others fill the four
-        # hardware queues a process gets by default: one to three groups, and
-        # the fewest within 2% of the fastest)
+        # (trials temper as the run does: each group runs its own energies and
+        # tempering after its colour phases, and those tails overlap the other
+        # groups' phases; the caller's stream plus three others fill the four
+        # hardware queues a process gets by default: one to three groups, the
+        # fastest, and the fewer groups on a tie within 0.5%)
         st = {}
         for n in range(1, min(3, n_phase) + 1):
             batch.set_phase_streams(n)
-            st[n] = min(_time(batch, n_sw, n_or, saved) for _ in range(2))
+            st[n] = min(_time(batch, n_sw, n_or, saved, pt_every) for _ in range(2))
         fastest = min(st.values())
-        n_best = min(n for n, v in st.items() if v <= 1.02 * fastest)
+        n_best = min(n for n, v in st.items() if v <= 1.005 * fastest)
         rep["phase_streams_ms_per_sweep"] = {str(n): round(v, 4) for n, v in st.items()}
         entry["phase_streams_ms_per_sweep"] = rep["phase_streams_ms_per_sweep"]
     batch.set_phase_streams(n_best)

@@ -94,20 +94,55 @@ __device__ __forceinline__ double2 unit64(uint32_t th, const double2 *t64)
     return make_double2(a.x * c.x - a.y * c.y, a.y * c.x + a.x * c.y);
 }
 
+// -beta log2(e): the factor of dE in the exponent of the acceptance
+// probability 2^(dE * (-beta log2 e)) = exp(-beta dE), one per slot.
+__device__ __forceinline__ float accept_factor(float beta) { return -beta * 1.4426950408889634f; }
+
 // Metropolis acceptance with probability min(1, exp(-beta dE)) for the FP32
-// exp.  The uniform is the top 16 bits of `word`; on a tie with the 16-bit
-// threshold (probability 2^-16) 32 more bits are drawn from the counter
-// (site, sweep, slot, purpose 4 | sub), so the test is exact: U < p.
-__device__ __forceinline__ bool accept_move(float dE, float beta, uint32_t word, uint32_t site, uint32_t sweep,
+// exp (the hardware 2^x of dE * accept_factor(beta)).  The uniform is the
+// top 16 bits of `word`; on a tie with the 16-bit threshold (probability
+// 2^-16) 32 more bits are drawn from the counter (site, sweep, slot,
+// purpose 4 | sub), so the test is exact: U < p.
+__device__ __forceinline__ bool accept_move(float dE, float factor, uint32_t word, uint32_t site, uint32_t sweep,
                                             uint32_t slot, uint32_t sub, const SampleDesc &d)
 {
     if (dE <= 0.f) return true;
-    const float p = __expf(-beta * dE);
+    const float p = __builtin_amdgcn_exp2f(dE * factor);
     const float p16 = p * 65536.0f;
     const uint32_t u16 = word >> 16, f = (uint32_t)p16;
     if (u16 != f) return u16 < f;
     const U4 x = philox4x32_10({site, sweep, slot, tag(kMetAcc, sub)}, d.seed_lo, d.seed_hi);
     return (double)x.x < (double)(p16 - (float)f) * 4294967296.0;
+}
+
+// Philox4x32-10 as philox4x32_10, for keys that are the same in every lane
+// of the wave (scalar registers): each round's two three-input XORs are one
+// v_bitop3_b32 each (truth table 0x96, a ^ b ^ c) instead of two v_xor_b32.
+__device__ __forceinline__ uint32_t xor3_sk(uint32_t a, uint32_t b, uint32_t k)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
+__device__ __forceinline__ U4 philox4x32_10_uniform_key(U4 c, uint32_t k0, uint32_t k1)
+{
+    const uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+    const uint32_t kBumpA = 0x9E3779B9u, kBumpB = 0xBB67AE85u;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t pa = (uint64_t)kMulA * c.x;
+        const uint64_t pb = (uint64_t)kMulB * c.z;
+        U4 n;
+        n.x = xor3_sk((uint32_t)(pb >> 32), c.y, k0);
+        n.y = (uint32_t)pb;
+        n.z = xor3_sk((uint32_t)(pa >> 32), c.w, k1);
+        n.w = (uint32_t)pa;
+        c = n;
+        k0 += kBumpA;
+        k1 += kBumpB;
+    }
+    return c;
 }
 
 // Phase form: threads per workgroup of the colour-phase kernel

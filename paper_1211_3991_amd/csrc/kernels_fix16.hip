@@ -139,7 +139,7 @@ template <bool kLast, int kWaves, int kGroup, typename Idx, typename Sp>
 __device__ __forceinline__ double colour_phase(const SampleDesc &d, const Sp &sp,
                                                const int32_t *cptr, const int32_t *cw, const Idx *col,
                                                const uint8_t *deg, int c0, int c1, int ch0, int nch, int wave,
-                                               int lane, uint32_t sweep, int slot, int sub, float beta)
+                                               int lane, uint32_t sweep, int slot, int sub, float factor)
 {
     static_assert(kGroup == 1 || kGroup == 2 || kGroup == 4, "groups must tile the 4-chunk key groups");
     double e_acc = 0.0;
@@ -219,7 +219,7 @@ __device__ __forceinline__ double colour_phase(const SampleDesc &d, const Sp &sp
             }
             const float2 nu = sp.unit(th_new);
             const float dE = hx[r] * (cur.x - nu.x) + hy[r] * (cur.y - nu.y);
-            const bool accept = accept_move(dE, beta, words[r], (uint32_t)site[r], sweep, (uint32_t)slot,
+            const bool accept = accept_move(dE, factor, words[r], (uint32_t)site[r], sweep, (uint32_t)slot,
                                             (uint32_t)sub, d);
             if (accept) sp.set(site[r], th_new, nu);
             if (kLast) {
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_fix16_sweep(DevBatch b, const Item *
     }
     __syncthreads();
 
-    const float beta = (float)b.beta[s * R + b.T_of_slot[s * R + slot]];
+    const float factor = accept_factor((float)b.beta[s * R + b.T_of_slot[s * R + slot]]);
     const uint32_t sweep = b.ctl->sweep;
     const int32_t *cptr = b.i32 + d.sell_ptr;
     const int32_t *cw = b.i32 + d.sell_w;
@@ -287,10 +287,10 @@ __global__ __launch_bounds__(kBlock) void k_fix16_sweep(DevBatch b, const Item *
             const int ch0 = d.chunk_off[c], nch = d.chunk_off[c + 1] - ch0;
             if (last)
                 e_acc += colour_phase<true, kW, kG, Idx>(d, sp, cptr, cw, col, deg, c0, c1, ch0, nch, wave, lane, sweep,
-                                                     slot, sub, beta);
+                                                     slot, sub, factor);
             else
                 colour_phase<false, kW, kG, Idx>(d, sp, cptr, cw, col, deg, c0, c1, ch0, nch, wave, lane, sweep, slot,
-                                             sub, beta);
+                                             sub, factor);
             __syncthreads();
         }
     }

@@ -129,13 +129,14 @@ __device__ __forceinline__ void update_unit(const DevBatch &b, const PhaseLanes 
     const int bx = __builtin_amdgcn_readfirstlane(ub.z), uw = __builtin_amdgcn_readfirstlane(ub.w);
     const int kmin = uw & 255, kmax = (uw >> 8) & 255;
     const SampleDesc &d = b.desc[s];
-    float beta[4];
+    float factor[4];   // accept_factor of each slot's inverse temperature
     {
         const int4 tq = *reinterpret_cast<const int4 *>(b.T_of_slot + s * R + 4 * q);
         const int ts[4] = {tq.x, tq.y, tq.z, tq.w};
         const char *bs = reinterpret_cast<const char *>(b.beta + s * R);   // this sample's ladder
 #pragma unroll
-        for (int r = 0; r < 4; ++r) beta[r] = (float)*reinterpret_cast<const double *>(bs + 8u * (uint32_t)ts[r]);
+        for (int r = 0; r < 4; ++r)
+            factor[r] = accept_factor((float)*reinterpret_cast<const double *>(bs + 8u * (uint32_t)ts[r]));
     }
     const int c0 = __builtin_amdgcn_readfirstlane(ua.w) - bx * S; // first site of the colour class
     float hx[4] = {0.f, 0.f, 0.f, 0.f}, hy[4] = {0.f, 0.f, 0.f, 0.f};
@@ -180,8 +181,9 @@ __device__ __forceinline__ void update_unit(const DevBatch &b, const PhaseLanes 
         for (int k = 0; k < 8; ++k)
             if (k0 + k < dg) add(v2[k], j2[k], false);
     }
-    const U4 w = philox4x32_10({(uint32_t)i, sweep, (uint32_t)(4 * q), tag(sub == 0 ? kMet : kOR, (uint32_t)sub)},
-                               d.seed_lo, d.seed_hi);
+    // the key is the sample's seed, the same in every lane (s is uniform)
+    const U4 w = philox4x32_10_uniform_key(
+        {(uint32_t)i, sweep, (uint32_t)(4 * q), tag(sub == 0 ? kMet : kOR, (uint32_t)sub)}, d.seed_lo, d.seed_hi);
     const uint32_t words[4] = {w.x, w.y, w.z, w.w};
     const uint2 me = angle_word(p.Ab, pl, i);
     const uint32_t cur_th[4] = {me.x & 0xFFFFu, me.x >> 16, me.y & 0xFFFFu, me.y >> 16};
@@ -194,7 +196,7 @@ __device__ __forceinline__ void update_unit(const DevBatch &b, const PhaseLanes 
         const uint32_t th_new = sub == 0 ? (words[r] & 0xFFFFu) : ((field_axis2(hx[r], hy[r]) - th) & 0xFFFFu);
         const float2 cur = Trig<kTrig>::unit(th, tab), nu = Trig<kTrig>::unit(th_new, tab);
         const float dE = hx[r] * (cur.x - nu.x) + hy[r] * (cur.y - nu.y);
-        const bool acc = accept_move(dE, beta[r], words[r], (uint32_t)i, sweep, (uint32_t)slot, (uint32_t)sub, d);
+        const bool acc = accept_move(dE, factor[r], words[r], (uint32_t)i, sweep, (uint32_t)slot, (uint32_t)sub, d);
         out[r] = acc ? th_new : th;
         const float2 f = acc ? nu : cur;
         e_q[r] = p.active ? -(f.x * lx[r] + f.y * ly[r]) : 0.f;

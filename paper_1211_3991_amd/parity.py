@@ -61,7 +61,7 @@ def run_records(graphs, T, precision, seeds, n_sweeps, meas_every, n_or=5, pt_ev
         if start == "cold":
             b.set_state(cold_state(graphs, np.shape(T)[-1], precision), sweep=0)
         if tune and precision == "fix16":
-            b.autotune(sweeps=1, n_or=n_or, use_cache=False)
+            b.autotune(sweeps=1, n_or=n_or, use_cache=False, pt_every=pt_every)
         if chunk:
             b.use_graph(chunk)
         b.sweep(n_sweeps, n_or=n_or, pt_every=pt_every, meas_every=meas_every)
