@@ -29,7 +29,16 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, published
-VALU_PEAK_TLANE = 78.64    # 256 CUs x 4 SIMDs x 64 lanes x 2.4 GHz / 2 cycles per wave instruction, in 1e12/s
+VALU_PEAK_TLANE = 78.64    # published FP32 vector 157.3 TFLOP/s / 2 flops per FMA: FMA lane-instructions, 1e12/s
+# Measured on MI355X with a standalone probe (independent chains, 8 waves per
+# SIMD): v_fma_f32 issues at 51.7e12 lane-instructions/s (3.04 cycles per
+# wave instruction per SIMD at 2.4 GHz), v_sin_f32 at 15.5e12 (10.2 cycles).
+VALU_FMA_ISSUE_TLANE = 51.7
+TRANS_COST = 10.17 / 3.04  # one transcendental in FMA issue slots
+# transcendentals per update of the phase kernel, from its code path at the
+# mean degree 6: (cos, sin) of 6 neighbours, of the own and the proposed angle,
+# one 2^x; the over-relaxation axis adds one reciprocal (5 of the 6 sub-sweeps)
+TRANS_PER_UPDATE = 12 + 4 + 1 + 5.0 / 6.0
 
 
 def traffic_file(workload):
@@ -125,6 +134,12 @@ def time_gpu(wl, precision, steps, warmup, graphs, torch, xy, n_or=None, form=No
             out.update(ms=ms_d, kernel_ms=k_ms_d, kernel_n=k_n_d, launch="direct")
         out["direct_ms"] = ms_d
         out["direct_kernel_ms"] = k_ms_d
+        if replay and ms_d < out["ms"]:
+            # the faster launch mode of the same window is the run's: a replay
+            # only saves host launch cost, and with many short launches on
+            # several streams (small graphs) it is the slower one
+            out.update(replay_ms=out["ms"], replay_kernel_ms=out["kernel_ms"], ms=ms_d, kernel_ms=k_ms_d,
+                       kernel_n=k_n_d, launch="direct (faster than the HIP-graph replay of the same window)")
     nrec, acc, tries = b.counters()
     acc, tries = acc - acc0, tries - tries0
     n_groups = b.phase_streams() if precision == "fix16" else 1
@@ -443,7 +458,8 @@ def main():
     elif uses_phase_form(wl):
         kname = ("k_fix16_phase (the colour-phase launches of one sweep, 6·Q per sample group on its own stream, "
                  "each group also running its own energies, tempering and records; timed by HIP events on the "
-                 "caller's stream around each replay of the captured window, per sweep)")
+                 "caller's stream around the timed window (its HIP-graph replay, or its direct launches when those "
+                 "are faster: config.launch), per sweep)")
     else:
         kname = "k_fix16_sweep (one launch = one sweep of every (sample, slot))"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -471,20 +487,27 @@ def main():
         alu = {"bound": "alu", "achieved": round(lane, 2), "peak": VALU_PEAK_TLANE, "unit": "T VALU lane-instr/s",
                "frac": round(lane / VALU_PEAK_TLANE, 4),
                "lane_instr_per_update": tr["valu_lane_instr_per_update"],
-               "note": "peak: 256 CUs x 4 SIMDs x 64 lanes x 2.4 GHz / 2 cycles per wave instruction (the FP32 "
-                       "157.3 TFLOP/s counting an FMA as 2); about 17 of the instructions per update are "
-                       "transcendentals, which issue at about a third of that rate"}
-        if "trans_lane_instr_per_update" in tr:
-            # transcendentals occupy the SIMD about 3.4 times as long as an FMA
-            w = tr["valu_lane_instr_per_update"] + 2.4 * tr["trans_lane_instr_per_update"]
-            alu["weighted_frac"] = round(alu["frac"] * w / tr["valu_lane_instr_per_update"], 4)
+               "note": "peak: the published FP32 vector 157.3 TFLOP/s as FMA lane-instructions (2 flops each); "
+                       "SQ_INSTS_VALU x 64 over the sweep's phase launches per second of kernel time"}
+        if uses_phase_form(wl) and args.precision == "fix16":
+            # issue slots: a transcendental occupies the SIMD TRANS_COST times as long as an FMA
+            w = tr["valu_lane_instr_per_update"] + (TRANS_COST - 1.0) * TRANS_PER_UPDATE
+            issue = lane * w / tr["valu_lane_instr_per_update"]
+            alu.update(weighted_frac=round(issue / VALU_PEAK_TLANE, 4),
+                       issue_frac_of_probe=round(issue / VALU_FMA_ISSUE_TLANE, 4),
+                       trans_per_update=round(TRANS_PER_UPDATE, 2), trans_cost=round(TRANS_COST, 2),
+                       probe_fma_issue=VALU_FMA_ISSUE_TLANE,
+                       issue_note="FMA issue slots per second (transcendentals counted TRANS_COST times) over the "
+                                  "rate a standalone v_fma_f32 probe reaches on this chip: the kernel is VALU-issue "
+                                  "bound when this is near 1")
     # what binds: the larger of the measured HBM and VALU-issue utilisations
     if traffic is not None and alu is not None:
-        u_hbm, u_alu = roofline["measured_frac"], alu.get("weighted_frac", alu["frac"])
+        u_hbm, u_alu = roofline["measured_frac"], alu.get("issue_frac_of_probe", alu["frac"])
         roofline["binding"] = {"resource": "alu" if u_alu > u_hbm else "hbm", "hbm_measured_frac": u_hbm,
+                               "valu_issue_frac_of_probe": alu.get("issue_frac_of_probe"),
                                "valu_frac": alu["frac"], "valu_weighted_frac": alu.get("weighted_frac"),
-                               "note": "neither is saturated: the rest of the time is the latency of the dependent "
-                                       "gathers (wave cycles waiting) and the launch ramp and tail"}
+                               "note": "HBM: measured bytes over the 8 TB/s peak; VALU: issue slots over the "
+                                       "probe's FMA issue rate; the remainder is launch ramp and tail"}
 
     fp64 = None
     if args.precision == "fix16" and args.fp64_steps > 0:
@@ -563,6 +586,9 @@ def main():
                    "records_in_window": -(-args.steps // wl.meas_every) if wl.meas_every else 0},
         "direct_launch": {"ms_per_step": round(main_run["direct_ms"] / args.steps, 4),
                           "value": round(upd_per_sweep * args.steps / (main_run["direct_ms"] * 1e6), 2)},
+        "graph_replay": ({"ms_per_step": round(main_run["replay_ms"] / args.steps, 4),
+                          "value": round(upd_per_sweep * args.steps / (main_run["replay_ms"] * 1e6), 2)}
+                         if "replay_ms" in main_run else None),
         "roofline": roofline,
         "alu_roofline": alu,
         "fp64_plain": fp64,
