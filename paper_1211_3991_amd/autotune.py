@@ -82,12 +82,14 @@ def autotune(batch, sweeps=3, n_or=5, use_cache=True, pt_every=1):
         rep.update(trig=trig, allow_unit=unit,
                    ms_per_sweep={f"trig{t}_unit{u}": round(v, 4) for (t, u), v in times.items()})
         entry.update(trig=trig, allow_unit=unit, ms_per_sweep=rep["ms_per_sweep"])
-    n_sw = sweeps
+    n_sw = n_sw_groups = sweeps
     if n_phase >= 1:
         # the candidates differ by a few percent: each trial runs about 40 ms
-        # of sweeps (at least 2 x sweeps), twice, keeping the faster
+        # of sweeps (at least 2 x sweeps), twice, keeping the faster; the
+        # stream-group counts, a percent or two apart, about 100 ms
         probe = _time(batch, sweeps, n_or, saved)
         n_sw = int(min(256, max(2 * sweeps, 40.0 / max(probe, 1e-3))))
+        n_sw_groups = int(min(512, max(2 * sweeps, 100.0 / max(probe, 1e-3))))
     if forms.all():
         # every sample in the phase form: the (cos, sin) form alone
         times = {}
@@ -108,7 +110,7 @@ def autotune(batch, sweeps=3, n_or=5, use_cache=True, pt_every=1):
         st = {}
         for n in range(1, min(3, n_phase) + 1):
             batch.set_phase_streams(n)
-            st[n] = min(_time(batch, n_sw, n_or, saved, pt_every) for _ in range(2))
+            st[n] = min(_time(batch, n_sw_groups, n_or, saved, pt_every) for _ in range(2))
         fastest = min(st.values())
         n_best = min(n for n, v in st.items() if v <= 1.005 * fastest)
         rep["phase_streams_ms_per_sweep"] = {str(n): round(v, 4) for n, v in st.items()}

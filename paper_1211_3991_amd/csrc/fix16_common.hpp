@@ -64,10 +64,14 @@ template <> struct Trig<2> {
 };
 
 // 2 phi in units of 2pi/2^16, rounded, for phi = atan2(hy, hx): the axis of
-// the over-relaxation reflection.  atan on [0, 1] by an odd polynomial of
-// degree 9, least-squares fitted on 4000 Chebyshev nodes (|error| < 1.3e-5
-// rad in FP32, an eighth of the angle quantum 2pi/2^16), then the octant is
-// restored.
+// the over-relaxation reflection, in the low 16 bits of the result (the
+// higher bits are not part of it; callers reduce mod 2^16).  atan on [0, 1]
+// by an odd polynomial of degree 9, least-squares fitted on 4000 Chebyshev
+// nodes (|error| < 1.3e-5 rad in FP32, an eighth of the angle quantum
+// 2pi/2^16), then the octant is restored.  The rounding adds 1.5 * 2^23 in
+// the same fused multiply-add that scales the angle: the sum's ulp is 1, so
+// it is the scaled angle rounded to the nearest integer (ties to even), and
+// for |x| < 2^22 the float's low mantissa bits hold that integer mod 2^16.
 // The accuracy only affects the acceptance rate of the reflection, not the
 // detailed balance (the reflection is accepted by a Metropolis test).
 __device__ __forceinline__ uint32_t field_axis2(float hx, float hy)
@@ -85,7 +89,7 @@ __device__ __forceinline__ uint32_t field_axis2(float hx, float hy)
     a = ay > ax ? 1.5707963267948966f - a : a;
     a = hx < 0.f ? 3.141592653589793f - a : a;
     a = hy < 0.f ? -a : a;
-    return (uint32_t)__float2int_rn(a * kTwoPhiScale);
+    return __float_as_uint(fmaf(a, kTwoPhiScale, 12582912.0f));
 }
 
 __device__ __forceinline__ double2 unit64(uint32_t th, const double2 *t64)
@@ -99,20 +103,21 @@ __device__ __forceinline__ double2 unit64(uint32_t th, const double2 *t64)
 __device__ __forceinline__ float accept_factor(float beta) { return -beta * 1.4426950408889634f; }
 
 // Metropolis acceptance with probability min(1, exp(-beta dE)) for the FP32
-// exp (the hardware 2^x of dE * accept_factor(beta)).  The uniform is the
-// top 16 bits of `word`; on a tie with the 16-bit threshold (probability
-// 2^-16) 32 more bits are drawn from the counter (site, sweep, slot,
-// purpose 4 | sub), so the test is exact: U < p.
+// exp p (the hardware 2^x of dE * accept_factor(beta); p >= 1 when dE <= 0).
+// The uniform is U = (u + V) / 2^16 with u the top 16 bits of `word` and V a
+// further uniform, drawn only when needed: with q = p 2^16 - u (exact in one
+// fused multiply-add), U < p holds for every V when q >= 1, for none when
+// q < 0, and else (probability 2^-16) iff V < q, V from 32 more bits of the
+// counter (site, sweep, slot, purpose 4 | sub).  So the test is exact.
 __device__ __forceinline__ bool accept_move(float dE, float factor, uint32_t word, uint32_t site, uint32_t sweep,
                                             uint32_t slot, uint32_t sub, const SampleDesc &d)
 {
-    if (dE <= 0.f) return true;
     const float p = __builtin_amdgcn_exp2f(dE * factor);
-    const float p16 = p * 65536.0f;
-    const uint32_t u16 = word >> 16, f = (uint32_t)p16;
-    if (u16 != f) return u16 < f;
+    const float q = fmaf(p, 65536.0f, -(float)(word >> 16));
+    if (q >= 1.0f) return true;
+    if (q < 0.0f) return false;
     const U4 x = philox4x32_10({site, sweep, slot, tag(kMetAcc, sub)}, d.seed_lo, d.seed_hi);
-    return (double)x.x < (double)(p16 - (float)f) * 4294967296.0;
+    return (double)x.x < (double)q * 4294967296.0;
 }
 
 // Philox4x32-10 as philox4x32_10, for keys that are the same in every lane

@@ -314,8 +314,8 @@ def test_graph_replay_equals_direct_launches():
 
 def test_autotune_phase_streams_restores_state(tmp_path, monkeypatch):
     """Every sample in the phase form: the tuner times one to three stream
-    groups, applies the fastest (the fewest within 2%), and restores the
-    state."""
+    groups, applies the fastest (the fewer on a tie within 0.5%), and
+    restores the state."""
     monkeypatch.setenv("XY_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
     g = [xy.Graph.levy(128, 6, 3.5, s) for s in range(4)]
     b = xy.Batch(g, workloads.linear_ladder(1.0, 2.5, 8), precision="fix16", max_records=4)
@@ -364,8 +364,10 @@ def test_full_headline_shape_sampled():
     graphs = [xy.Graph.levy(s.L, s.z, s.rho, s.seed) for s in wl.samples]
     b = xy.Batch(graphs, wl.T, precision="fix16", seeds=[s.seed for s in wl.samples], max_records=4)
     b.autotune(sweeps=1, use_cache=False)
+    _, _, tries0 = b.counters()                  # the tuner's trials temper too
     b.sweep(6, pt_every=1, meas_every=3)
     nrec, acc, tries = b.counters()
+    tries = tries - tries0
     assert nrec == 2
     rec = b.records().cpu().numpy()
     o = b.measure().cpu().numpy()
