@@ -1,8 +1,12 @@
-"""Fixed-point sweep against the FP64 sweep at the two large workload shapes
+"""Fixed-point sweep against the FP64 sweep at the batched workload shapes
 (through the C ABI): 64 samples of L=256 (rho=3.5, 24 temperatures in
-[1.0, 2.5]) and 32 samples of L=512 (rho=2.5, 16 temperatures in [1.5, 3.5]),
-z = 6, parallel tempering every sweep (App. B), in the launch configuration
-the benchmark uses (autotuned stream groups, HIP-graph replay).
+[1.0, 2.5]), 32 samples of L=512 (rho=2.5, 16 temperatures in [1.5, 3.5]),
+64 samples of L=128 (rho=3.5, 16 temperatures in [1.0, 2.5]) and the 128
+uneven samples (L = 32, 64, 128, 256; rho = 2.5, 3.5, 4.5; 32 temperatures in
+[0.8, 3.0]; the smaller graphs in the workgroup form, the larger in the phase
+form), z = 6, parallel tempering every sweep (App. B), in the launch
+configuration the benchmark uses (autotuned form and stream groups, HIP-graph
+replay).
 
 Both precisions sweep the same graphs from independent uniform random starts
 for the same number of sweeps, measuring E, |m|^2, |m|^4, F_x, F_y (Sec. 3)
@@ -41,7 +45,7 @@ if not torch.cuda.is_available():
 
 from paper_1211_3991_amd import analysis, parity  # noqa: E402
 
-SWEEPS = {"headline_l256": 2048, "large_l512": 2048}
+SWEEPS = {"headline_l256": 2048, "large_l512": 2048, "batch_l128": 2048, "uneven_sizes": 1024}
 
 
 def _report(out):
@@ -49,14 +53,20 @@ def _report(out):
         s = out[k]
         print(f"{out['workload']} {k}: n={s['n']} frac|z|>3={s['frac_gt']:.4f} chi2/dof={s['chi2_dof']:.3f} "
               f"max|z|={s['max_abs']:.2f} outliers={s['outliers'][:20]}", flush=True)
+    mv = out["disorder"].get("mv")
+    if mv:
+        print(f"{out['workload']} disorder Hotelling: min p={mv['min_p']:.4g} (bar {1e-3 / mv['n_T']:.2g}) "
+              f"chi2/dof={mv['chi2_dof']:.3f} (bar {mv['chi2_dof_bar']:.2f})", flush=True)
     print(json.dumps(out["per_observable"]), flush=True)
+    print(json.dumps({"max_rel_dev_disorder": out["max_rel_dev_disorder"],
+                      "rel_err_disorder": out["rel_err_disorder"]}), flush=True)
     path = os.environ.get("XY_PARITY_OUT")
     if path:
         with open(os.path.join(path, f"parity_{out['workload']}.json"), "w") as fh:
             json.dump(out, fh, indent=1)
 
 
-@pytest.mark.parametrize("name", ["headline_l256", "large_l512"])
+@pytest.mark.parametrize("name", ["headline_l256", "large_l512", "batch_l128", "uneven_sizes"])
 def test_fix16_matches_fp64_at_full_shape(name):
     wl = workloads.ALL[name]()
     out, rec16, rec64 = parity.fix16_vs_fp64(wl, SWEEPS[name], meas_every=4, n_bins=20)
