@@ -21,9 +21,16 @@ constexpr float kAngle = 9.587379924285257e-05f;      // 2 pi / 2^16
 //      low 5 bits, delta <= 3.1e-3, with cos = 1 - delta^2/2 and sin = delta
 //      (truncation errors 4e-12 and 5e-9)
 //   2: the hardware sine/cosine of theta / 2^16 revolutions (no table)
+// unit takes a 16-bit angle; unit_lo and unit_hi the angle in the low or the
+// high half of a 32-bit word (two slots' angles).
 template <int kTrig> struct Trig;
 
-template <> struct Trig<0> {
+template <int kTrig> struct TrigHalves {
+    static __device__ __forceinline__ float2 unit_lo(uint32_t w, const float2 *t) { return Trig<kTrig>::unit(w & 0xFFFFu, t); }
+    static __device__ __forceinline__ float2 unit_hi(uint32_t w, const float2 *t) { return Trig<kTrig>::unit(w >> 16, t); }
+};
+
+template <> struct Trig<0> : TrigHalves<0> {
     static constexpr size_t kBytes = 512 * 8;
     static __device__ __forceinline__ void load(float2 *t, const DevBatch &b, int tid, int stride)
     {
@@ -36,7 +43,7 @@ template <> struct Trig<0> {
     }
 };
 
-template <> struct Trig<1> {
+template <> struct Trig<1> : TrigHalves<1> {
     static constexpr size_t kBytes = 2048 * 8;
     static __device__ __forceinline__ void load(float2 *t, const DevBatch &b, int tid, int stride)
     {
@@ -54,31 +61,65 @@ template <> struct Trig<1> {
 template <> struct Trig<2> {
     static constexpr size_t kBytes = 0;
     static __device__ __forceinline__ void load(float2 *, const DevBatch &, int, int) {}
-    static __device__ __forceinline__ float2 unit(uint32_t th, const float2 *)
+    // The input is 128 + theta / 2^16 revolutions: the float of exponent 7
+    // (ulp 2^-16) whose low 16 mantissa bits are theta, exact and built from
+    // the bits in one instruction; sine and cosine see only its fraction
+    // theta / 2^16 (the 128 whole turns are invisible to them, and the results
+    // equal those for 1 + theta / 2^16 bit for bit).
+    static __device__ __forceinline__ float2 at(float r)
     {
-        // 1 + theta / 2^16 revolutions, built from the bits (exact); one whole
-        // turn more than theta, which sine and cosine do not see
-        const float r = __uint_as_float(0x3F800000u | (th << 7));
         return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
     }
+    static __device__ __forceinline__ float2 unit(uint32_t th, const float2 *)
+    {
+        return at(__uint_as_float(0x43000000u | th));
+    }
+    // bits of w above the sixteenth are ignored (one v_and_or_b32)
+    static __device__ __forceinline__ float2 unit_lo(uint32_t w, const float2 *)
+    {
+        return at(__uint_as_float(0x43000000u | (w & 0xFFFFu)));
+    }
+    // (one v_or_b32 with the high half selected by SDWA)
+    static __device__ __forceinline__ float2 unit_hi(uint32_t w, const float2 *)
+    {
+        return at(__uint_as_float(0x43000000u | (w >> 16)));
+    }
 };
+
+// a ^ b ^ c in one v_bitop3_b32 (truth table 0x96), all operands per lane
+__device__ __forceinline__ uint32_t xor3_v(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
 
 // 2 phi in units of 2pi/2^16, rounded, for phi = atan2(hy, hx): the axis of
 // the over-relaxation reflection, in the low 16 bits of the result (the
 // higher bits are not part of it; callers reduce mod 2^16).  atan on [0, 1]
 // by an odd polynomial of degree 9, least-squares fitted on 4000 Chebyshev
 // nodes (|error| < 1.3e-5 rad in FP32, an eighth of the angle quantum
-// 2pi/2^16), then the octant is restored.  The rounding adds 1.5 * 2^23 in
-// the same fused multiply-add that scales the angle: the sum's ulp is 1, so
-// it is the scaled angle rounded to the nearest integer (ties to even), and
-// for |x| < 2^22 the float's low mantissa bits hold that integer mod 2^16.
-// The accuracy only affects the acceptance rate of the reflection, not the
-// detailed balance (the reflection is accepted by a Metropolis test).
+// 2pi/2^16), of t = min(|hx|, |hy|) / max(|hx|, |hy|) (0 for a zero field).
+// The octant is restored on the doubled angle, where it is a sign and a half
+// turn: with a = atan(t), phi is +-phi0 or +-(pi - phi0) for phi0 = a, or
+// pi/2 - a when |hy| > |hx| ("swapped"), so 2 phi = +-2 phi0 (mod 2 pi), +
+// when hx and hy have equal signs; that is 2 phi = sigma 2a, plus pi when
+// swapped, where sigma's sign bit is the XOR of those of hx, hy and
+// |hx| - |hy| (negative exactly when swapped; the sign of a zero component
+// does not matter, as a = 0 then).  The rounding adds 1.5 * 2^23 (+ 2^15 for
+// the half turn) in the same fused multiply-add that scales the angle: the
+// sum's ulp is 1, so it is the scaled angle rounded to the nearest integer
+// (ties to even), and for |x| < 2^22 the float's low mantissa bits hold that
+// integer mod 2^16.  The accuracy only affects the acceptance rate of the
+// reflection, not the detailed balance (the reflection is accepted by a
+// Metropolis test).
 __device__ __forceinline__ uint32_t field_axis2(float hx, float hy)
 {
     const float ax = fabsf(hx), ay = fabsf(hy);
-    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
-    const float t = mx > 0.f ? mn * __builtin_amdgcn_rcpf(mx) : 0.f;
+    // the floor keeps t = 0 for a zero field; the median of (ax, ay, 0) is the
+    // smaller magnitude (one v_med3_f32 with the absolute values as modifiers)
+    const float mx = fmaxf(fmaxf(ax, ay), 1e-30f), mn = __builtin_amdgcn_fmed3f(ax, ay, 0.0f);
+    const float t = mn * __builtin_amdgcn_rcpf(mx);
     const float t2 = t * t;
     float p = 0.02093181200325489f;
     p = fmaf(p, t2, -0.08540830761194229f);
@@ -86,10 +127,9 @@ __device__ __forceinline__ uint32_t field_axis2(float hx, float hy)
     p = fmaf(p, t2, -0.3304055631160736f);
     p = fmaf(p, t2, 0.9998787641525269f);
     float a = p * t;                                   // atan(t), t in [0, 1]
-    a = ay > ax ? 1.5707963267948966f - a : a;
-    a = hx < 0.f ? 3.141592653589793f - a : a;
-    a = hy < 0.f ? -a : a;
-    return __float_as_uint(fmaf(a, kTwoPhiScale, 12582912.0f));
+    const float d = ax - ay;                           // negative: swapped
+    a = copysignf(a, __uint_as_float(xor3_v(__float_as_uint(hx), __float_as_uint(hy), __float_as_uint(d))));
+    return __float_as_uint(fmaf(a, kTwoPhiScale, d < 0.f ? 12615680.0f : 12582912.0f));
 }
 
 __device__ __forceinline__ double2 unit64(uint32_t th, const double2 *t64)
@@ -97,10 +137,6 @@ __device__ __forceinline__ double2 unit64(uint32_t th, const double2 *t64)
     const double2 a = t64[th >> 8], c = t64[256 + (th & 255u)];
     return make_double2(a.x * c.x - a.y * c.y, a.y * c.x + a.x * c.y);
 }
-
-// -beta log2(e): the factor of dE in the exponent of the acceptance
-// probability 2^(dE * (-beta log2 e)) = exp(-beta dE), one per slot.
-__device__ __forceinline__ float accept_factor(float beta) { return -beta * 1.4426950408889634f; }
 
 // Metropolis acceptance with probability min(1, exp(-beta dE)) for the FP32
 // exp p (the hardware 2^x of dE * accept_factor(beta); p >= 1 when dE <= 0).
@@ -116,6 +152,9 @@ __device__ __forceinline__ bool accept_move(float dE, float factor, uint32_t wor
     const float q = fmaf(p, 65536.0f, -(float)(word >> 16));
     if (q >= 1.0f) return true;
     if (q < 0.0f) return false;
+    // (an empty volatile asm on the counter words: the compiler may not start
+    // this rare draw's rounds ahead of the branch)
+    asm volatile("" : "+v"(site), "+v"(slot));
     const U4 x = philox4x32_10({site, sweep, slot, tag(kMetAcc, sub)}, d.seed_lo, d.seed_hi);
     return (double)x.x < (double)q * 4294967296.0;
 }

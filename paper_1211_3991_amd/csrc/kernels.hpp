@@ -23,6 +23,7 @@ struct DevBatch {
     const double *beta;       // [G][R] by temperature index
     int32_t *slot_of_T;       // [G][R]
     int32_t *T_of_slot;       // [G][R]
+    float *fac_slot;          // [G][R]: accept_factor of the inverse temperature each slot holds (fix16)
     double *E_slot;           // [G][R]
     double *obs_slot;         // [G][R][XY_NOBS]
     double *partial;          // [G][64][R][11] block partial sums of the observables (fp64, fix16 phase form)
@@ -35,6 +36,15 @@ struct DevBatch {
     uint8_t *log;             // Metropolis decision log (fp64) or NULL
     int log_sweeps;
 };
+
+// -beta log2(e) in FP32: the factor of dE in the exponent of the fixed-point
+// acceptance probability 2^(dE * factor) = exp(-beta dE).  The table
+// fac_slot holds it by slot; whatever moves a temperature to another slot
+// (tempering, a new ladder, a restored state) rewrites it.
+__device__ __forceinline__ float accept_factor(double beta) { return -(float)beta * 1.4426950408889634f; }
+
+// fac_slot of every (sample, slot) from beta and T_of_slot
+hipError_t launch_slot_factors(const DevBatch &b, hipStream_t s);
 
 // FP64 path (kernels_fp64.hip, built with -ffp-contract=off).
 hipError_t launch_fp64_init(const DevBatch &b, int max_n, hipStream_t s);

@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_fix16_sweep(DevBatch b, const Item *
     }
     __syncthreads();
 
-    const float factor = accept_factor((float)b.beta[s * R + b.T_of_slot[s * R + slot]]);
+    const float factor = b.fac_slot[s * R + slot];
     const uint32_t sweep = b.ctl->sweep;
     const int32_t *cptr = b.i32 + d.sell_ptr;
     const int32_t *cw = b.i32 + d.sell_w;

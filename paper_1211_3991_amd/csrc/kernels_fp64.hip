@@ -266,6 +266,8 @@ __global__ __launch_bounds__(kEndBlock) void k_end_sweep(DevBatch b, const int32
             if (accept) {
                 sot[k] = hi; sot[k + 1] = lo;
                 tos[hi] = k; tos[lo] = k + 1;
+                b.fac_slot[s * R + hi] = accept_factor(beta[k]);
+                b.fac_slot[s * R + lo] = accept_factor(beta[k + 1]);
                 b.pt_acc[s * R + k] += 1;
             }
         }
@@ -286,7 +288,22 @@ __global__ __launch_bounds__(kEndBlock) void k_end_sweep(DevBatch b, const int32
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_slot_factors(DevBatch b)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= b.G * b.R) return;
+    const int s = t / b.R;
+    b.fac_slot[t] = accept_factor(b.beta[s * b.R + b.T_of_slot[t]]);
+}
+
 }  // namespace
+
+hipError_t launch_slot_factors(const DevBatch &b, hipStream_t s)
+{
+    const int n = b.G * b.R;
+    hipLaunchKernelGGL(k_slot_factors, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, b);
+    return hipGetLastError();
+}
 
 hipError_t launch_fp64_init(const DevBatch &b, int max_n, hipStream_t s)
 {

@@ -114,8 +114,10 @@ __device__ __forceinline__ void load_words(char *Ab, const PhaseLanes &pl, const
 // The update of one unit's sites by this thread, from its loaded rows jj and
 // neighbour words vv.  kLast: the last sub-sweep of the sweep, which also sums
 // the links to lower colours into the energy partials (uses esum and a
-// workgroup barrier; every thread of the workgroup calls it).
-template <typename Idx, bool kLast, int kTrig>
+// workgroup barrier; every thread of the workgroup calls it).  kMetro: the
+// Metropolis sub-sweep (sub == 0; a uniform new angle), else an
+// over-relaxation one (the reflection about the local field).
+template <typename Idx, bool kLast, int kTrig, bool kMetro>
 __device__ __forceinline__ void update_unit(const DevBatch &b, const PhaseLanes &pl, const float2 *tab, float *esum,
                                             int colour, int sub, int max_blocks, uint32_t sweep, const int4 &ua,
                                             const int4 &ub, const UnitPtrs &p, const int *jj, const uint2 *vv)
@@ -129,15 +131,9 @@ __device__ __forceinline__ void update_unit(const DevBatch &b, const PhaseLanes 
     const int bx = __builtin_amdgcn_readfirstlane(ub.z), uw = __builtin_amdgcn_readfirstlane(ub.w);
     const int kmin = uw & 255, kmax = (uw >> 8) & 255;
     const SampleDesc &d = b.desc[s];
-    float factor[4];   // accept_factor of each slot's inverse temperature
-    {
-        const int4 tq = *reinterpret_cast<const int4 *>(b.T_of_slot + s * R + 4 * q);
-        const int ts[4] = {tq.x, tq.y, tq.z, tq.w};
-        const char *bs = reinterpret_cast<const char *>(b.beta + s * R);   // this sample's ladder
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            factor[r] = accept_factor((float)*reinterpret_cast<const double *>(bs + 8u * (uint32_t)ts[r]));
-    }
+    // accept_factor of the inverse temperatures at the thread's four slots
+    const float4 fq = *reinterpret_cast<const float4 *>(b.fac_slot + s * R + 4 * q);
+    const float factor[4] = {fq.x, fq.y, fq.z, fq.w};
     const int c0 = __builtin_amdgcn_readfirstlane(ua.w) - bx * S; // first site of the colour class
     float hx[4] = {0.f, 0.f, 0.f, 0.f}, hy[4] = {0.f, 0.f, 0.f, 0.f};
     float lx[4] = {0.f, 0.f, 0.f, 0.f}, ly[4] = {0.f, 0.f, 0.f, 0.f};   // last sub-sweep: links to lower colours
@@ -145,10 +141,10 @@ __device__ __forceinline__ void update_unit(const DevBatch &b, const PhaseLanes 
     // lower colours are a prefix: their field is the running sum taken after
     // the last of them
     auto add = [&](uint2 v, int j, bool first) {                // first: the sum starts here
-        const uint32_t th[4] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16};
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const float2 e = Trig<kTrig>::unit(th[r], tab);
+            const uint32_t w = r < 2 ? v.x : v.y;
+            const float2 e = (r & 1) ? Trig<kTrig>::unit_hi(w, tab) : Trig<kTrig>::unit_lo(w, tab);
             hx[r] = first ? e.x : hx[r] + e.x;
             hy[r] = first ? e.y : hy[r] + e.y;
         }
@@ -183,25 +179,32 @@ __device__ __forceinline__ void update_unit(const DevBatch &b, const PhaseLanes 
     }
     // the key is the sample's seed, the same in every lane (s is uniform)
     const U4 w = philox4x32_10_uniform_key(
-        {(uint32_t)i, sweep, (uint32_t)(4 * q), tag(sub == 0 ? kMet : kOR, (uint32_t)sub)}, d.seed_lo, d.seed_hi);
+        {(uint32_t)i, sweep, (uint32_t)(4 * q), tag(kMetro ? kMet : kOR, (uint32_t)sub)}, d.seed_lo, d.seed_hi);
     const uint32_t words[4] = {w.x, w.y, w.z, w.w};
     const uint2 me = angle_word(p.Ab, pl, i);
-    const uint32_t cur_th[4] = {me.x & 0xFFFFu, me.x >> 16, me.y & 0xFFFFu, me.y >> 16};
+    // the angles in the low 16 bits (higher bits are not part of them: the
+    // (cos, sin) forms and the packing below ignore them)
+    const uint32_t cur_th[4] = {me.x, me.x >> 16, me.y, me.y >> 16};
     uint32_t out[4];
     float e_q[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int slot = 4 * q + r;
         const uint32_t th = cur_th[r];
-        const uint32_t th_new = sub == 0 ? (words[r] & 0xFFFFu) : ((field_axis2(hx[r], hy[r]) - th) & 0xFFFFu);
-        const float2 cur = Trig<kTrig>::unit(th, tab), nu = Trig<kTrig>::unit(th_new, tab);
+        const uint32_t th_new = kMetro ? words[r] : field_axis2(hx[r], hy[r]) - th;
+        const uint32_t w = r < 2 ? me.x : me.y;
+        const float2 cur = (r & 1) ? Trig<kTrig>::unit_hi(w, tab) : Trig<kTrig>::unit_lo(w, tab);
+        const float2 nu = Trig<kTrig>::unit_lo(th_new, tab);
         const float dE = hx[r] * (cur.x - nu.x) + hy[r] * (cur.y - nu.y);
         const bool acc = accept_move(dE, factor[r], words[r], (uint32_t)i, sweep, (uint32_t)slot, (uint32_t)sub, d);
         out[r] = acc ? th_new : th;
         const float2 f = acc ? nu : cur;
         e_q[r] = p.active ? -(f.x * lx[r] + f.y * ly[r]) : 0.f;
     }
-    if (p.active) angle_word(p.Ab, pl, i) = make_uint2(out[0] | (out[1] << 16), out[2] | (out[3] << 16));
+    // low halves of out[2k + 1] over those of out[2k], one byte permute each
+    if (p.active)
+        angle_word(p.Ab, pl, i) =
+            make_uint2(__builtin_amdgcn_perm(out[1], out[0], 0x05040100u), __builtin_amdgcn_perm(out[3], out[2], 0x05040100u));
     if constexpr (kLast) {
         // per-slot energy of this unit, summed in a fixed order, to
         // epart[k_ph][colour][block][slot]; a final pass adds the blocks in order
@@ -219,7 +222,7 @@ __device__ __forceinline__ void update_unit(const DevBatch &b, const PhaseLanes 
 }
 
 // One work unit per workgroup (gridDim.x == n_units).
-template <typename Idx, bool kLast, int kTrig>
+template <typename Idx, bool kLast, int kTrig, bool kMetro>
 __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const int4 *units, int n_units, int colour,
                                                             int sub, int max_blocks, int grp, int reverse)
 {
@@ -239,7 +242,7 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
         Trig<kTrig>::load(tab, b, threadIdx.x, kPhaseBlock);
         __syncthreads();
     }
-    update_unit<Idx, kLast, kTrig>(b, pl, tab, esum, colour, sub, max_blocks, b.ctl[grp].sweep, ua, ub, p, jj,
+    update_unit<Idx, kLast, kTrig, kMetro>(b, pl, tab, esum, colour, sub, max_blocks, b.ctl[grp].sweep, ua, ub, p, jj,
                                           vv);
 }
 
@@ -247,19 +250,27 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
 
 int fix16_phase_sites_per_block(int R) { return kPhaseBlock / (R / 4); }
 
-template <int kTrig>
-void (*phase_kernel(int idx16, int last))(DevBatch, const int4 *, int, int, int, int, int, int)
+using PhaseKernel = void (*)(DevBatch, const int4 *, int, int, int, int, int, int);
+
+template <int kTrig, bool kMetro>
+PhaseKernel phase_kernel(int idx16, int last)
 {
-    return idx16 ? (last ? k_fix16_phase<uint16_t, true, kTrig> : k_fix16_phase<uint16_t, false, kTrig>)
-                 : (last ? k_fix16_phase<int32_t, true, kTrig> : k_fix16_phase<int32_t, false, kTrig>);
+    return idx16 ? (last ? k_fix16_phase<uint16_t, true, kTrig, kMetro> : k_fix16_phase<uint16_t, false, kTrig, kMetro>)
+                 : (last ? k_fix16_phase<int32_t, true, kTrig, kMetro> : k_fix16_phase<int32_t, false, kTrig, kMetro>);
+}
+
+template <bool kMetro>
+PhaseKernel phase_kernel(int trig, int idx16, int last)
+{
+    return trig == 0 ? phase_kernel<0, kMetro>(idx16, last)
+                     : trig == 1 ? phase_kernel<1, kMetro>(idx16, last) : phase_kernel<2, kMetro>(idx16, last);
 }
 
 hipError_t launch_fix16_phase(const DevBatch &b, const int4 *units, int colour, int sub,
                               int last, int n_units, int max_blocks, int grp, int reverse, hipStream_t s)
 {
     if (n_units == 0) return hipSuccess;
-    auto k = b.trig == 0 ? phase_kernel<0>(b.idx16, last)
-                         : b.trig == 1 ? phase_kernel<1>(b.idx16, last) : phase_kernel<2>(b.idx16, last);
+    const PhaseKernel k = sub == 0 ? phase_kernel<true>(b.trig, b.idx16, last) : phase_kernel<false>(b.trig, b.idx16, last);
     hipLaunchKernelGGL(k, dim3((unsigned)n_units), dim3(kPhaseBlock), 0, s, b, units, n_units, colour, sub, max_blocks,
                        grp, reverse);
     return hipGetLastError();

@@ -249,6 +249,7 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
     wl.beta = off;      off = align_up(off + 8 * GR, 256);
     wl.slot_of_T = off; off = align_up(off + 4 * GR, 256);
     wl.T_of_slot = off; off = align_up(off + 4 * GR, 256);
+    wl.fac_slot = off;  off = align_up(off + 4 * GR, 256);
     wl.E_slot = off;    off = align_up(off + 8 * GR, 256);
     wl.obs_slot = off;  off = align_up(off + 8 * XY_NOBS * GR, 256);
     wl.pt_acc = off;    off = align_up(off + 8 * GR, 256);
@@ -592,6 +593,7 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
         dv.beta = reinterpret_cast<const double *>(wbase + wl.beta);
         dv.slot_of_T = reinterpret_cast<int32_t *>(wbase + wl.slot_of_T);
         dv.T_of_slot = reinterpret_cast<int32_t *>(wbase + wl.T_of_slot);
+        dv.fac_slot = reinterpret_cast<float *>(wbase + wl.fac_slot);
         dv.E_slot = reinterpret_cast<double *>(wbase + wl.E_slot);
         dv.obs_slot = reinterpret_cast<double *>(wbase + wl.obs_slot);
         dv.pt_acc = reinterpret_cast<unsigned long long *>(wbase + wl.pt_acc);
@@ -604,7 +606,9 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
         dv.idx16 = p.idx16 ? 1 : 0;
         dv.trig = trig;
 
-        e = (precision == XY_FP64) ? launch_fp64_init(dv, p.max_n, s) : launch_fix16_init(dv, p.max_n, s);
+        e = launch_slot_factors(dv, s);
+        if (e == hipSuccess)
+            e = (precision == XY_FP64) ? launch_fp64_init(dv, p.max_n, s) : launch_fix16_init(dv, p.max_n, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);   // host images must outlive the copies
         if (e != hipSuccess) { xy_batch_free(b); return hip_err(e, "xy_batch_init"); }
     } catch (const std::bad_alloc &) {
@@ -826,6 +830,7 @@ xy_status set_ladder(xy_batch *b, const double *T, hipStream_t s)
     for (size_t k = 0; k < GR; ++k) b->beta_host[k] = 1.0 / T[k];
     e = hipMemcpyAsync(b->d_beta, b->beta_host.data(), 8 * GR, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipEventRecord(b->ev_beta, s);
+    if (e == hipSuccess) e = launch_slot_factors(b->dev, s);
     return e == hipSuccess ? XY_OK : hip_err(e, "xy_sweep ladder");
 }
 
@@ -1021,6 +1026,7 @@ extern "C" xy_status xy_set_state(xy_batch *b, const void *h_state, const int32_
         if (e == hipSuccess && h_slot_of_T) {
             e = hipMemcpyAsync(b->dev.slot_of_T, sot.data(), sot.size() * 4, hipMemcpyHostToDevice, s);
             if (e == hipSuccess) e = hipMemcpyAsync(b->dev.T_of_slot, tos.data(), tos.size() * 4, hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = launch_slot_factors(b->dev, s);
         }
         for (int g = 0; g < kMaxPhaseStreams && e == hipSuccess; ++g)
             e = hipMemcpyAsync(&b->dev.ctl[g].sweep, &sweep, 4, hipMemcpyHostToDevice, s);

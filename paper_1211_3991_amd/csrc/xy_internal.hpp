@@ -124,7 +124,7 @@ struct Ctl {
 
 // Work region layout (byte offsets computed by layout_work()).
 struct WorkLayout {
-    size_t ctl, beta, slot_of_T, T_of_slot, E_slot, obs_slot, pt_acc, pt_try, partial, epart, total;
+    size_t ctl, beta, slot_of_T, T_of_slot, fac_slot, E_slot, obs_slot, pt_acc, pt_try, partial, epart, total;
 };
 
 struct GraphLayout {

@@ -8,19 +8,23 @@ form), z = 6, parallel tempering every sweep (App. B), in the launch
 configuration the benchmark uses (autotuned form and stream groups, HIP-graph
 replay).
 
-Both precisions sweep the same graphs from independent uniform random starts
-for the same number of sweeps, measuring E, |m|^2, |m|^4, F_x, F_y (Sec. 3)
-every 4 sweeps; the second half of the records is kept (the last time
-window, Sec. 4).  The FP64 sweep is the path whose decisions equal the
+Both precisions sweep the same graphs from the ordered start with
+independent random keys for the same number of sweeps, measuring E, |m|^2,
+|m|^4, F_x, F_y (Sec. 3) every 4 sweeps; the second half of the records is
+kept (the last time window, Sec. 4).  A time bin must span several
+integrated autocorrelation times for the jackknife errors to hold: at L=512
+that time reaches 25-35 sweeps for E and |m|^2 in the slowest chains (median
+3.5, 90th percentile 7), so that case runs 4096 sweeps (bins of 102 sweeps;
+at 2048, bins of 51 sweeps, a few such chains give too small errors).  The FP64 sweep is the path whose decisions equal the
 oracle's bit for bit (tests/test_gpu_fp64_parity.py, also at this L=256
 shape), so this ties the fixed-point form, at its real shape, to the oracle's
 observables.  The bar: per (sample, temperature, observable) with jackknife
 errors over 20 time bins (thousands of comparisons), at most 1% beyond 3
 sigma and chi^2/dof at most 1.5; disorder-paired per (temperature,
 observable) (tens of comparisons, errors from the sample-to-sample spread),
-the largest |z| below the 1e-3 family-wise bar and chi^2/dof below the
-larger of 1.5 and its 1e-3 quantile (analysis.comparison_ok); every outlier
-is printed.  The two chains of a sample follow the same law from the
+the largest |z| below the 1e-3 family-wise bar and, per temperature,
+Hotelling's test of the five observables together at the family-wise 1e-3
+(analysis.comparison_ok); every outlier is printed.  The two chains of a sample follow the same law from the
 same initial law, so their windows compare even where a chain is still
 relaxing; the first-against-second-quarter drift of the kept records is
 printed as the equilibration check.
@@ -45,7 +49,7 @@ if not torch.cuda.is_available():
 
 from paper_1211_3991_amd import analysis, parity  # noqa: E402
 
-SWEEPS = {"headline_l256": 2048, "large_l512": 2048, "batch_l128": 2048, "uneven_sizes": 1024}
+SWEEPS = {"headline_l256": 2048, "large_l512": 4096, "batch_l128": 2048, "uneven_sizes": 1024}
 
 
 def _report(out):

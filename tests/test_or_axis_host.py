@@ -49,6 +49,23 @@ def test_polynomial_within_stated_bound():
     assert 1.3e-5 < (2 * np.pi / 65536) / 7               # under an eighth of the quantum (with margin)
 
 
+def _axis2(hx, hy):
+    """The device's 2 phi on the 2^16 grid: a = atan(min/max) by the
+    polynomial, signed by the XOR of the sign bits of hx, hy and |hx| - |hy|,
+    scaled by 2^16 / pi and rounded, plus a half turn when |hy| > |hx|."""
+    ax, ay = np.abs(hx), np.abs(hy)
+    mx, mn = np.maximum(np.maximum(ax, ay), np.float32(1e-30)), np.minimum(ax, ay)
+    a = _atan01((mn / mx).astype(np.float32)).astype(np.float64)
+    d = (ax - ay).astype(np.float32)
+    neg = np.signbit(hx) ^ np.signbit(hy) ^ np.signbit(d)
+    a = np.where(neg, -a, a)
+    return (np.rint(a * 65536 / np.pi).astype(np.int64) + np.where(d < 0, 32768, 0)) & 0xFFFF
+
+
+def _axis2_exact(hx, hy):
+    return np.rint(np.arctan2(hy.astype(np.float64), hx.astype(np.float64)) * 65536 / np.pi).astype(np.int64) & 0xFFFF
+
+
 def test_axis_within_one_grid_step():
     """2 phi on the 2^16 grid, with the octant restored as on the device, is
     the exact rounding or one step from it over random fields (about 15% of
@@ -56,14 +73,19 @@ def test_axis_within_one_grid_step():
     exact reflection, which the Metropolis test of the move absorbs)."""
     rng = np.random.default_rng(7)
     hx, hy = (rng.standard_normal(200000) * 3).astype(np.float32), (rng.standard_normal(200000) * 3).astype(np.float32)
-    ax, ay = np.abs(hx), np.abs(hy)
-    mx, mn = np.maximum(ax, ay), np.minimum(ax, ay)
-    a = _atan01((mn / mx).astype(np.float32)).astype(np.float64)
-    a = np.where(ay > ax, np.pi / 2 - a, a)
-    a = np.where(hx < 0, np.pi - a, a)
-    a = np.where(hy < 0, -a, a)
-    got = np.rint(a * 65536 / np.pi).astype(np.int64) & 0xFFFF
-    exact = np.rint(np.arctan2(hy.astype(np.float64), hx.astype(np.float64)) * 65536 / np.pi).astype(np.int64) & 0xFFFF
-    d = (got - exact) & 0xFFFF
+    d = (_axis2(hx, hy) - _axis2_exact(hx, hy)) & 0xFFFF
     d = np.minimum(d, 65536 - d)
     assert d.max() <= 1 and d.mean() < 0.25, (d.max(), d.mean())
+
+
+def test_axis_octants_and_degenerate_fields():
+    """Every octant, the axes with either sign of zero, the diagonals and the
+    zero field: the doubled angle is the exact one within a grid step, and a
+    zero field gives the axis 0 (a reflection theta -> -theta)."""
+    ang = np.arange(16) * (np.pi / 8) + 0.1                         # interior points of all octants
+    hx = np.concatenate([np.cos(ang), [1, -1, 0, 0, -0.0, 1, -1, 1, -1], [0.0, -0.0]]).astype(np.float32)
+    hy = np.concatenate([np.sin(ang), [0, 0, 1, -1, 1, -0.0, -0.0, 1, -1], [0.0, -0.0]]).astype(np.float32)
+    got, exact = _axis2(hx, hy), _axis2_exact(hx, hy)
+    d = (got - exact) & 0xFFFF
+    assert np.minimum(d, 65536 - d).max() <= 1, (got, exact)
+    assert got[-1] == 0 and got[-2] == 0
