@@ -172,10 +172,10 @@ class Batch:
         _lib.call("xy_batch_forms", self._h, ctypes.c_void_p(out.ctypes.data))
         return out
 
-    def autotune(self, sweeps=3, n_or=5, use_cache=True, pt_every=1):
+    def autotune(self, sweeps=3, n_or=5, use_cache=True, pt_every=1, replay=True):
         """Times the fixed-point configurations on this batch and keeps the fastest."""
         from .autotune import autotune
-        return autotune(self, sweeps=sweeps, n_or=n_or, use_cache=use_cache, pt_every=pt_every)
+        return autotune(self, sweeps=sweeps, n_or=n_or, use_cache=use_cache, pt_every=pt_every, replay=replay)
 
     def kernel_timing(self, enable=True):
         _lib.call("xy_kernel_timing", self._h, int(bool(enable)))

@@ -4,9 +4,13 @@ The candidates are the (cos, sin) form (hardware sine/cosine, 2048-entry
 LDS table, two-level LDS table), which every sample uses, times, for batches
 with workgroup-form samples, the storage form (unit vectors in LDS where a
 replica fits, or angles); then, for phase-form samples, the number of stream
-groups (1 to 3), which changes only how the colour-phase launches overlap.  Each candidate is timed on the live batch
-with HIP events (``xy_kernel_timing``).  Trial sweeps run without tempering or
-records, and the spins, permutations and sweep counter are restored
+groups (1 to 3), which changes only how the colour-phase launches overlap.
+Each candidate is timed on the live batch with HIP events
+(``xy_kernel_timing``); a group count is timed both by direct launches and by
+the replay of a captured HIP graph of its sweeps (how far the groups'
+launches overlap differs between the two), and keeps the better of the two.
+The form trials run without tempering or records, the group trials temper as
+the run does; the spins, permutations and sweep counter are restored
 afterwards, so tuning does not change the trajectory's inputs.  The choice is
 cached in a JSON file keyed by the GPU architecture and the batch shape (the
 multiset of graph sizes and the number of temperatures).
@@ -50,11 +54,30 @@ def _time(batch, sweeps, n_or, saved, pt_every=0):
     return ms / max(n, 1)
 
 
-def autotune(batch, sweeps=3, n_or=5, use_cache=True, pt_every=1):
+def _time_replay(batch, sweeps, n_or, saved, pt_every=0):
+    """ms per sweep of one replay of a HIP graph of `sweeps` sweeps (captured
+    and run once first)."""
+    kw = dict(n_or=n_or, pt_every=pt_every, meas_every=0)
+    batch.use_graph(sweeps)
+    batch.sweep(sweeps, **kw)                                      # capture, run once
+    batch.kernel_timing(True)
+    batch.sweep(sweeps, **kw)                                      # one replay
+    ms, n = batch.kernel_time()
+    batch.kernel_timing(False)
+    batch.use_graph(0)
+    batch.set_state(*saved)
+    return ms / max(n, 1)
+
+
+def autotune(batch, sweeps=3, n_or=5, use_cache=True, pt_every=1, replay=True):
     """Picks and applies the fastest (trig, allow_unit) and stream-group count;
     returns a report dict.  The stream-group trials temper every pt_every
     sweeps, as the run will (their swaps add to the batch's PT counters; the
-    state, labels and sweep counter are restored)."""
+    state, labels and sweep counter are restored); with replay, each count
+    is also timed by HIP-graph replay and scored by the faster of the two
+    launch modes (the report names the faster mode per count; a batch on the
+    null stream, which cannot be captured, is timed by direct launches only).
+    The batch is left with direct launches (use_graph(0))."""
     if batch.precision != "fix16":
         return {"tuned": False, "reason": "fp64 batch"}
     forms = batch.forms()
@@ -107,13 +130,18 @@ def autotune(batch, sweeps=3, n_or=5, use_cache=True, pt_every=1):
         # groups' phases; the caller's stream plus three others fill the four
         # hardware queues a process gets by default: one to three groups, the
         # fastest, and the fewer groups on a tie within 0.5%)
-        st = {}
+        st, mode = {}, {}
+        n_rep = min(n_sw_groups, 128)          # the replayed graph: at most 128 sweeps of launches
+        replay = replay and bool(batch._s().value)   # graph capture needs a stream other than the null one
         for n in range(1, min(3, n_phase) + 1):
             batch.set_phase_streams(n)
-            st[n] = min(_time(batch, n_sw_groups, n_or, saved, pt_every) for _ in range(2))
+            d = min(_time(batch, n_sw_groups, n_or, saved, pt_every) for _ in range(2))
+            r = min(_time_replay(batch, n_rep, n_or, saved, pt_every) for _ in range(2)) if replay else float("inf")
+            st[n], mode[n] = (r, "replay") if r < d else (d, "direct")
         fastest = min(st.values())
         n_best = min(n for n, v in st.items() if v <= 1.005 * fastest)
         rep["phase_streams_ms_per_sweep"] = {str(n): round(v, 4) for n, v in st.items()}
+        rep["phase_streams_launch"] = {str(n): m for n, m in mode.items()}
         entry["phase_streams_ms_per_sweep"] = rep["phase_streams_ms_per_sweep"]
     batch.set_phase_streams(n_best)
     rep["phase_streams"] = n_best

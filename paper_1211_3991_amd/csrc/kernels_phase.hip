@@ -120,7 +120,8 @@ __device__ __forceinline__ void load_words(char *Ab, const PhaseLanes &pl, const
 template <typename Idx, bool kLast, int kTrig, bool kMetro>
 __device__ __forceinline__ void update_unit(const DevBatch &b, const PhaseLanes &pl, const float2 *tab, float *esum,
                                             int colour, int sub, int max_blocks, uint32_t sweep, const int4 &ua,
-                                            const int4 &ub, const UnitPtrs &p, const int *jj, const uint2 *vv)
+                                            const int4 &ub, const UnitPtrs &p, const int *jj, const uint2 *vv,
+                                            const uint2 me)
 {
     const int R = pl.R, Lq = pl.Lq, S = pl.S, q = pl.q, i = p.i;
     // the unit is the workgroup's: its fields are uniform, and reading them
@@ -131,6 +132,7 @@ __device__ __forceinline__ void update_unit(const DevBatch &b, const PhaseLanes 
     const int bx = __builtin_amdgcn_readfirstlane(ub.z), uw = __builtin_amdgcn_readfirstlane(ub.w);
     const int kmin = uw & 255, kmax = (uw >> 8) & 255;
     const SampleDesc &d = b.desc[s];
+    const uint32_t seed_lo = d.seed_lo, seed_hi = d.seed_hi;   // the Philox key (scalar loads, with the unit's)
     // accept_factor of the inverse temperatures at the thread's four slots
     const float4 fq = *reinterpret_cast<const float4 *>(b.fac_slot + s * R + 4 * q);
     const float factor[4] = {fq.x, fq.y, fq.z, fq.w};
@@ -162,26 +164,34 @@ __device__ __forceinline__ void update_unit(const DevBatch &b, const PhaseLanes 
         else if (k < kmax && jj[k] != i) add(vv[k], jj[k], false);
     }
     // rows past the eighth, eight at a time: the indices of a batch, then its
-    // neighbour words, all in flight before the first use (a lane reads only
-    // the rows below its own degree, which its chunk holds; the batch count
-    // kmax is uniform)
+    // neighbour words, all in flight before the first use (the batch count
+    // kmax is uniform).  Every load is unconditional, so that the wait counts
+    // stay exact: a row at or past the lane's degree reads row dg instead,
+    // which lies in the lane's chunk, the chunk after it or the pool's
+    // trailing padding rows, and its gather reads the site's own word; only
+    // the additions are masked.
     for (int k0 = 8; k0 < kmax; k0 += 8) {
         int j2[8];
         uint2 v2[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-            j2[k] = k0 + k < dg ? (int)*reinterpret_cast<const Idx *>(p.colb + (k0 + k) * 64 * (int)sizeof(Idx)) : i;
+        for (int k = 0; k < 8; ++k) {
+            const int jr = (int)*reinterpret_cast<const Idx *>(p.colb + min(k0 + k, dg) * 64 * (int)sizeof(Idx));
+            j2[k] = k0 + k < dg ? jr : i;
+        }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v2[k] = k0 + k < dg ? angle_word(p.Ab, pl, j2[k]) : make_uint2(0u, 0u);
+        for (int k = 0; k < 8; ++k) v2[k] = angle_word(p.Ab, pl, j2[k]);
+        // (empty volatile asm on the words: the compiler may not sink a load
+        // into the masked addition that alone uses it, where it would wait at once)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) asm volatile("" : "+v"(v2[k].x), "+v"(v2[k].y));
 #pragma unroll
         for (int k = 0; k < 8; ++k)
             if (k0 + k < dg) add(v2[k], j2[k], false);
     }
     // the key is the sample's seed, the same in every lane (s is uniform)
     const U4 w = philox4x32_10_uniform_key(
-        {(uint32_t)i, sweep, (uint32_t)(4 * q), tag(kMetro ? kMet : kOR, (uint32_t)sub)}, d.seed_lo, d.seed_hi);
+        {(uint32_t)i, sweep, (uint32_t)(4 * q), tag(kMetro ? kMet : kOR, (uint32_t)sub)}, seed_lo, seed_hi);
     const uint32_t words[4] = {w.x, w.y, w.z, w.w};
-    const uint2 me = angle_word(p.Ab, pl, i);
     // the angles in the low 16 bits (higher bits are not part of them: the
     // (cos, sin) forms and the packing below ignore them)
     const uint32_t cur_th[4] = {me.x, me.x >> 16, me.y, me.y >> 16};
@@ -236,6 +246,9 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
     int jj[8];
     uint2 vv[8];
     load_rows<Idx>(p.colb, jj);
+    // the site's own word (no other thread writes it during the phase), in
+    // flight with the rows
+    const uint2 me = angle_word(p.Ab, pl, p.i);
     load_words(p.Ab, pl, jj, vv);
     // the (cos, sin) table of a table form, while the gathers are in flight
     if constexpr (Trig<kTrig>::kBytes > 0) {
@@ -243,7 +256,7 @@ __global__ __launch_bounds__(kPhaseBlock) void k_fix16_phase(DevBatch b, const i
         __syncthreads();
     }
     update_unit<Idx, kLast, kTrig, kMetro>(b, pl, tab, esum, colour, sub, max_blocks, b.ctl[grp].sweep, ua, ub, p, jj,
-                                          vv);
+                                           vv, me);
 }
 
 }  // namespace
