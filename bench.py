@@ -73,10 +73,11 @@ def kernel_source_digest():
 
 
 def time_gpu(wl, precision, steps, warmup, graphs, torch, xy, n_or=None, form=None, phase_streams=0, replay=True,
-             direct=True):
+             direct=True, phase_slices=1):
     """Times `steps` sweeps (fix16: autotunes first, or takes `form` =
     (trig, allow_unit) from an earlier tuning; phase_streams > 0 then fixes
-    the stream-group count of the phase-form samples).
+    the stream count of the phase-form sample groups, and phase_slices the
+    number of group slices swept one after the other).
 
     The timed window of `steps` sweeps is placed so that it ends on a
     measurement sweep (it starts at a sweep index congruent to -steps modulo
@@ -100,7 +101,7 @@ def time_gpu(wl, precision, steps, warmup, graphs, torch, xy, n_or=None, form=No
         else:
             b.set_fix16_form(trig=form[0], allow_unit=form[1])
         if phase_streams:
-            b.set_phase_streams(phase_streams)
+            b.set_phase_streams(phase_streams, phase_slices)
     kw = dict(n_or=n_or, pt_every=wl.pt_every, meas_every=wl.meas_every)
     _, acc0, tries0 = b.counters()                             # the tuner's trial swaps, left out of the rate
     b.sweep(w0, **kw)                                          # direct warm-up, ends at the window's phase
@@ -143,8 +144,10 @@ def time_gpu(wl, precision, steps, warmup, graphs, torch, xy, n_or=None, form=No
     nrec, acc, tries = b.counters()
     acc, tries = acc - acc0, tries - tries0
     n_groups = b.phase_streams() if precision == "fix16" else 1
+    n_slices = b.phase_slices() if precision == "fix16" else 1
     b.close()
     out.update(window=[w0 + (steps + phase if replay else 0), steps], records=nrec, phase_streams=n_groups,
+               phase_slices=n_slices,
                pt_rate=float(acc.sum()) / max(float(tries.sum()), 1.0), autotune=tune)
     return out
 
@@ -201,7 +204,7 @@ def _pmc_rows(path):
     return sorted(rows, key=lambda r: int(r["Dispatch_Id"]))
 
 
-def write_traffic(wl, paths, argv, phase_streams):
+def write_traffic(wl, paths, argv, phase_streams, phase_slices=1):
     """HBM bytes per sweep of the dominant fix16 kernel from rocprofv3 counter
     CSVs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch, summed over a sweep's
     dispatches), each scaled by what the same counter reads for a plain 512 MiB
@@ -245,7 +248,8 @@ def write_traffic(wl, paths, argv, phase_streams):
            "dispatches_per_sweep": round(n_per_sweep, 2), "fetch_kib_per_sweep": round(f_kib, 1),
            "write_kib_per_sweep": round(w_kib, 1), "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
            "bytes_per_sweep": int(bytes_sweep), "bytes_per_update": round(bytes_sweep / upd, 4),
-           "updates_per_sweep": upd, "phase_streams": phase_streams, "command": f"python bench.py {argv}"}
+           "updates_per_sweep": upd, "phase_streams": phase_streams,
+           "phase_slices": phase_slices, "command": f"python bench.py {argv}"}
     # further counter CSVs (SQ_*, TCC_*, TCP_*): every counter they hold,
     # summed over a sweep's dispatches of the same kernels
     cnt = {}
@@ -380,8 +384,10 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (HBM counter calibration)")
     ap.add_argument("--phase-streams", type=int, default=0,
-                    help="stream groups of the phase-form samples (default: the autotuner's choice); with "
+                    help="streams of the phase-form sample groups (default: the autotuner's choice); with "
                          "--traffic-from, the count the counters were taken with")
+    ap.add_argument("--phase-slices", type=int, default=1,
+                    help="with --phase-streams: slices of groups swept one after the other (default 1)")
     ap.add_argument("--traffic-from", nargs="+", metavar="CSV",
                     help="no GPU work: FETCH_CSV WRITE_CSV CAL_FETCH_CSV CAL_WRITE_CSV [COUNTER_CSV ...]: turn "
                          "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter CSVs of this workload and of "
@@ -393,7 +399,8 @@ def main():
             ap.error("--traffic-from takes at least 4 CSV paths")
         if not args.phase_streams:
             ap.error("--traffic-from needs --phase-streams: the group count the counters were taken with")
-        write_traffic(workloads.ALL[args.workload](), args.traffic_from, " ".join(sys.argv[1:]), args.phase_streams)
+        write_traffic(workloads.ALL[args.workload](), args.traffic_from, " ".join(sys.argv[1:]), args.phase_streams,
+                      args.phase_slices)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the samples are independent and a multi-GPU "
@@ -432,7 +439,7 @@ def main():
             os.environ["XY_FIX16_PHASE_MIN"] = str(threshold["phase_min"])
         print(f"# phase-form threshold: {threshold}", file=sys.stderr, flush=True)
     main_run = time_gpu(wl, args.precision, args.steps, args.warmup, graphs, torch, xy,
-                        phase_streams=args.phase_streams, replay=not args.direct)
+                        phase_streams=args.phase_streams, replay=not args.direct, phase_slices=args.phase_slices)
     value = upd_per_sweep * args.steps / (main_run["ms"] * 1e6)
     print(f"# {args.precision}: {main_run['ms'] / args.steps:.3f} ms/sweep ({main_run['launch']}), "
           f"{value:.1f} updates/ns; direct launches {main_run['direct_ms'] / args.steps:.3f} ms/sweep",
@@ -449,7 +456,8 @@ def main():
             tr = json.load(fh)
         # the counters hold for this source and for the stream-group count they were taken with
         if (tr.get("kernel_digest") == kernel_source_digest() and tr.get("workload") == wl.name
-                and tr.get("phase_streams") == main_run["phase_streams"]):
+                and tr.get("phase_streams") == main_run["phase_streams"]
+                and tr.get("phase_slices", 1) == main_run["phase_slices"]):
             traffic = tr["bytes_per_sweep"]
         else:
             tr = {}
@@ -549,7 +557,8 @@ def main():
         tuned = main_run["autotune"]
         form = (tuned["trig"], tuned["allow_unit"]) if tuned and "trig" in tuned else None
         met = time_gpu(wl, args.precision, args.split_steps, 2, graphs, torch, xy, n_or=0, form=form,
-                       phase_streams=main_run["phase_streams"], replay=not args.direct, direct=False)
+                       phase_streams=main_run["phase_streams"], replay=not args.direct, direct=False,
+                       phase_slices=main_run["phase_slices"])
         n_upd = upd_per_sweep // (1 + wl.n_or)
         or_ms = k_ms - met["kernel_ms"]
         split = {"met_only": round(n_upd / (met["kernel_ms"] * 1e6), 2),
@@ -583,6 +592,7 @@ def main():
                    "state": "uint16 angles, FP32 fields, FP64 accumulators" if args.precision == "fix16"
                    else "FP64 unit vectors", "parallelism": "samples x temperatures on one GPU",
                    "launch": main_run["launch"], "timed_window": main_run["window"],
+                   "sample_groups": {"streams": main_run["phase_streams"], "slices": main_run["phase_slices"]},
                    "records_in_window": -(-args.steps // wl.meas_every) if wl.meas_every else 0},
         "direct_launch": {"ms_per_step": round(main_run["direct_ms"] / args.steps, 4),
                           "value": round(upd_per_sweep * args.steps / (main_run["direct_ms"] * 1e6), 2)},

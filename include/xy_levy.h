@@ -246,6 +246,23 @@ xy_status xy_kernel_time(xy_batch *b, double *ms_total, int *n_timed);
 xy_status xy_batch_set_phase_streams(xy_batch *b, int n_streams, void *stream);
 xy_status xy_batch_phase_streams(const xy_batch *b, int *n_streams);
 
+/* Stream groups in slices (fix16 batches whose samples are all in the phase
+ * form; used by the autotuner): n_streams * n_slices groups of about equal
+ * work, group g on stream g % n_streams; within an xy_sweep call the slices
+ * run one after the other, each for all the call's sweeps (its groups
+ * concurrently on the n_streams streams), so that only one slice's samples
+ * are swept at a time: a smaller working set for the memory-side caches.
+ * Samples are independent (each group has its own tempering, records and
+ * sweep counter), so the trajectory does not depend on the choice.
+ * xy_batch_set_phase_streams(b, n, s) is n streams in one slice.  Batches
+ * with workgroup-form samples keep one slice.  Synchronises like
+ * xy_batch_set_phase_streams.  XY_EINVAL unless 1 <= n_streams <= 4,
+ * n_slices >= 1 and n_streams * n_slices <= 8; the slice count is lowered
+ * where the phase samples are fewer than the groups.
+ * xy_batch_phase_groups returns the configuration in effect. */
+xy_status xy_batch_set_phase_groups(xy_batch *b, int n_streams, int n_slices, void *stream);
+xy_status xy_batch_phase_groups(const xy_batch *b, int *n_streams, int *n_slices);
+
 /* Fixed-point sweep configuration (fix16 batches; used by the autotuner).
  *   trig        : (cos, sin) of a 16-bit angle, for every sample: 0 two-level
  *                 LDS table, 1 2048-entry LDS table with a small-angle

@@ -156,15 +156,21 @@ class Batch:
         _lib.call("xy_batch_set_fix16_form", self._h, int(trig), int(bool(allow_unit)), int(bool(force_global)),
                   self._s())
 
-    def set_phase_streams(self, n):
-        """Number of stream groups of the phase-form samples (1..4); the
-        trajectory does not depend on it."""
-        _lib.call("xy_batch_set_phase_streams", self._h, int(n), self._s())
+    def set_phase_streams(self, n, slices=1):
+        """Stream groups of the phase-form samples: n streams (1..4) times
+        `slices` groups per stream, the slices swept one after the other
+        (n * slices <= 8); the trajectory does not depend on it."""
+        _lib.call("xy_batch_set_phase_groups", self._h, int(n), int(slices), self._s())
 
     def phase_streams(self):
         n = ctypes.c_int()
         _lib.call("xy_batch_phase_streams", self._h, ctypes.byref(n))
         return n.value
+
+    def phase_slices(self):
+        n, sl = ctypes.c_int(), ctypes.c_int()
+        _lib.call("xy_batch_phase_groups", self._h, ctypes.byref(n), ctypes.byref(sl))
+        return sl.value
 
     def forms(self):
         """Storage form per sample: 1 site-major phase form, 0 workgroup per replica."""

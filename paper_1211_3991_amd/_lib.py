@@ -18,7 +18,7 @@ STATUS_NAMES = {0: "XY_OK", -1: "XY_EINVAL", -2: "XY_ENOMEM", -3: "XY_EHIP", -4:
 
 EXPORTS = ("xy_graph_levy", "xy_graph_levy_free", "xy_graph_from_edges", "xy_graph_info", "xy_graph_export", "xy_graph_free",
            "xy_batch_sizes", "xy_batch_init", "xy_sweep", "xy_measure", "xy_pt_energies", "xy_pt_swap", "xy_get_state",
-           "xy_set_state", "xy_get_counters", "xy_decision_log", "xy_batch_use_graph", "xy_batch_set_fix16_form", "xy_batch_set_phase_streams", "xy_batch_phase_streams", "xy_batch_forms", "xy_walk_bytes", "xy_random_walk", "xy_random_walk_noalloc", "xy_kernel_timing",
+           "xy_set_state", "xy_get_counters", "xy_decision_log", "xy_batch_use_graph", "xy_batch_set_fix16_form", "xy_batch_set_phase_streams", "xy_batch_phase_streams", "xy_batch_set_phase_groups", "xy_batch_phase_groups", "xy_batch_forms", "xy_walk_bytes", "xy_random_walk", "xy_random_walk_noalloc", "xy_kernel_timing",
            "xy_kernel_time", "xy_last_error", "xy_batch_free")
 
 
@@ -69,6 +69,8 @@ _sigs = {
     "xy_batch_forms": ([_vp, _vp], _i32),
     "xy_batch_set_phase_streams": ([_vp, _i32, _vp], _i32),
     "xy_batch_phase_streams": ([_vp, _vp], _i32),
+    "xy_batch_set_phase_groups": ([_vp, _i32, _i32, _vp], _i32),
+    "xy_batch_phase_groups": ([_vp, _vp, _vp], _i32),
     "xy_walk_bytes": ([_vp, _i32, ctypes.POINTER(ctypes.c_size_t)], _i32),
     "xy_random_walk": ([_vp, _i32, _i32, _i32, _vp, _i32, _vp, ctypes.c_size_t, _vp, _vp,
                         ctypes.POINTER(ctypes.c_float)], _i32),

@@ -4,7 +4,10 @@ The candidates are the (cos, sin) form (hardware sine/cosine, 2048-entry
 LDS table, two-level LDS table), which every sample uses, times, for batches
 with workgroup-form samples, the storage form (unit vectors in LDS where a
 replica fits, or angles); then, for phase-form samples, the number of stream
-groups (1 to 3), which changes only how the colour-phase launches overlap.
+groups (1 to 3 streams, and, when every sample is in the phase form, two or
+three streams with two or four groups each swept one after the other), which
+changes only how the colour-phase launches overlap and how much state is
+swept at a time.
 Each candidate is timed on the live batch with HIP events
 (``xy_kernel_timing``); a group count is timed both by direct launches and by
 the replay of a captured HIP graph of its sweeps (how far the groups'
@@ -89,9 +92,9 @@ def autotune(batch, sweeps=3, n_or=5, use_cache=True, pt_every=1, replay=True):
         c = cache[key]
         if "trig" in c:
             batch.set_fix16_form(c["trig"], c["allow_unit"])
-        batch.set_phase_streams(c["phase_streams"])
+        batch.set_phase_streams(c["phase_streams"], c.get("phase_slices", 1))
         return {"tuned": True, "cached": True, "trig": c.get("trig"), "allow_unit": c.get("allow_unit"),
-                "phase_streams": c["phase_streams"], "key": key}
+                "phase_streams": c["phase_streams"], "phase_slices": c.get("phase_slices", 1), "key": key}
     saved = batch.get_state()
     rep = {"tuned": True, "cached": False, "key": key}
     entry = {}
@@ -123,29 +126,36 @@ def autotune(batch, sweeps=3, n_or=5, use_cache=True, pt_every=1, replay=True):
         batch.set_fix16_form(trig, 1)
         rep.update(trig=trig, allow_unit=1, trig_ms_per_sweep={f"trig{t}": round(v, 4) for t, v in times.items()})
         entry.update(trig=trig, allow_unit=1, trig_ms_per_sweep=rep["trig_ms_per_sweep"])
-    n_best = batch.phase_streams()
+    best = (batch.phase_streams(), batch.phase_slices())
     if n_phase >= 2:
         # (trials temper as the run does: each group runs its own energies and
         # tempering after its colour phases, and those tails overlap the other
         # groups' phases; the caller's stream plus three others fill the four
-        # hardware queues a process gets by default: one to three groups, the
-        # fastest, and the fewer groups on a tie within 0.5%)
+        # hardware queues a process gets by default: one to three streams.
+        # With every sample in the phase form, also two or three streams in
+        # slices of groups swept one after the other, which shrinks the state
+        # swept at a time for the memory-side caches.  The fastest, the fewer
+        # groups on a tie within 0.5%.)
+        cands = [(n, 1) for n in range(1, min(3, n_phase) + 1)]
+        if forms.all():
+            cands += [(n, k) for n, k in ((2, 2), (3, 2), (2, 4)) if n * k <= n_phase]
         st, mode = {}, {}
         n_rep = min(n_sw_groups, 128)          # the replayed graph: at most 128 sweeps of launches
         replay = replay and bool(batch._s().value)   # graph capture needs a stream other than the null one
-        for n in range(1, min(3, n_phase) + 1):
-            batch.set_phase_streams(n)
+        for c in cands:
+            batch.set_phase_streams(*c)
             d = min(_time(batch, n_sw_groups, n_or, saved, pt_every) for _ in range(2))
             r = min(_time_replay(batch, n_rep, n_or, saved, pt_every) for _ in range(2)) if replay else float("inf")
-            st[n], mode[n] = (r, "replay") if r < d else (d, "direct")
+            st[c], mode[c] = (r, "replay") if r < d else (d, "direct")
         fastest = min(st.values())
-        n_best = min(n for n, v in st.items() if v <= 1.005 * fastest)
-        rep["phase_streams_ms_per_sweep"] = {str(n): round(v, 4) for n, v in st.items()}
-        rep["phase_streams_launch"] = {str(n): m for n, m in mode.items()}
+        best = next(c for c in cands if st[c] <= 1.005 * fastest)
+        label = {c: (str(c[0]) if c[1] == 1 else f"{c[0]}x{c[1]}") for c in cands}
+        rep["phase_streams_ms_per_sweep"] = {label[c]: round(v, 4) for c, v in st.items()}
+        rep["phase_streams_launch"] = {label[c]: m for c, m in mode.items()}
         entry["phase_streams_ms_per_sweep"] = rep["phase_streams_ms_per_sweep"]
-    batch.set_phase_streams(n_best)
-    rep["phase_streams"] = n_best
-    entry["phase_streams"] = n_best
+    batch.set_phase_streams(*best)
+    rep["phase_streams"], rep["phase_slices"] = best
+    entry["phase_streams"], entry["phase_slices"] = best
     if use_cache:
         cache[key] = entry
         try:

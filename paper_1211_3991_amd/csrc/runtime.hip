@@ -45,6 +45,10 @@ struct xy_batch {
     std::vector<hipEvent_t> ev_join;          // per auxiliary stream
     std::vector<int> phase_bounds;            // [colour][group + 1]: first unit of each group
     std::vector<int> group_first;             // [group + 1]: first phase sample of each group
+    // independent groups only: n_slices groups per stream, run one after the
+    // other (group g on stream g % n_streams, in slice g / n_streams), so that
+    // only one slice's samples are swept at a time
+    int n_slices = 1;
     std::vector<int32_t> unit_k;              // phase index of each work unit, in d_units order
     // every sample in the phase form: each group also runs its own energies,
     // tempering and records with its own control block b.ctl[g], so the
@@ -89,11 +93,12 @@ xy_status hip_err(hipError_t e, const char *where)
     return set_error(XY_EHIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-// Splits the phase samples into n_streams contiguous groups of about equal
-// work units, group 0 on the caller's stream and the others on auxiliary
-// streams created here (the previous ones are released); no work may be in
-// flight on them.
-hipError_t setup_phase_groups(xy_batch *b, int n_streams)
+// Splits the phase samples into n_streams x n_slices contiguous groups of
+// about equal work units, group g on stream g % n_streams (stream 0 the
+// caller's, the others auxiliary streams created here; the previous ones are
+// released); no work may be in flight on them.  Slices apply to independent
+// groups only (every sample in the phase form); otherwise n_slices is 1.
+hipError_t setup_phase_groups(xy_batch *b, int n_streams, int n_slices)
 {
     if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     for (hipEvent_t ev : b->ev_join) (void)hipEventDestroy(ev);
@@ -103,32 +108,35 @@ hipError_t setup_phase_groups(xy_batch *b, int n_streams)
     b->aux.clear();
     const int n_ph = b->n_phase, Q = (int)b->phase_units.size();
     n_streams = std::max(1, std::min({n_streams, kMaxPhaseStreams, std::max(n_ph, 1)}));
-    std::vector<int> first(n_streams + 1, n_ph);   // group g: phase samples [first[g], first[g+1])
+    n_slices = (n_ph == b->G) ? std::max(1, std::min(n_slices, std::min(kMaxPhaseGroups, n_ph) / n_streams)) : 1;
+    const int n_groups = n_streams * n_slices;
+    std::vector<int> first(n_groups + 1, n_ph);    // group g: phase samples [first[g], first[g+1])
     first[0] = 0;
     std::vector<size_t> per(std::max(n_ph, 1), 0);
     for (int32_t k : b->unit_k) ++per[k];
     size_t total = 0, acc = 0;
     for (size_t v : per) total += v;
     int g = 1;
-    for (int k = 0; k < n_ph && g < n_streams; ++k) {
+    for (int k = 0; k < n_ph && g < n_groups; ++k) {
         acc += per[k];
         // close group g-1 after sample k once it holds its share, leaving a
         // sample for each later group
-        if (acc * n_streams >= total * g && n_ph - (k + 1) >= n_streams - g) first[g++] = k + 1;
+        if (acc * n_groups >= total * g && n_ph - (k + 1) >= n_groups - g) first[g++] = k + 1;
     }
-    for (; g < n_streams; ++g) first[g] = std::min(n_ph, first[g - 1] + 1);
-    b->phase_bounds.assign((size_t)Q * (n_streams + 1), 0);
+    for (; g < n_groups; ++g) first[g] = std::min(n_ph, first[g - 1] + 1);
+    b->phase_bounds.assign((size_t)Q * (n_groups + 1), 0);
     for (int c = 0; c < Q; ++c) {
-        int *bd = b->phase_bounds.data() + (size_t)c * (n_streams + 1);
+        int *bd = b->phase_bounds.data() + (size_t)c * (n_groups + 1);
         const int32_t *uk = b->unit_k.data() + b->phase_unit_off[c] / 2;
-        for (int h = 0; h <= n_streams; ++h) {
+        for (int h = 0; h <= n_groups; ++h) {
             int n = 0;   // units of colour c whose sample precedes group h
             for (int a = 0; a < b->phase_units[c]; ++a) n += uk[a] < first[h];
             bd[h] = n;
         }
     }
     b->group_first = first;
-    b->indep = n_streams > 1 && n_ph == b->G;
+    b->n_slices = n_slices;
+    b->indep = n_groups > 1 && n_ph == b->G;
     hipError_t e = hipSuccess;
     if (n_streams > 1) {
         e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
@@ -245,7 +253,7 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
     WorkLayout &wl = p.wl;
     const size_t GR = (size_t)G * R;
     off = 0;
-    wl.ctl = off;       off = align_up(off + sizeof(Ctl) * kMaxPhaseStreams, 256);
+    wl.ctl = off;       off = align_up(off + sizeof(Ctl) * kMaxPhaseGroups, 256);
     wl.beta = off;      off = align_up(off + 8 * GR, 256);
     wl.slot_of_T = off; off = align_up(off + 4 * GR, 256);
     wl.T_of_slot = off; off = align_up(off + 4 * GR, 256);
@@ -534,9 +542,10 @@ extern "C" xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int
             for (size_t a = 0; a < b->unit_k.size(); ++a) b->unit_k[a] = units[2 * a + 1].y;
             b->n_phase = (int)phase.size();
             if (const char *env = std::getenv("XY_PHASE_SERPENTINE")) b->serpentine = std::atoi(env) != 0;
-            int n_streams = 2;   // XY_PHASE_STREAMS=1..4 overrides
+            int n_streams = 2, n_slices = 1;   // XY_PHASE_STREAMS=1..4 and XY_PHASE_SLICES override
             if (const char *env = std::getenv("XY_PHASE_STREAMS")) n_streams = std::atoi(env);
-            const hipError_t e = setup_phase_groups(b, n_streams);
+            if (const char *env = std::getenv("XY_PHASE_SLICES")) n_slices = std::atoi(env);
+            const hipError_t e = setup_phase_groups(b, n_streams, n_slices);
             if (e != hipSuccess) {
                 xy_batch_free(b);
                 return hip_err(e, "xy_batch_init: phase streams");
@@ -643,6 +652,7 @@ hipError_t next_events(xy_batch *b, hipEvent_t *start, hipEvent_t *stop)
 // Forks the auxiliary streams of the phase form from s, and joins them back.
 hipError_t fork_groups(xy_batch *b, hipStream_t s)
 {
+    if (b->aux.empty()) return hipSuccess;   // one stream (groups in slices only): nothing to fork
     hipError_t e = hipEventRecord(b->ev_fork, s);
     for (size_t g = 0; g < b->aux.size() && e == hipSuccess; ++g) e = hipStreamWaitEvent(b->aux[g], b->ev_fork, 0);
     return e;
@@ -658,9 +668,10 @@ hipError_t join_groups(xy_batch *b, hipStream_t s)
     return e;
 }
 
-// Enqueues one sweep with the given flags.  With independent groups the
-// caller has forked them (fork_groups) and joins them after its last sweep.
-hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream_t s)
+// Enqueues one sweep with the given flags.  With independent groups: one
+// sweep of the groups of slice `slice`; the caller has forked the streams
+// (fork_groups) and joins them after its last sweep.
+hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream_t s, int slice = 0)
 {
     hipError_t e = hipSuccess;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -672,6 +683,7 @@ hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream
         b->timed_stream = s;
     }
     const int n_st = 1 + (int)b->aux.size();
+    const int n_gr = n_st * (b->indep ? b->n_slices : 1);   // groups: the stride of phase_bounds
     if (b->precision == XY_FP64) {
         // the energies for tempering are summed in the last sub-sweep, except
         // on a measurement sweep, whose observation pass sums them anyway
@@ -685,19 +697,23 @@ hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream
         if (e == hipSuccess && fuse)
             e = launch_fp64_energy_final(b->dev, b->max_class.data(), b->Qmax, b->phase_stride, s);
     } else if (b->indep) {
-        // each group: its colour phases, then its energies, tempering,
-        // records and sweep counter, all on its own stream
+        // each group of the slice: its colour phases, then its energies,
+        // tempering, records and sweep counter, all on its own stream
+        const int g0 = slice * n_st;
         for (int sub = 0; sub <= n_or && e == hipSuccess; ++sub)
             for (int c = 0; c < (int)b->phase_units.size() && e == hipSuccess; ++c) {
-                const int *bd = b->phase_bounds.data() + (size_t)c * (n_st + 1);
+                const int *bd = b->phase_bounds.data() + (size_t)c * (n_gr + 1);
                 const int4 *u = b->d_units + b->phase_unit_off[c];
                 const int rev = b->serpentine ? (sub * (int)b->phase_units.size() + c) & 1 : 0;
-                for (int g = 0; g < n_st && e == hipSuccess; ++g)
+                for (int h = 0; h < n_st && e == hipSuccess; ++h) {
+                    const int g = g0 + h;
                     e = launch_fix16_phase(b->dev, u + 2 * (size_t)bd[g], c, sub, sub == n_or, bd[g + 1] - bd[g],
-                                           b->phase_stride, g, rev, g == 0 ? s : b->aux[g - 1]);
+                                           b->phase_stride, g, rev, h == 0 ? s : b->aux[h - 1]);
+                }
             }
-        for (int g = 0; g < n_st && e == hipSuccess; ++g) {
-            hipStream_t st = g == 0 ? s : b->aux[g - 1];
+        for (int h = 0; h < n_st && e == hipSuccess; ++h) {
+            hipStream_t st = h == 0 ? s : b->aux[h - 1];
+            const int g = g0 + h;
             const int k0 = b->group_first[g], nk = b->group_first[g + 1] - k0;
             if (do_rec) e = launch_fix16_observe_sm(b->dev, b->d_phase, k0, nk, 1, st);
             if (e == hipSuccess && do_pt) e = launch_fix16_phase_energy(b->dev, b->d_phase, k0, nk, b->phase_stride, st);
@@ -715,7 +731,7 @@ hipError_t enqueue_sweep(xy_batch *b, int n_or, int do_pt, int do_rec, hipStream
         }
         for (int sub = 0; sub <= n_or && e == hipSuccess && b->n_phase > 0; ++sub)
             for (int c = 0; c < (int)b->phase_units.size() && e == hipSuccess; ++c) {
-                const int *bd = b->phase_bounds.data() + (size_t)c * (n_st + 1);
+                const int *bd = b->phase_bounds.data() + (size_t)c * (n_gr + 1);
                 const int4 *u = b->d_units + b->phase_unit_off[c];
                 const int rev = b->serpentine ? (sub * (int)b->phase_units.size() + c) & 1 : 0;
                 for (int g = 0; g < n_st && e == hipSuccess; ++g)
@@ -774,10 +790,16 @@ hipError_t run_direct(xy_batch *b, int n, int n_or, int pt_every, int meas_every
         e = fork_groups(b, s);
         if (e != hipSuccess) return e;
     }
-    for (int k = 0; k < n && e == hipSuccess; ++k) {
-        const uint32_t sw = b->host_sweep;
-        e = enqueue_sweep(b, n_or, flag_at(sw, pt_every), flag_at(sw, meas_every), s);
-        if (e == hipSuccess) b->host_sweep++;
+    // independent groups: the slices one after the other, each for all n sweeps
+    const uint32_t sw0 = b->host_sweep;
+    const int n_sl = b->indep ? b->n_slices : 1;
+    for (int sl = 0; sl < n_sl && e == hipSuccess; ++sl) {
+        b->host_sweep = sw0;
+        for (int k = 0; k < n && e == hipSuccess; ++k) {
+            const uint32_t sw = b->host_sweep;
+            e = enqueue_sweep(b, n_or, flag_at(sw, pt_every), flag_at(sw, meas_every), s, sl);
+            if (e == hipSuccess) b->host_sweep++;
+        }
     }
     if (b->indep) {
         const hipError_t e2 = join_groups(b, s);   // also after a failed launch: leave no stream forked
@@ -797,10 +819,13 @@ hipError_t capture_chunk(xy_batch *b, int n_or, int pt_every, int meas_every, ui
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        uint32_t sw = b->host_sweep;
         if (b->indep) e = fork_groups(b, s);
-        for (int k = 0; k < b->chunk && e == hipSuccess; ++k, ++sw)
-            e = enqueue_sweep(b, n_or, flag_at(sw, pt_every), flag_at(sw, meas_every), s);
+        const int n_sl = b->indep ? b->n_slices : 1;
+        for (int sl = 0; sl < n_sl && e == hipSuccess; ++sl) {
+            uint32_t sw = b->host_sweep;
+            for (int k = 0; k < b->chunk && e == hipSuccess; ++k, ++sw)
+                e = enqueue_sweep(b, n_or, flag_at(sw, pt_every), flag_at(sw, meas_every), s, sl);
+        }
         if (b->indep && e == hipSuccess) e = join_groups(b, s);
         const hipError_t e2 = hipStreamEndCapture(s, &graph);
         if (e == hipSuccess) e = e2;
@@ -1028,7 +1053,7 @@ extern "C" xy_status xy_set_state(xy_batch *b, const void *h_state, const int32_
             if (e == hipSuccess) e = hipMemcpyAsync(b->dev.T_of_slot, tos.data(), tos.size() * 4, hipMemcpyHostToDevice, s);
             if (e == hipSuccess) e = launch_slot_factors(b->dev, s);
         }
-        for (int g = 0; g < kMaxPhaseStreams && e == hipSuccess; ++g)
+        for (int g = 0; g < kMaxPhaseGroups && e == hipSuccess; ++g)
             e = hipMemcpyAsync(&b->dev.ctl[g].sweep, &sweep, 4, hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_err(e, "xy_set_state");
@@ -1104,21 +1129,37 @@ extern "C" xy_status xy_kernel_time(xy_batch *b, double *ms_total, int *n_timed)
     return XY_OK;
 }
 
-extern "C" xy_status xy_batch_set_phase_streams(xy_batch *b, int n_streams, void *stream)
+extern "C" xy_status xy_batch_set_phase_groups(xy_batch *b, int n_streams, int n_slices, void *stream)
 {
-    if (!b || n_streams < 1 || n_streams > kMaxPhaseStreams)
-        return set_error(XY_EINVAL, "xy_batch_set_phase_streams: n_streams must be in [1, 4]");
+    if (!b || n_streams < 1 || n_streams > kMaxPhaseStreams || n_slices < 1 || n_streams * n_slices > kMaxPhaseGroups)
+        return set_error(XY_EINVAL, "xy_batch_set_phase_groups: need 1 <= n_streams <= 4, n_slices >= 1 and "
+                                    "n_streams * n_slices <= 8");
     if (b->precision != XY_FIX16 || b->n_phase == 0) return XY_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipStreamSynchronize(s);
     for (size_t g = 0; g < b->aux.size() && e == hipSuccess; ++g) e = hipStreamSynchronize(b->aux[g]);
-    if (e == hipSuccess) e = setup_phase_groups(b, n_streams);
+    if (e == hipSuccess) e = setup_phase_groups(b, n_streams, n_slices);
     // every group's control block continues from group 0's (equal after a sweep call)
-    for (int g = 1; g < kMaxPhaseStreams && e == hipSuccess; ++g)
+    for (int g = 1; g < kMaxPhaseGroups && e == hipSuccess; ++g)
         e = hipMemcpyAsync(b->dev.ctl + g, b->dev.ctl, sizeof(Ctl), hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
-    return e == hipSuccess ? XY_OK : hip_err(e, "xy_batch_set_phase_streams");
+    return e == hipSuccess ? XY_OK : hip_err(e, "xy_batch_set_phase_groups");
+}
+
+extern "C" xy_status xy_batch_set_phase_streams(xy_batch *b, int n_streams, void *stream)
+{
+    if (!b || n_streams < 1 || n_streams > kMaxPhaseStreams)
+        return set_error(XY_EINVAL, "xy_batch_set_phase_streams: n_streams must be in [1, 4]");
+    return xy_batch_set_phase_groups(b, n_streams, 1, stream);
+}
+
+extern "C" xy_status xy_batch_phase_groups(const xy_batch *b, int *n_streams, int *n_slices)
+{
+    if (!b || !n_streams || !n_slices) return set_error(XY_EINVAL, "xy_batch_phase_groups: NULL argument");
+    *n_streams = 1 + (int)b->aux.size();
+    *n_slices = b->indep ? b->n_slices : 1;
+    return XY_OK;
 }
 
 extern "C" xy_status xy_batch_phase_streams(const xy_batch *b, int *n_streams)

@@ -84,7 +84,8 @@ struct xy_graph {
 namespace xy {
 
 constexpr int kMaxColours = 31;
-constexpr int kMaxPhaseStreams = 4;   // stream groups of the phase form, each with its own control block
+constexpr int kMaxPhaseStreams = 4;   // streams of the phase form's sample groups (the caller's and three more)
+constexpr int kMaxPhaseGroups = 8;    // sample groups of the phase form, each with its own control block
 constexpr int kMaxT = 256;
 
 xy_status set_error(xy_status code, const std::string &msg);

@@ -313,22 +313,24 @@ def test_graph_replay_equals_direct_launches():
 
 
 def test_autotune_phase_streams_restores_state(tmp_path, monkeypatch):
-    """Every sample in the phase form: the tuner times one to three stream
-    groups, applies the fastest (the fewer on a tie within 0.5%), and
-    restores the state."""
+    """Every sample in the phase form: the tuner times one to three streams
+    and two streams in two slices (four samples), applies the fastest (the
+    fewer groups on a tie within 0.5%), caches it, and restores the state."""
     monkeypatch.setenv("XY_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
     g = [xy.Graph.levy(128, 6, 3.5, s) for s in range(4)]
     b = xy.Batch(g, workloads.linear_ladder(1.0, 2.5, 8), precision="fix16", max_records=4)
     b.sweep(5, pt_every=1, meas_every=0)
     before = b.get_state()
     rep = b.autotune(sweeps=2)
-    assert rep["tuned"] and set(rep["phase_streams_ms_per_sweep"]) == {"1", "2", "3"}
-    assert b.phase_streams() == rep["phase_streams"]
+    assert rep["tuned"] and set(rep["phase_streams_ms_per_sweep"]) == {"1", "2", "3", "2x2"}
+    assert b.phase_streams() == rep["phase_streams"] and b.phase_slices() == rep["phase_slices"]
     after = b.get_state()
     assert after[2] == before[2] == 5 and np.array_equal(after[1], before[1])
     assert all(np.array_equal(x, y) for x, y in zip(after[0], before[0]))
-    again = xy.Batch(g, workloads.linear_ladder(1.0, 2.5, 8), precision="fix16", max_records=4).autotune()
+    again_b = xy.Batch(g, workloads.linear_ladder(1.0, 2.5, 8), precision="fix16", max_records=4)
+    again = again_b.autotune()
     assert again["cached"] and again["phase_streams"] == rep["phase_streams"]
+    assert again["phase_slices"] == rep["phase_slices"] == again_b.phase_slices()
     for bad in (0, 5):
         with pytest.raises(xy.XYError):
             b.set_phase_streams(bad)
@@ -434,9 +436,11 @@ def test_stream_groups_give_identical_trajectories(mixed, trig, monkeypatch):
     the same order with the same random words: states, temperature labels,
     records and tempering counters are identical.  With every sample in the
     phase form and two or more groups, each group runs its own energies,
-    tempering, records and sweep counter (once also replayed from a captured
-    HIP graph, once regrouped from two to four groups half way); in a batch
-    that also holds workgroup-form samples the groups join every sweep."""
+    tempering, records and sweep counter (also replayed from a captured HIP
+    graph, and regrouped half way), and the groups may run in slices one
+    after the other (two or three groups per stream); in a batch that also
+    holds workgroup-form samples the groups join every sweep and there is one
+    slice."""
     monkeypatch.setenv("XY_FIX16_TRIG", str(trig))
     graphs = [xy.Graph.levy(128, 6, 3.5, s) for s in range(5)]
     if mixed:
@@ -444,17 +448,22 @@ def test_stream_groups_give_identical_trajectories(mixed, trig, monkeypatch):
     G = len(graphs)
     T = workloads.linear_ladder(1.0, 2.5, 8)
     runs = []
-    for streams, chunk in (("1", 0), ("2", 0), ("3", 0), ("2", 4), ("2>4", 0)):
-        monkeypatch.setenv("XY_PHASE_STREAMS", streams[0])
+    # (streams, slices, graph chunk, regrouped half way to (streams, slices))
+    configs = ((1, 1, 0, None), (2, 1, 0, None), (3, 1, 0, None), (2, 1, 4, None), (2, 1, 0, (4, 1)),
+               (2, 2, 0, None), (1, 3, 0, None), (2, 2, 4, None), (1, 1, 0, (2, 2)))
+    for streams, slices, chunk, regroup in configs:
+        monkeypatch.setenv("XY_PHASE_STREAMS", str(streams))
+        monkeypatch.setenv("XY_PHASE_SLICES", str(slices))
         b = xy.Batch(graphs, T, precision="fix16", seeds=np.arange(G) + 60, max_records=8, stream=torch.cuda.Stream())
         assert list(b.forms()) == [1] * 5 + [0] * (G - 5)
-        assert b.phase_streams() == int(streams[0])
+        assert b.phase_streams() == streams
+        assert b.phase_slices() == (1 if mixed else slices)      # slices only for independent groups
         if chunk:
             b.use_graph(chunk)
-        if ">" in streams:                       # regrouped half way (xy_batch_set_phase_streams)
+        if regroup:                               # regrouped half way (xy_batch_set_phase_groups)
             b.sweep(6, pt_every=1, meas_every=4)
-            b.set_phase_streams(int(streams[2]))
-            assert b.phase_streams() == int(streams[2])
+            b.set_phase_streams(*regroup)
+            assert b.phase_streams() == regroup[0] and b.phase_slices() == (1 if mixed else regroup[1])
             b.sweep(6, pt_every=1, meas_every=4)
         else:
             b.sweep(12, pt_every=1, meas_every=4)
