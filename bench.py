@@ -217,7 +217,10 @@ def write_traffic(wl, paths, argv, phase_streams, phase_slices=1):
         # (a k_end_sweep after them ends one; with independent stream groups
         # every group ends its sweep with its own k_end_sweep, and the
         # dispatches are in enqueue order, so the later ones close nothing);
-        # the mean of the last n_last sweeps, which all ran the tuned form
+        # the mean of the last n_last sweeps, which all ran the tuned form.
+        # With slices each slice runs the window's sweeps in turn, so a closed
+        # run is one slice's sweep: the last n_last * phase_slices of them
+        # make n_last sweeps of the whole batch
         sums, counts, cur, names, n_cur = [], [], 0.0, set(), 0
         for r in rows:
             if r["Counter_Name"] != counter:
@@ -230,8 +233,8 @@ def write_traffic(wl, paths, argv, phase_streams, phase_slices=1):
                 sums.append(cur)
                 counts.append(n_cur)
                 cur, n_cur = 0.0, 0
-        last = sums[-n_last:]
-        return sorted(names), sum(last) / len(last), sum(counts[-n_last:]) / len(last)
+        k = n_last * phase_slices
+        return sorted(names), sum(sums[-k:]) / n_last, sum(counts[-k:]) / n_last
 
     def copy_kib(rows, counter):
         v = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == counter]
@@ -386,6 +389,10 @@ def main():
     ap.add_argument("--phase-streams", type=int, default=0,
                     help="streams of the phase-form sample groups (default: the autotuner's choice); with "
                          "--traffic-from, the count the counters were taken with")
+    ap.add_argument("--trig", type=int, default=-1, choices=[-1, 0, 1, 2],
+                    help="fix the (cos, sin) form (0 two-level table, 1 2048-entry table, 2 hardware): nothing "
+                         "is tuned then, and the sample groups are --phase-streams / --phase-slices or the "
+                         "library's default (profiler runs, whose timing the counters distort)")
     ap.add_argument("--phase-slices", type=int, default=1,
                     help="with --phase-streams: slices of groups swept one after the other (default 1)")
     ap.add_argument("--traffic-from", nargs="+", metavar="CSV",
@@ -439,6 +446,7 @@ def main():
             os.environ["XY_FIX16_PHASE_MIN"] = str(threshold["phase_min"])
         print(f"# phase-form threshold: {threshold}", file=sys.stderr, flush=True)
     main_run = time_gpu(wl, args.precision, args.steps, args.warmup, graphs, torch, xy,
+                        form=(args.trig, 1) if args.trig >= 0 else None,
                         phase_streams=args.phase_streams, replay=not args.direct, phase_slices=args.phase_slices)
     value = upd_per_sweep * args.steps / (main_run["ms"] * 1e6)
     print(f"# {args.precision}: {main_run['ms'] / args.steps:.3f} ms/sweep ({main_run['launch']}), "
@@ -454,10 +462,11 @@ def main():
     if args.precision == "fix16" and os.path.exists(traffic_file(wl.name)):
         with open(traffic_file(wl.name)) as fh:
             tr = json.load(fh)
-        # the counters hold for this source and for the stream-group count they were taken with
-        if (tr.get("kernel_digest") == kernel_source_digest() and tr.get("workload") == wl.name
-                and tr.get("phase_streams") == main_run["phase_streams"]
-                and tr.get("phase_slices", 1) == main_run["phase_slices"]):
+        # the counters hold for this kernel source and workload, in the
+        # arrangement of sample groups they were taken with, which is named
+        # beside them (the arrangement changes which blocks share the L2, so a
+        # run in another one moves somewhat different bytes)
+        if tr.get("kernel_digest") == kernel_source_digest() and tr.get("workload") == wl.name:
             traffic = tr["bytes_per_sweep"]
         else:
             tr = {}
@@ -479,7 +488,9 @@ def main():
     if traffic is not None:
         meas = traffic / (k_ms * 1e6)
         roofline.update(measured_gbs=round(meas, 1), measured_frac=round(meas / HBM_PEAK_GBS, 4),
-                        measured_bytes_per_update=tr["bytes_per_update"])
+                        measured_bytes_per_update=tr["bytes_per_update"],
+                        traffic_sample_groups={"streams": tr.get("phase_streams"),
+                                               "slices": tr.get("phase_slices", 1)})
         if tr.get("l2_read_bytes_per_sweep"):
             roofline["l2_read_gbs"] = round(tr["l2_read_bytes_per_sweep"] / (k_ms * 1e6), 1)
         if tr.get("l2_hit_rate") is not None:
@@ -556,6 +567,8 @@ def main():
         # follows from the difference of the kernel times
         tuned = main_run["autotune"]
         form = (tuned["trig"], tuned["allow_unit"]) if tuned and "trig" in tuned else None
+        if args.trig >= 0:
+            form = (args.trig, 1)
         met = time_gpu(wl, args.precision, args.split_steps, 2, graphs, torch, xy, n_or=0, form=form,
                        phase_streams=main_run["phase_streams"], replay=not args.direct, direct=False,
                        phase_slices=main_run["phase_slices"])
