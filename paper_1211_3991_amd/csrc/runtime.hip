@@ -199,11 +199,18 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
         const xy_graph &gr = *g[s];
         SampleDesc &d = p.desc[s];
         d.n = gr.n; d.Q = gr.Q; d.L = gr.L; d.max_deg = gr.max_deg;
+        const bool phase = fix16 && R % 4 == 0 && (phase_mode == 1 || (phase_mode < 0 && gr.n >= phase_min));
         if (!fix16) {
             d.row_ptr = (int64_t)n_i32; n_i32 += gr.n + 1;
             d.col = (int64_t)n_i32;     n_i32 += 2 * (size_t)gr.m;
         } else {
-            p.sell[s] = build_sell(gr, sell_window(gr.n));
+            // phase-form samples take their own degree-sort window
+            // (XY_SELL_WINDOW overrides it): their gathers come from global memory
+            int window = phase ? kPhaseSellWindow : sell_window(gr.n);
+            if (phase)
+                if (const char *env = std::getenv("XY_SELL_WINDOW"))
+                    if (*env && std::atoi(env) > 0) window = std::atoi(env);
+            p.sell[s] = build_sell(gr, window);
             const Sell &S = p.sell[s];
             d.sell_ptr = (int64_t)n_i32; n_i32 += S.chunk_ptr.size();
             d.sell_w = (int64_t)n_i32;   n_i32 += S.chunk_w.size();
@@ -217,7 +224,7 @@ xy_status plan_batch(const xy_graph *const *g, int G, int R, int precision, int 
         d.coord = (int64_t)n_u32;   n_u32 += align_up(gr.n, 4);
         d.trig = (int64_t)n_f64;    n_f64 += gr.L;
         for (int c = 0; c <= kMaxColours; ++c) d.colour_off[c] = gr.colour_off[std::min(c, gr.Q)];
-        d.layout = (fix16 && R % 4 == 0 && (phase_mode == 1 || (phase_mode < 0 && gr.n >= phase_min))) ? 1 : 0;
+        d.layout = phase ? 1 : 0;
         n_phase += d.layout;
         if (d.layout) {
             const int spb = fix16_phase_sites_per_block(R);

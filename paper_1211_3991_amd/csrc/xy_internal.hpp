@@ -152,10 +152,17 @@ struct Sell {
 // window: sites per degree-sorted window (the whole class when >= n).
 Sell build_sell(const xy_graph &g, int window);
 
-// Window for a graph of n sites: whole classes when a replica fits in LDS
-// (n <= 65536 on gfx950; neighbour locality is irrelevant there and uniform
-// chunks matter), 4096-site windows otherwise (gathers from global memory).
+// Window for a graph of n sites in a workgroup-per-replica form: whole
+// classes when a replica fits in LDS (n <= 65536 on gfx950; neighbour
+// locality is irrelevant there and uniform chunks matter), 4096-site windows
+// otherwise (gathers from global memory).
 inline int sell_window(int n) { return n <= 65536 ? n : 4096; }
+// Window of the phase form, whose gathers always come from global memory: a
+// window of a class covers a compact band of the lattice, so the blocks that
+// run together gather from a small part of the state (measured on 64 x L=256:
+// whole classes 317, 4096 sites 323.5, 8192 323, 16384 318.5 updates/ns; on
+// 32 x L=512: 2048 297, 4096 299, 8192 299, 16384 287).
+constexpr int kPhaseSellWindow = 4096;
 
 // One fix16 work item: a (sample, slot) pair run by one workgroup.
 struct Item { int32_t sample, slot; };
