@@ -159,6 +159,34 @@ __device__ __forceinline__ bool accept_move(float dE, float factor, uint32_t wor
     return (double)x.x < (double)q * 4294967296.0;
 }
 
+// Over-relaxation: true when the Metropolis test of the reflection accepts
+// for certain, so that its energy change need not be evaluated.  The
+// reflection theta' = 2 phi~ - theta about the computed axis changes the
+// energy by dE = h . (s(theta) - s(theta')), s(x) = (cos x, sin x); with the
+// axis 2 phi~ = 2 atan2(h_y, h_x) + delta it equals |h| (cos x - cos(x - delta))
+// for x = theta - atan2(h_y, h_x), so |dE| <= |h| |delta| exactly, where
+// |delta| <= 2 x 1.3e-5 (the atan polynomial) + 2pi / 2^17 (the rounding of
+// 2 phi~ to the grid; the ratio's reciprocal and the scale add under 1e-6
+// grid units) < 7.44e-5 rad.  The FP32 (cos, sin) of the 2^16 grid angles are
+// within kTrigErr of the exact values (the largest error over all of them,
+// measured on the GPU, is 1.2e-7), and the FP32 evaluation of dE adds under
+// 4e-7 (|h_x| + |h_y|), so |dE| <= kDeltaE (|h_x| + |h_y|).  accept_move
+// accepts when p 2^16 - u >= 1 for p = 2^(dE factor) (factor = -beta log2 e):
+// with 2^(-y) >= 1 - y ln 2 and the hardware 2^x within kExp2Err (relative)
+// for the arguments where this matters (|y| < 1.5; measured on [-2, 0.5]),
+// u + 2^16 ln 2 kDeltaE |factor| (|h_x| + |h_y|) + 2^16 kExp2Err <= 65535
+// suffices.  The test below uses a coefficient and a bound with margin over
+// these; a move it does not clear takes the full test.
+constexpr float kTrigErr = 2e-7f;
+constexpr float kExp2Err = 2e-7f;
+constexpr float kDeltaE = 7.44e-5f + 2.0f * kTrigErr + 4e-7f;
+constexpr float kOrSureCoef = 4.0f;                            // > 2^16 ln 2 kDeltaE = 3.42
+
+__device__ __forceinline__ bool or_accepts_surely(float hx, float hy, float factor, uint32_t word)
+{
+    return fmaf(-kOrSureCoef * factor, fabsf(hx) + fabsf(hy), (float)(word >> 16)) <= 65534.0f;
+}
+
 // Philox4x32-10 as philox4x32_10, for keys that are the same in every lane
 // of the wave (scalar registers): each round's two three-input XORs are one
 // v_bitop3_b32 each (truth table 0x96, a ^ b ^ c) instead of two v_xor_b32.

@@ -203,10 +203,19 @@ __device__ __forceinline__ void update_unit(const DevBatch &b, const PhaseLanes 
         const uint32_t th = cur_th[r];
         const uint32_t th_new = kMetro ? words[r] : field_axis2(hx[r], hy[r]) - th;
         const uint32_t w = r < 2 ? me.x : me.y;
-        const float2 cur = (r & 1) ? Trig<kTrig>::unit_hi(w, tab) : Trig<kTrig>::unit_lo(w, tab);
-        const float2 nu = Trig<kTrig>::unit_lo(th_new, tab);
-        const float dE = hx[r] * (cur.x - nu.x) + hy[r] * (cur.y - nu.y);
-        const bool acc = accept_move(dE, factor[r], words[r], (uint32_t)i, sweep, (uint32_t)slot, (uint32_t)sub, d);
+        // an over-relaxation move that is surely accepted skips the energy
+        // change (its result is the same); the branch is per lane, and a wave
+        // whose lanes all skip jumps over the evaluation
+        const bool full = kMetro || !or_accepts_surely(hx[r], hy[r], factor[r], words[r]);
+        float2 nu = kLast ? Trig<kTrig>::unit_lo(th_new, tab) : make_float2(0.f, 0.f);   // the energy needs it
+        float2 cur = nu;
+        bool acc = true;
+        if (full) {
+            cur = (r & 1) ? Trig<kTrig>::unit_hi(w, tab) : Trig<kTrig>::unit_lo(w, tab);
+            if (!kLast) nu = Trig<kTrig>::unit_lo(th_new, tab);
+            const float dE = hx[r] * (cur.x - nu.x) + hy[r] * (cur.y - nu.y);
+            acc = accept_move(dE, factor[r], words[r], (uint32_t)i, sweep, (uint32_t)slot, (uint32_t)sub, d);
+        }
         out[r] = acc ? th_new : th;
         const float2 f = acc ? nu : cur;
         e_q[r] = p.active ? -(f.x * lx[r] + f.y * ly[r]) : 0.f;

@@ -89,3 +89,26 @@ def test_axis_octants_and_degenerate_fields():
     d = (got - exact) & 0xFFFF
     assert np.minimum(d, 65536 - d).max() <= 1, (got, exact)
     assert got[-1] == 0 and got[-2] == 0
+
+
+def _const(name):
+    body = open(SRC).read()
+    return float(re.search(r"constexpr float %s = ([-0-9.e]+)f;" % name, body).group(1))
+
+
+def test_axis_error_bound_used_by_the_sure_accept_test():
+    """The doubled axis differs from twice the field's angle by under
+    7.44e-5 rad (the polynomial's error twice over plus half a grid step), the
+    bound the over-relaxation's sure-accept test takes for |dE| / |h|; and the
+    test's constants clear the inequality it rests on."""
+    rng = np.random.default_rng(11)
+    hx = (rng.standard_normal(400000) * 3).astype(np.float32)
+    hy = (rng.standard_normal(400000) * 3).astype(np.float32)
+    got = _axis2(hx, hy) * (2 * np.pi / 65536)
+    exact = 2 * np.arctan2(hy.astype(np.float64), hx.astype(np.float64))
+    d = np.angle(np.exp(1j * (got - exact)))
+    assert np.abs(d).max() < 7.44e-5, np.abs(d).max()
+    trig, exp2 = _const("kTrigErr"), _const("kExp2Err")
+    delta_e = 7.44e-5 + 2 * trig + 4e-7
+    assert _const("kOrSureCoef") > 65536 * np.log(2) * delta_e * 1.1
+    assert 65534 + 65536 * exp2 + 0.01 < 65535
