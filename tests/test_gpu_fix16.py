@@ -334,6 +334,9 @@ def test_autotune_phase_streams_restores_state(tmp_path, monkeypatch):
     for bad in (0, 5):
         with pytest.raises(xy.XYError):
             b.set_phase_streams(bad)
+    for bad in ((2, 0), (2, 5), (3, 3)):                 # slices: at least one, at most 8 groups
+        with pytest.raises(xy.XYError):
+            b.set_phase_streams(*bad)
     assert b.phase_streams() == rep["phase_streams"]
 
 
