@@ -112,3 +112,35 @@ def test_axis_error_bound_used_by_the_sure_accept_test():
     delta_e = 7.44e-5 + 2 * trig + 4e-7
     assert _const("kOrSureCoef") > 65536 * np.log(2) * delta_e * 1.1
     assert 65534 + 65536 * exp2 + 0.01 < 65535
+
+
+def test_sure_accept_bound_against_worst_case_full_test():
+    """Random fields, angles, temperatures and uniforms, with fields up to
+    |h_x| + |h_y| = 60 and beta up to 10, near the bound: whenever the
+    sure-accept test passes, the full acceptance test accepts even with every
+    error at its worst (the (cos, sin) values off by kTrigErr against the
+    move, 2^x low by kExp2Err, and the FP32 rounding of dE against it)."""
+    rng = np.random.default_rng(3)
+    n = 1_000_000
+    scale = rng.uniform(0.0, 20.0, n).astype(np.float32)
+    hx = (rng.standard_normal(n) * scale).astype(np.float32)
+    hy = (rng.standard_normal(n) * scale).astype(np.float32)
+    th = rng.integers(0, 65536, n)
+    beta = rng.uniform(0.05, 10.0, n)
+    factor = (-beta.astype(np.float32) * np.float32(1.4426950408889634)).astype(np.float32)
+    h1 = (np.abs(hx) + np.abs(hy)).astype(np.float32)
+    coef = np.float32(-_const("kOrSureCoef")) * factor
+    # uniforms at and just below the sure-accept threshold, where it is tightest
+    u = np.clip(np.floor(65534.0 - coef.astype(np.float64) * h1 - rng.uniform(0, 3, n)), 0, 65535)
+    sure = (coef.astype(np.float64) * h1 + u) <= 65534.0
+    new = (_axis2(hx, hy) - th) & 0xFFFF
+    a0, a1 = th * (2 * np.pi / 65536), new * (2 * np.pi / 65536)
+    de = hx.astype(np.float64) * (np.cos(a0) - np.cos(a1)) + hy.astype(np.float64) * (np.sin(a0) - np.sin(a1))
+    worst = de + h1 * (2 * _const("kTrigErr") + 4e-7)                  # every error against the move
+    p = np.exp2(-np.maximum(worst, 0.0) * beta * 1.4426950408889634) * (1 - _const("kExp2Err"))
+    q = p * 65536 - u
+    assert sure.mean() > 0.5
+    assert np.all(q[sure] >= 1.0), (q[sure].min(), np.argmin(q[sure]))
+    # and the bound is of the right size: |dE| / |h| comes within a factor 2.5 of 7.44e-5 on these fields
+    hn = np.sqrt(hx.astype(np.float64) ** 2 + hy.astype(np.float64) ** 2)
+    assert (np.abs(de) / np.maximum(hn, 1e-30)).max() > 0.4 * 7.44e-5
