@@ -143,7 +143,10 @@ xy_status xy_batch_sizes(const xy_graph *const *g, int n_graphs, int n_T, int pr
  * workgroup per replica with the replica in LDS when it fits (else in global
  * memory).  The environment variables XY_FIX16_PHASE_MIN (the site threshold)
  * and XY_FIX16_PHASE (1: every sample, 0: none) override the rule; they are
- * read here and by xy_batch_sizes, which must see the same values. */
+ * read here and by xy_batch_sizes, which must see the same values.  The
+ * phase form sorts each colour class by degree inside windows of 4096 sites
+ * (XY_SELL_WINDOW overrides the window); the other forms inside whole classes
+ * for graphs of up to 65536 sites and inside windows of 4096 sites above. */
 xy_status xy_batch_init(xy_batch **out, const xy_graph *const *g, int n_graphs, int n_T,
                         const double *T, int precision, const uint64_t *seeds, int max_records,
                         void *d_state, void *d_graph, void *d_work, void *d_obs, void *stream);
@@ -258,7 +261,8 @@ xy_status xy_batch_phase_streams(const xy_batch *b, int *n_streams);
  * with workgroup-form samples keep one slice.  Synchronises like
  * xy_batch_set_phase_streams.  XY_EINVAL unless 1 <= n_streams <= 4,
  * n_slices >= 1 and n_streams * n_slices <= 8; the slice count is lowered
- * where the phase samples are fewer than the groups.
+ * where the phase samples are fewer than the groups.  Initial value one
+ * slice (XY_PHASE_SLICES overrides it at xy_batch_init).
  * xy_batch_phase_groups returns the configuration in effect. */
 xy_status xy_batch_set_phase_groups(xy_batch *b, int n_streams, int n_slices, void *stream);
 xy_status xy_batch_phase_groups(const xy_batch *b, int *n_streams, int *n_slices);
