@@ -111,6 +111,7 @@ __device__ __forceinline__ void observe(const DevBatch &b, const SampleDesc &d, 
 enum Mode { kAngLds = 0, kAngGlobal = 1, kUnitLds = 2 };
 
 template <int kMode, int kTrig> struct Spins {
+    static constexpr bool kStoresUnit = false;   // set() keeps the angle only
     uint16_t *ang;
     const float2 *tab;
     __device__ __forceinline__ float2 nbr(int j) const { return Trig<kTrig>::unit(ang[j], tab); }
@@ -121,6 +122,7 @@ template <int kMode, int kTrig> struct Spins {
 };
 
 template <int kTrig> struct Spins<kUnitLds, kTrig> {
+    static constexpr bool kStoresUnit = true;    // set() also stores the unit vector
     uint16_t *ang;          // global memory
     float2 *uv;             // LDS
     const float2 *tab;
@@ -210,17 +212,26 @@ __device__ __forceinline__ double colour_phase(const SampleDesc &d, const Sp &sp
         for (int r = 0; r < kGroup; ++r) {
             if (site[r] >= c1 || g0 + r >= nch) continue;
             const uint32_t th = sp.angle(site[r]);
-            const float2 cur = sp.own(site[r], th);
             uint32_t th_new;
             if (sub == 0) {
                 th_new = words[r] & 0xFFFFu;                          // uniform proposal
             } else {
                 th_new = (field_axis2(hx[r], hy[r]) - th) & 0xFFFFu;   // reflection
             }
-            const float2 nu = sp.unit(th_new);
-            const float dE = hx[r] * (cur.x - nu.x) + hy[r] * (cur.y - nu.y);
-            const bool accept = accept_move(dE, factor, words[r], (uint32_t)site[r], sweep, (uint32_t)slot,
-                                            (uint32_t)sub, d);
+            // a surely accepted reflection skips its energy change (the same
+            // decision, see or_accepts_surely); the proposal's unit vector is
+            // still needed where it is stored or enters the energy
+            constexpr bool kNeedNu = Sp::kStoresUnit || kLast;
+            const bool full = sub == 0 || !or_accepts_surely(hx[r], hy[r], factor, words[r]);
+            float2 nu = kNeedNu ? sp.unit(th_new) : make_float2(0.f, 0.f);
+            float2 cur = nu;
+            bool accept = true;
+            if (full) {
+                cur = sp.own(site[r], th);
+                if (!kNeedNu) nu = sp.unit(th_new);
+                const float dE = hx[r] * (cur.x - nu.x) + hy[r] * (cur.y - nu.y);
+                accept = accept_move(dE, factor, words[r], (uint32_t)site[r], sweep, (uint32_t)slot, (uint32_t)sub, d);
+            }
             if (accept) sp.set(site[r], th_new, nu);
             if (kLast) {
                 const float2 f = accept ? nu : cur;
