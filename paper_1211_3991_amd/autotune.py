@@ -184,7 +184,8 @@ def tune_phase_threshold(graphs, T, seeds=None, sweeps=4, n_or=5, use_cache=True
     major state, a launch per colour phase) instead of a workgroup per
     replica, for this batch: builds a trial batch per candidate threshold
     (threshold_candidates), tunes it and times `sweeps` sweeps with the
-    kernel-event timer, and returns the fastest threshold with the timings.
+    kernel-event timer (direct launches; see below), and returns the
+    fastest threshold with the timings.
     The form is fixed when a batch is created, so the caller creates its
     batch with the result (environment variable XY_FIX16_PHASE_MIN, which
     xy_batch_sizes and xy_batch_init read).  Cached like autotune()."""
@@ -213,7 +214,12 @@ def tune_phase_threshold(graphs, T, seeds=None, sweeps=4, n_or=5, use_cache=True
             os.environ["XY_FIX16_PHASE_MIN"] = str(thr)
             b = Batch(graphs, T, precision="fix16", seeds=seeds, device=device, stream=torch.cuda.Stream())
             try:
-                autotune(b, sweeps=2, n_or=n_or, use_cache=False)
+                # (trial batches are tuned by direct launches only: a
+                # replayed trial of a batch of small graphs captures up to
+                # 128 sweeps of very short launches, tens of thousands of
+                # graph nodes, and one such trial ended the process with an
+                # abort whose cause is not known)
+                autotune(b, sweeps=2, n_or=n_or, use_cache=False, replay=False)
                 saved = b.get_state()
                 times[thr] = min(_time(b, sweeps, n_or, saved) for _ in range(2))
             finally:
