@@ -145,7 +145,10 @@ def autotune(batch, sweeps=3, n_or=5, use_cache=True, pt_every=1, replay=True):
         for c in cands:
             batch.set_phase_streams(*c)
             d = min(_time(batch, n_sw_groups, n_or, saved, pt_every) for _ in range(2))
-            r = min(_time_replay(batch, n_rep, n_or, saved, pt_every) for _ in range(2)) if replay else float("inf")
+            # (and at most 256 group sweeps, about ten thousand launches: the
+            # one abort of unknown cause came in a larger trial graph)
+            n_c = max(2, min(n_rep, 256 // (c[0] * c[1])))
+            r = min(_time_replay(batch, n_c, n_or, saved, pt_every) for _ in range(2)) if replay else float("inf")
             st[c], mode[c] = (r, "replay") if r < d else (d, "direct")
         fastest = min(st.values())
         best = next(c for c in cands if st[c] <= 1.005 * fastest)
