@@ -44,7 +44,7 @@ typedef int xy_status;
 #define XY_ENOMEM    -2   /* host allocation failed */
 #define XY_EHIP      -3   /* HIP runtime error */
 #define XY_ESTATE    -4   /* call not valid in the handle's current state */
-#define XY_EUNSUP    -5   /* valid request this build does not support */
+#define XY_EUNSUP    -5   /* valid request the library does not support */
 #define XY_ECONVERGE -6   /* graph sampler hit its attempt cap */
 
 /* Spin representation. */
