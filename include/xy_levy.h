@@ -214,7 +214,9 @@ xy_status xy_decision_log(xy_batch *b, uint8_t *d_log, int max_sweeps);
 /* HIP-graph replay: xy_sweep captures `chunk` sweeps of its shape (n_or,
  * pt_every, meas_every, stream) into a HIP graph on first use and replays it
  * for every whole chunk of later calls of the same shape (chunk = 0 turns it
- * off; a non-null stream is then required).  The captured tempering and
+ * off; with chunk > 0, xy_sweep needs a non-null stream).  The graph holds
+ * the launches of chunk sweeps of every sample group: (n_or + 1) per colour
+ * and a few more per group and sweep.  The captured tempering and
  * record flags repeat with P = lcm(pt_every, meas_every) (0 counting as 1):
  * a replay starts only at a sweep index congruent modulo P to the one it was
  * captured at, and direct launches reach that index first (chunk a multiple
