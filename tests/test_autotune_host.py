@@ -1,9 +1,12 @@
-"""Host logic of the phase-form threshold tuner (no GPU): the candidate
-thresholds, one trial batch per candidate created under that threshold, the
-environment restored afterwards (also when a trial fails), the fastest
-candidate chosen and cached, and no candidates when the temperature count
-rules the phase form out.  The device parts (trial batches, their timing and
-tuning) are stand-ins here; the GPU runs them in `bench.py --workload uneven`."""
+"""Host logic of the tuners (no GPU), with stand-ins for the device parts.
+Phase-form threshold: the candidate thresholds, one trial batch per
+candidate created under that threshold, the environment restored afterwards
+(also when a trial fails), the fastest candidate chosen and cached, and no
+candidates when the temperature count rules the phase form out (the GPU runs
+it in `bench.py --workload uneven`).  Stream-group trials of autotune(): the
+candidate arrangements, each scored by the faster of its two launch modes,
+the fewer groups on a tie within 0.5%, replayed trials of at most 256 group
+sweeps, direct launches only on the null stream, and the cached choice."""
 import json
 import os
 import types
@@ -96,3 +99,102 @@ def test_env_restored_when_a_trial_fails(fake_device, monkeypatch):
 def test_no_phase_form_for_ladders_not_a_multiple_of_four(fake_device):
     rep = autotune.tune_phase_threshold([_G(16384)] * 2, np.arange(1.0, 4.0))
     assert rep["phase_min"] is None and not fake_device.log
+
+
+class _TuneBatch:
+    """Stand-in for a fixed-point batch whose every sample is in the phase
+    form: records the arrangement and (cos, sin) form the tuner sets."""
+    precision = "fix16"
+    device = "cuda:0"
+    R = 8
+
+    def __init__(self, n_samples):
+        self.graphs = [_G(16384)] * n_samples
+        self.arr = (1, 1)
+        self.trig = None
+        self.calls = []
+
+    def forms(self):
+        return np.ones(len(self.graphs), dtype=np.int32)
+
+    def get_state(self):
+        return ("state",)
+
+    def set_fix16_form(self, trig, allow_unit):
+        self.trig = trig
+
+    def set_phase_streams(self, n, slices=1):
+        self.arr = (n, slices)
+        self.calls.append(self.arr)
+
+    def phase_streams(self):
+        return self.arr[0]
+
+    def phase_slices(self):
+        return self.arr[1]
+
+    def _s(self):
+        return types.SimpleNamespace(value=1234)
+
+
+@pytest.fixture
+def fake_tuning(monkeypatch, tmp_path):
+    import torch
+    monkeypatch.setenv("XY_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    monkeypatch.setattr(torch.cuda, "get_device_properties",
+                        lambda dev: types.SimpleNamespace(gcnArchName="gfx950:sramecc+:xnack-"))
+    t = types.SimpleNamespace(direct={}, replay={}, trig={2: 1.0, 1: 1.3, 0: 1.2}, replay_sweeps=[])
+
+    def fake_time(batch, sweeps, n_or, saved, pt_every=0):
+        if batch.calls:
+            return t.direct[batch.arr]
+        return t.trig.get(batch.trig, 1.0)     # the probe and the (cos, sin) trials come first
+
+    def fake_replay(batch, sweeps, n_or, saved, pt_every=0):
+        t.replay_sweeps.append((batch.arr, sweeps))
+        return t.replay[batch.arr]
+    monkeypatch.setattr(autotune, "_time", fake_time)
+    monkeypatch.setattr(autotune, "_time_replay", fake_replay)
+    return t
+
+
+def test_group_trials_pick_fastest_mode_and_cap_replays(fake_tuning):
+    b = _TuneBatch(10)
+    arrs = [(1, 1), (2, 1), (3, 1), (2, 2), (3, 2), (2, 4)]
+    fake_tuning.direct.update(dict(zip(arrs, [1.00, 0.95, 0.96, 0.99, 0.97, 1.10])))
+    fake_tuning.replay.update(dict(zip(arrs, [0.99, 0.96, 0.90, 0.98, 0.904, 1.20])))
+    rep = autotune.autotune(b, sweeps=3)
+    assert rep["trig"] == 2 and b.trig == 2
+    assert set(rep["phase_streams_ms_per_sweep"]) == {"1", "2", "3", "2x2", "3x2", "2x4"}
+    assert rep["phase_streams_ms_per_sweep"]["3"] == 0.9 and rep["phase_streams_launch"]["3"] == "replay"
+    assert rep["phase_streams_launch"]["2"] == "direct" and rep["phase_streams_launch"]["2x4"] == "direct"
+    # 3 streams wins; 3x2 (0.904) is within 0.5% but has more groups and comes later
+    assert (rep["phase_streams"], rep["phase_slices"]) == (3, 1) and b.arr == (3, 1)
+    # every replayed trial holds at most 256 group sweeps (and at least 2 sweeps)
+    for (n, k), sweeps in fake_tuning.replay_sweeps:
+        assert 2 <= sweeps <= max(2, 256 // (n * k))
+    assert dict(fake_tuning.replay_sweeps)[(2, 4)] == 32
+    # the cached choice is applied to a fresh batch without trials
+    b2 = _TuneBatch(10)
+    n_trials = len(fake_tuning.replay_sweeps)
+    again = autotune.autotune(b2)
+    assert again["cached"] and b2.arr == (3, 1) and b2.trig == 2 and len(fake_tuning.replay_sweeps) == n_trials
+
+
+def test_group_trials_tie_goes_to_fewer_groups(fake_tuning):
+    b = _TuneBatch(4)
+    arrs = [(1, 1), (2, 1), (3, 1), (2, 2)]
+    fake_tuning.direct.update(dict(zip(arrs, [1.004, 1.0, 1.02, 1.03])))
+    fake_tuning.replay.update(dict(zip(arrs, [1.05, 1.05, 1.05, 1.05])))
+    rep = autotune.autotune(b, sweeps=2, use_cache=False)
+    assert set(rep["phase_streams_ms_per_sweep"]) == {"1", "2", "3", "2x2"}     # (2, 4) needs 8 samples
+    assert (rep["phase_streams"], rep["phase_slices"]) == (1, 1)
+
+
+def test_group_trials_direct_only_on_the_null_stream(fake_tuning):
+    b = _TuneBatch(4)
+    b._s = lambda: types.SimpleNamespace(value=None)
+    fake_tuning.direct.update({(1, 1): 1.0, (2, 1): 0.9, (3, 1): 0.95, (2, 2): 0.97})
+    rep = autotune.autotune(b, sweeps=2, use_cache=False)
+    assert not fake_tuning.replay_sweeps and set(rep["phase_streams_launch"].values()) == {"direct"}
+    assert rep["phase_streams"] == 2
